@@ -1,0 +1,196 @@
+/*
+ * bri.h - C ABI of the MI355X (gfx950) Brillouin Dirac operator library.
+ *
+ * The operator is the "Brillouin operator" of Durr & Koutsou,
+ * arXiv:1012.3615, Eq. def_pref with c_SW = 0 and lattice spacing a = 1:
+ *
+ *   D = sum_mu gamma_mu nabla^iso_mu - (1/2) Lap^bri + m,
+ *
+ * both stencils living on the 81 points x + n, n in {-1,0,1}^4 (App. C),
+ * made gauge covariant by the transporter W(x, x+n) = average of the link
+ * products over all k! shortest lattice paths from x to x+n (Sec. 5.1,
+ * averaged, not back-projected).  Per site
+ *
+ *   (D psi)(x) = (lambda_0 + m) psi(x)
+ *              + sum_{n != 0} [lambda_k + rho_k sum_mu n_mu gamma_mu] W(x,x+n) psi(x+n)
+ *
+ * with k = |n|_1, lambda_k = -2^(4-k)/128 (k >= 1), lambda_0 = 240/128 and
+ * rho_k = 4^(4-k)/432 (Tab. rholambda).  Boundary conditions are periodic.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Extents: dims.L[0..3] = (Lx, Ly, Lz, Lt), each >= 2.  The linear site
+ *   index is  site = x + Lx*(y + Ly*(z + Lz*t)).
+ * - Directions mu = 0..3 are x, y, z, t.  U_mu(x) transports from x+mu to x,
+ *   i.e. it multiplies psi(x+mu) (the Wilson-operator orientation, Sec. 1).
+ * - Gamma matrices: Hermitian chiral basis
+ *     gamma_{x,y,z} = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0,1],[1,0]],
+ *     gamma_5 = gamma_x gamma_y gamma_z gamma_t = diag(1,1,-1,-1).
+ * - Canonical (user) layouts, complex128 = two doubles (re, im):
+ *     links   U[mu][site][a][b]            (4 * V * 9 complex)
+ *     spinors psi[rhs][site][spin][colour] (nrhs * V * 12 complex)
+ * - Internal structure-of-arrays (SoA) layouts, one complex scalar per
+ *   element, site index fastest ("planes" of V complex numbers):
+ *     links        [mu][9][V]          element e = 3*a + b
+ *     spinors      [rhs][12][V]        component = 3*spin + colour
+ *     transporters [n_offsets][9][V]
+ *   The complex scalar is double2 (BRI_F64), float2 (BRI_F32) or two IEEE
+ *   binary16 halves (BRI_F16).  Casts to narrower types round to nearest even.
+ * - Offsets n are numbered i = (nx+1) + 3(ny+1) + 9(nz+1) + 27(nt+1) in 0..80;
+ *   i = 40 is n = 0.  With n_offsets = 80, plane j holds offset i = j (j < 40)
+ *   or i = j+1 (j >= 40).  With n_offsets = 40, plane c holds the offset
+ *   i = 41 + c (the offsets whose last non-zero component is +1) and the other
+ *   40 are recovered from W(x, x-n) = W(x-n, x)^dag.
+ * - All pointers are DEVICE pointers owned by the caller, unless a comment
+ *   says "host".  The library never allocates or frees device memory; scratch
+ *   is passed in as a workspace whose size the *_workspace_bytes query gives.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   calls are asynchronous on it, except bri_solve_cgne, which synchronises
+ *   the stream to read convergence data and returns after completion.
+ * - Errors: every call returns a bri_status; nothing throws or aborts across
+ *   the ABI.  BRI_E_ARG for null / misaligned (16-byte) pointers, bad sizes,
+ *   unsupported enum values and in == out aliasing; BRI_E_HIP for HIP runtime
+ *   failures; bri_last_error() then returns a message (thread-local, valid
+ *   until the next bri_* call on the same thread).
+ */
+#ifndef BRI_H
+#define BRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { int32_t L[4]; } bri_dims;
+
+typedef enum { BRI_F64 = 0, BRI_F32 = 1, BRI_F16 = 2 } bri_prec;
+typedef enum { BRI_STORED = 0, BRI_RECOMPUTE = 1 } bri_variant;
+typedef enum {
+    BRI_OK = 0,
+    BRI_E_ARG = -1,
+    BRI_E_UNSUPPORTED = -2,
+    BRI_E_HIP = -3,
+    BRI_E_NOCONV = -4,
+    BRI_E_WORKSPACE = -5
+} bri_status;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *bri_last_error(void);
+/* ABI revision of this header (incremented on incompatible change). */
+int32_t bri_abi_version(void);
+
+/* ---- sizes (bytes) of the SoA buffers ----------------------------------- */
+size_t bri_spinor_bytes(bri_dims d, bri_prec p, int32_t nrhs);
+size_t bri_links_bytes(bri_dims d, bri_prec p);
+size_t bri_transporter_bytes(bri_dims d, bri_prec p, int32_t n_offsets);
+
+/* ---- layout conversion (canonical complex128 <-> SoA) --------------------
+ * Links are the input of the transporter construction (Sec. 5.1; the gauge
+ * field U_mu(x) of Eq. def_pref).  p selects the SoA precision; U_soa must
+ * hold bri_links_bytes(d, p).  psi_canon/psi_soa hold nrhs fields. */
+bri_status bri_pack_links(bri_dims d, const double *U_canon, void *U_soa, bri_prec p, void *stream);
+bri_status bri_pack_spinor(bri_dims d, int32_t nrhs, const double *psi_canon, void *psi_soa,
+                           bri_prec p, void *stream);
+bri_status bri_unpack_spinor(bri_dims d, int32_t nrhs, const void *psi_soa, bri_prec p,
+                             double *psi_canon, void *stream);
+
+/* ---- transporter construction (Sec. 5.1) ---------------------------------
+ * W(x, x+n) for n_offsets = 80 (all) or 40 (hermitian half) offsets, built in
+ * FP64 from FP64 SoA links and stored in w_prec.  The k-hop transporters are
+ * obtained in hop order from the (k-1)-hop ones at the same site,
+ *   W(x, x+n) = (1/k) sum_{mu in supp n} W(x, x+n-s_mu mu) V_mu(x+n-s_mu mu),
+ * V_mu(y) = U_mu(y) for s_mu = +1 and U_mu(y-mu)^dag for s_mu = -1, which is
+ * the average over all k! paths.  work: FP64 scratch of
+ * bri_build_workspace_bytes(d, w_prec, n_offsets) bytes (0 is allowed when
+ * that query returns 0). */
+size_t bri_build_workspace_bytes(bri_dims d, bri_prec w_prec, int32_t n_offsets);
+bri_status bri_build_transporters(bri_dims d, const double *U_soa, void *W, bri_prec w_prec,
+                                  int32_t n_offsets, void *work, size_t work_bytes, void *stream);
+
+/* ---- operator application (Eq. def_pref, c_SW = 0) -----------------------
+ * out = D in (bri_apply) or out = D^dag in (bri_apply_dag) for nrhs fields.
+ * variant BRI_STORED:    W_or_U = transporters (w_prec, n_offsets = 40|80).
+ * variant BRI_RECOMPUTE: W_or_U = SoA links in w_prec (F64 or F32), the
+ *                        transporters are rebuilt on the fly; n_offsets ignored.
+ * Spinor precision s_prec: F64 (needs w_prec F64), F32 (w_prec F32 or F16),
+ * or F16 (w_prec F16).  Accumulation is FP64 for F64 and FP32 otherwise.
+ * D^dag = gamma5 D gamma5 (Sec. 1), i.e. D with rho_k -> -rho_k.
+ * nrhs >= 1 fields are processed in one fused launch that reads each
+ * transporter once per group of right-hand sides.  in and out must not
+ * overlap. */
+bri_status bri_apply(bri_dims d, bri_variant v, const void *W_or_U, bri_prec w_prec,
+                     int32_t n_offsets, bri_prec s_prec, double mass, const void *in, void *out,
+                     int32_t nrhs, void *stream);
+bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W_or_U, bri_prec w_prec,
+                         int32_t n_offsets, bri_prec s_prec, double mass, const void *in,
+                         void *out, int32_t nrhs, void *stream);
+
+/* Choose the number of right-hand sides held per thread in the fused
+ * multi-RHS apply (1, 2, 3, 4, 6 or 12; 0 restores the built-in default) for
+ * the given precisions.  Used by the autotuner; host-side state, not
+ * thread-safe against concurrent applies. */
+bri_status bri_set_rhs_block(bri_prec w_prec, bri_prec s_prec, int32_t rhs_per_thread);
+int32_t bri_get_rhs_block(bri_prec w_prec, bri_prec s_prec);
+
+/* ---- solver: CG on the normal equations D^dag D x = D^dag b ----------------
+ * The paper inverts D for propagators (Sec. 6.4, BiCGstab to 1e-7); here the
+ * solver is CGNE, stopped on the true relative residual ||b - D x||/||b||
+ * computed in FP64 for every right-hand side.
+ * inner_prec == BRI_F64: plain FP64 CGNE with W_hi (FP64 transporters).
+ * inner_prec == BRI_F32 / BRI_F16: defect correction; the outer loop forms
+ * r = b - D x in FP64 with W_hi, the inner CGNE solves D e = r in FP32
+ * arithmetic with W_lo (F32 or F16 transporters, same n_offsets) to relative
+ * inner_tol, and x += e.  b and x are FP64 SoA spinors ([rhs][12][V]); x holds
+ * the initial guess on entry and the solution on exit.  All right-hand sides
+ * iterate together (one fused apply per iteration) with their own scalars;
+ * converged columns are frozen.  Reductions are deterministic FP64. */
+typedef struct {
+    double tol;              /* target true relative residual, per RHS          */
+    double inner_tol;        /* inner relative residual for defect correction    */
+    int32_t max_iter;        /* cap on inner CG iterations (summed over outers)  */
+    int32_t max_outer;       /* cap on defect-correction cycles                  */
+    int32_t n_offsets;       /* 40 or 80, for both W_hi and W_lo                 */
+    bri_prec inner_prec;     /* F64 (plain), F32 or F16 (transporters of W_lo)   */
+    int32_t check_every;     /* iterations between host convergence checks (>=1) */
+    int32_t use_initial_guess; /* 0: x is zeroed first                           */
+} bri_solve_params;
+
+#define BRI_MAX_RHS 64
+typedef struct {
+    int32_t iterations;      /* inner CG iterations (all cycles)                 */
+    int32_t outer;           /* defect-correction cycles (1 for plain FP64)      */
+    int32_t applies;         /* operator applications (D or D^dag), per RHS block*/
+    int32_t converged;       /* 1 if every RHS met tol                           */
+    double true_residual[BRI_MAX_RHS]; /* final ||b - D x||/||b|| per RHS        */
+} bri_solve_stats;
+
+size_t bri_solve_workspace_bytes(bri_dims d, const bri_solve_params *p, int32_t nrhs);
+bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_hi,
+                          const void *W_lo, double mass, const double *b, double *x,
+                          int32_t nrhs, void *work, size_t work_bytes,
+                          bri_solve_stats *stats /* host */, void *stream);
+
+/* ---- gradient with respect to the links -----------------------------------
+ * For S = Re sum_rhs <chi, D psi> (FP64 SoA spinors, nrhs fields each) writes
+ * gradU = dS/dRe U + i dS/dIm U in the FP64 SoA link layout, treating link
+ * entries as unconstrained complex numbers, through the path averaging of
+ * the transporters.  The transporters are rebuilt from U inside the call
+ * (not stored across calls).  The psi gradient is D^dag chi (bri_apply_dag).
+ * work: bri_grad_workspace_bytes(d). */
+size_t bri_grad_workspace_bytes(bri_dims d);
+bri_status bri_grad_links(bri_dims d, const double *U_soa, const double *chi, const double *psi,
+                          int32_t nrhs, double *gradU, void *work, size_t work_bytes,
+                          void *stream);
+
+/* ---- BLAS-1 on SoA FP64 fields (deterministic) ---------------------------
+ * Per-RHS inner products <a_r, b_r> (complex, written to host array dots of
+ * 2*nrhs doubles) over n = 12*V complex numbers per RHS. */
+bri_status bri_dot(bri_dims d, int32_t nrhs, const double *a, const double *b,
+                   double *dots /* host */, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BRI_H */

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) Brillouin Dirac operator: HIP kernels behind a C ABI.
+
+Importing the package loads the in-tree HIP library ``libbri.so``; there is
+no fallback implementation, so the import fails loudly when the library has
+not been built.
+"""
+from .api import (  # noqa: F401
+    F64, F32, F16, STORED, RECOMPUTE, BriError, volume,
+    spinor_empty, links_empty, transporters_empty,
+    bri_pack_links, bri_pack_spinor, bri_unpack_spinor,
+    bri_build_transporters, bri_apply, bri_apply_dag,
+    bri_set_rhs_block, bri_get_rhs_block,
+    solve_params, bri_solve_cgne, bri_grad_links, bri_dot,
+)

@@ -1,0 +1,237 @@
+"""Python binding of the C ABI (include/bri.h): argument marshalling only.
+
+Every function forwards to the library entry point of the same name; torch
+tensors supply device memory and the current HIP stream.  SoA buffers are
+real tensors whose last axis holds (re, im):
+
+    spinors       [nrhs, 12, V, 2]     component = 3*spin + colour
+    links         [4, 9, V, 2]         element   = 3*a + b
+    transporters  [n_offsets, 9, V, 2]
+
+with dtype float64 (F64), float32 (F32) or float16 (F16).  Canonical fields
+are complex128 tensors [4, Lt, Lz, Ly, Lx, 3, 3] (links) and
+[nrhs, Lt, Lz, Ly, Lx, 4, 3] (spinors).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+F64, F32, F16 = 0, 1, 2
+STORED, RECOMPUTE = 0, 1
+
+_lib_handle = _lib.load()
+
+_TORCH = {F64: torch.float64, F32: torch.float32, F16: torch.float16}
+_PREC = {torch.float64: F64, torch.float32: F32, torch.float16: F16}
+
+
+class BriError(RuntimeError):
+    def __init__(self, status, where):
+        msg = _lib_handle.bri_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    return _lib_handle
+
+
+def _check(status, where):
+    if status != 0:
+        raise BriError(status, where)
+
+
+def _dims(dims):
+    d = _lib.bri_dims()
+    for mu in range(4):
+        d.L[mu] = int(dims[mu])
+    return d
+
+
+def volume(dims):
+    v = 1
+    for x in dims:
+        v *= int(x)
+    return v
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def prec_of(t):
+    return _PREC[t.dtype]
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("expected contiguous device tensors")
+
+
+# ------------------------------------------------------------------ allocation
+def spinor_empty(dims, prec, nrhs=1, device="cuda"):
+    return torch.empty((nrhs, 12, volume(dims), 2), dtype=_TORCH[prec], device=device)
+
+
+def links_empty(dims, prec, device="cuda"):
+    return torch.empty((4, 9, volume(dims), 2), dtype=_TORCH[prec], device=device)
+
+
+def transporters_empty(dims, prec, n_offsets, device="cuda"):
+    return torch.empty((n_offsets, 9, volume(dims), 2), dtype=_TORCH[prec], device=device)
+
+
+# ------------------------------------------------------------------ layout
+def bri_pack_links(dims, U_canon, prec=F64):
+    _need_cuda(U_canon)
+    if U_canon.dtype != torch.complex128 or U_canon.numel() != 36 * volume(dims):
+        raise ValueError("links: expected complex128 [4, Lt, Lz, Ly, Lx, 3, 3]")
+    out = links_empty(dims, prec, U_canon.device)
+    _check(_lib_handle.bri_pack_links(_dims(dims), _ptr(U_canon), _ptr(out), prec, _stream()),
+           "bri_pack_links")
+    return out
+
+
+def bri_pack_spinor(dims, psi_canon, prec=F64):
+    _need_cuda(psi_canon)
+    nrhs = psi_canon.numel() // (12 * volume(dims))
+    if psi_canon.dtype != torch.complex128 or nrhs < 1 or psi_canon.numel() != 12 * volume(dims) * nrhs:
+        raise ValueError("spinor: expected complex128 [nrhs, Lt, Lz, Ly, Lx, 4, 3]")
+    out = spinor_empty(dims, prec, nrhs, psi_canon.device)
+    _check(_lib_handle.bri_pack_spinor(_dims(dims), nrhs, _ptr(psi_canon), _ptr(out), prec,
+                                       _stream()), "bri_pack_spinor")
+    return out
+
+
+def bri_unpack_spinor(dims, soa):
+    _need_cuda(soa)
+    _shape(soa, (soa.shape[0], 12, volume(dims), 2), "spinor")
+    nrhs = soa.shape[0]
+    lx, ly, lz, lt = dims
+    out = torch.empty((nrhs, lt, lz, ly, lx, 4, 3), dtype=torch.complex128, device=soa.device)
+    _check(_lib_handle.bri_unpack_spinor(_dims(dims), nrhs, _ptr(soa), prec_of(soa), _ptr(out),
+                                         _stream()), "bri_unpack_spinor")
+    return out
+
+
+# ------------------------------------------------------------------ transporters
+def bri_build_transporters(dims, U_soa, prec=F64, n_offsets=80, out=None):
+    _need_cuda(U_soa)
+    if prec_of(U_soa) != F64:
+        raise ValueError("transporters are built from FP64 links")
+    _shape(U_soa, (4, 9, volume(dims), 2), "links")
+    if out is not None:
+        _shape(out, (n_offsets, 9, volume(dims), 2), "transporters")
+    W = out if out is not None else transporters_empty(dims, prec, n_offsets, U_soa.device)
+    nbytes = _lib_handle.bri_build_workspace_bytes(_dims(dims), prec, n_offsets)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=U_soa.device) if nbytes else None
+    _check(_lib_handle.bri_build_transporters(_dims(dims), _ptr(U_soa), _ptr(W), prec, n_offsets,
+                                              _ptr(work), nbytes, _stream()),
+           "bri_build_transporters")
+    return W
+
+
+# ------------------------------------------------------------------ apply
+def _shape(t, shape, what):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _apply(fn, name, dims, W_or_U, psi, mass, variant, out):
+    _need_cuda(W_or_U, psi, out)
+    V = volume(dims)
+    _shape(psi, (psi.shape[0], 12, V, 2), "spinor")
+    if variant == STORED:
+        _shape(W_or_U, (W_or_U.shape[0], 9, V, 2), "transporters")
+    else:
+        _shape(W_or_U, (4, 9, V, 2), "links")
+    if out is None:
+        out = torch.empty_like(psi)
+    elif out.shape != psi.shape or out.dtype != psi.dtype:
+        raise ValueError("out must match the input spinor's shape and dtype")
+    n_off = W_or_U.shape[0] if variant == STORED else 80
+    _check(fn(_dims(dims), variant, _ptr(W_or_U), prec_of(W_or_U), n_off, prec_of(psi),
+              float(mass), _ptr(psi), _ptr(out), psi.shape[0], _stream()), name)
+    return out
+
+
+def bri_apply(dims, W_or_U, psi, mass, variant=STORED, out=None):
+    """out = D psi.  W_or_U: transporters (STORED) or SoA links (RECOMPUTE)."""
+    return _apply(_lib_handle.bri_apply, "bri_apply", dims, W_or_U, psi, mass, variant, out)
+
+
+def bri_apply_dag(dims, W_or_U, psi, mass, variant=STORED, out=None):
+    """out = D^dag psi."""
+    return _apply(_lib_handle.bri_apply_dag, "bri_apply_dag", dims, W_or_U, psi, mass, variant, out)
+
+
+def bri_set_rhs_block(w_prec, s_prec, rhs_per_thread):
+    _check(_lib_handle.bri_set_rhs_block(w_prec, s_prec, rhs_per_thread), "bri_set_rhs_block")
+
+
+def bri_get_rhs_block(w_prec, s_prec):
+    return _lib_handle.bri_get_rhs_block(w_prec, s_prec)
+
+
+# ------------------------------------------------------------------ solver
+def solve_params(tol=1e-10, inner_tol=1e-4, max_iter=20000, max_outer=100, n_offsets=80,
+                 inner_prec=F64, check_every=8, use_initial_guess=False):
+    p = _lib.bri_solve_params()
+    p.tol, p.inner_tol = tol, inner_tol
+    p.max_iter, p.max_outer = max_iter, max_outer
+    p.n_offsets, p.inner_prec = n_offsets, inner_prec
+    p.check_every, p.use_initial_guess = check_every, int(bool(use_initial_guess))
+    return p
+
+
+def bri_solve_cgne(dims, W_hi, b, mass, params, W_lo=None, x=None, raise_on_noconv=True):
+    """Solve D x = b (FP64 SoA spinors).  Returns (x, stats dict)."""
+    _need_cuda(W_hi, b, W_lo, x)
+    nrhs = b.shape[0]
+    if x is None:
+        x = torch.zeros_like(b)
+    nbytes = _lib_handle.bri_solve_workspace_bytes(_dims(dims), ctypes.byref(params), nrhs)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=b.device)
+    stats = _lib.bri_solve_stats()
+    st = _lib_handle.bri_solve_cgne(_dims(dims), ctypes.byref(params), _ptr(W_hi), _ptr(W_lo),
+                                    float(mass), _ptr(b), _ptr(x), nrhs, _ptr(work), nbytes,
+                                    ctypes.byref(stats), _stream())
+    info = {
+        "iterations": stats.iterations, "outer": stats.outer, "applies": stats.applies,
+        "converged": bool(stats.converged),
+        "true_residual": [stats.true_residual[i] for i in range(min(nrhs, _lib.BRI_MAX_RHS))],
+        "status": st,
+    }
+    if st != 0 and (raise_on_noconv or st != -4):
+        raise BriError(st, "bri_solve_cgne")
+    return x, info
+
+
+# ------------------------------------------------------------------ gradient
+def bri_grad_links(dims, U_soa, chi, psi):
+    """dS/dU (FP64 SoA links) for S = Re sum_rhs <chi, D psi>."""
+    _need_cuda(U_soa, chi, psi)
+    nbytes = _lib_handle.bri_grad_workspace_bytes(_dims(dims))
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=U_soa.device)
+    g = torch.empty_like(U_soa)
+    _check(_lib_handle.bri_grad_links(_dims(dims), _ptr(U_soa), _ptr(chi), _ptr(psi), chi.shape[0],
+                                      _ptr(g), _ptr(work), nbytes, _stream()), "bri_grad_links")
+    return g
+
+
+def bri_dot(dims, a, b):
+    """Per-RHS complex inner products <a_r, b_r> of FP64 SoA fields (host result)."""
+    _need_cuda(a, b)
+    nrhs = a.shape[0]
+    res = (ctypes.c_double * (2 * nrhs))()
+    _check(_lib_handle.bri_dot(_dims(dims), nrhs, _ptr(a), _ptr(b), res, _stream()), "bri_dot")
+    return [complex(res[2 * i], res[2 * i + 1]) for i in range(nrhs)]

@@ -1,0 +1,156 @@
+// Construction of the gauge transporters W(x, x+n) (Sec. 5.1): the average of
+// the link products over all k! shortest paths from x to x+n.
+//
+// The k-hop transporters follow from the (k-1)-hop ones at the same site by
+// splitting off the last step of every path:
+//   W(x, x+n) = (1/k) sum_{mu in supp n} W(x, x+n-s_mu mu) L(n, mu),
+//   L(n, mu) = U_mu(x+n-mu)      if s_mu = +1,
+//            = U_mu(x+n)^dag     if s_mu = -1,
+// (grouping the k! paths by their last direction gives k groups of (k-1)!
+// paths, each of which is the (k-1)-hop average times the last link).
+// Levels are built in separate launches (1, 2, 3, 4 hops), in FP64, into the
+// 40-offset store (offsets whose last non-zero component is +1); the other
+// orientation of a lower-level transporter is read through
+// W(x, x+m) = W(x+m, x)^dag.
+#include "common.h"
+#include "kernels.h"
+
+namespace bri {
+
+namespace {
+
+__device__ __forceinline__ void load_mat(const double2 *p, size_t V, bool dagger, cx<double> m[3][3]) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        cx<double> v = ldc<double>(p + e * V);
+        if (dagger)
+            m[e % 3][e / 3] = cconj(v);
+        else
+            m[e / 3][e % 3] = v;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_build_level(Geom g, const double2 *__restrict__ U,
+                                                     double2 *__restrict__ W40) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= g.V) return;
+    const size_t V = (size_t)g.V;
+    int c[4];
+    coords(g, site, c);
+    const Nbr nb = make_nbr(g, c);
+
+    static_for<41, 81>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (off_k(i) == K) {
+            constexpr int n[4] = {off_n(i, 0), off_n(i, 1), off_n(i, 2), off_n(i, 3)};
+            cx<double> acc[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) acc[a][b] = cmake(0.0, 0.0);
+            static_for<0, 4>([&](auto M) {
+                constexpr int mu = decltype(M)::value;
+                if constexpr (n[mu] != 0) {
+                    // last link L(n, mu)
+                    constexpr int sm = n[mu];
+                    int dl[4] = {n[0], n[1], n[2], n[3]};
+                    if (sm > 0) dl[mu] -= 1;
+                    const int yl = nb.at(dl[0], dl[1], dl[2], dl[3]);
+                    cx<double> l[3][3];
+                    load_mat(U + (size_t)mu * 9 * V + yl, V, sm < 0, l);
+                    if constexpr (K == 1) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) acc[a][b] = cadd(acc[a][b], l[a][b]);
+                    } else {
+                        // predecessor m = n - s_mu mu
+                        constexpr int m0 = mu == 0 ? 0 : n[0], m1 = mu == 1 ? 0 : n[1],
+                                      m2 = mu == 2 ? 0 : n[2], m3 = mu == 3 ? 0 : n[3];
+                        constexpr int im = off_index(m0, m1, m2, m3);
+                        cx<double> p[3][3];
+                        if constexpr (is_canonical(im)) {
+                            load_mat(W40 + (size_t)plane40(im) * 9 * V + site, V, false, p);
+                        } else {
+                            const int ym = nb.at(m0, m1, m2, m3);
+                            load_mat(W40 + (size_t)plane40(80 - im) * 9 * V + ym, V, true, p);
+                        }
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) {
+                                cx<double> t = acc[a][b];
+                                t = cmac(t, p[a][0], l[0][b]);
+                                t = cmac(t, p[a][1], l[1][b]);
+                                acc[a][b] = cmac(t, p[a][2], l[2][b]);
+                            }
+                    }
+                }
+            });
+            constexpr double inv = 1.0 / K;
+            double2 *o = W40 + (size_t)plane40(i) * 9 * V + site;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) st(o + (3 * a + b) * V, cscale(inv, acc[a][b]));
+        }
+    });
+}
+
+// W40 (FP64) -> target store (precision WT, 40 or 80 offsets).  One thread per
+// (site, target plane).
+template <typename WT>
+__global__ __launch_bounds__(256) void k_convert(Geom g, const double2 *__restrict__ W40,
+                                                 WT *__restrict__ W, int noff) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= g.V) return;
+    const int j = blockIdx.y;
+    const size_t V = (size_t)g.V;
+    const int i = noff == 80 ? (j < 40 ? j : j + 1) : j + 41;
+    WT *o = W + (size_t)j * 9 * V + site;
+    if (i > 40) {
+        const double2 *p = W40 + (size_t)(i - 41) * 9 * V + site;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) st(o + e * V, ldc<double>(p + e * V));
+    } else {
+        int c[4];
+        coords(g, site, c);
+        const Nbr nb = make_nbr(g, c);
+        const int y = nb.at(off_n(i, 0), off_n(i, 1), off_n(i, 2), off_n(i, 3));
+        const double2 *p = W40 + (size_t)(80 - i - 41) * 9 * V + y;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            // element (a,b) of W(x,x+n) = conj of element (b,a) of W(x+n,x)
+            const int a = e / 3, b = e % 3;
+            st(o + e * V, cconj(ldc<double>(p + (3 * b + a) * V)));
+        }
+    }
+}
+
+constexpr int kBlock = 256;
+}  // namespace
+
+hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st) {
+    dim3 grid((g.V + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_build_level<1>, grid, dim3(kBlock), 0, st, g, U, W40);
+    hipLaunchKernelGGL(k_build_level<2>, grid, dim3(kBlock), 0, st, g, U, W40);
+    hipLaunchKernelGGL(k_build_level<3>, grid, dim3(kBlock), 0, st, g, U, W40);
+    hipLaunchKernelGGL(k_build_level<4>, grid, dim3(kBlock), 0, st, g, U, W40);
+    return hipGetLastError();
+}
+
+hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st) {
+    dim3 grid((g.V + kBlock - 1) / kBlock, noff);
+    if (wp == 0)
+        hipLaunchKernelGGL(k_convert<double2>, grid, dim3(kBlock), 0, st, g, W40, (double2 *)W, noff);
+    else if (wp == 1)
+        hipLaunchKernelGGL(k_convert<float2>, grid, dim3(kBlock), 0, st, g, W40, (float2 *)W, noff);
+    else if (wp == 2)
+        hipLaunchKernelGGL(k_convert<__half2>, grid, dim3(kBlock), 0, st, g, W40, (__half2 *)W, noff);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace bri

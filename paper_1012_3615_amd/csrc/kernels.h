@@ -1,0 +1,43 @@
+// Host-side launchers of the HIP kernels (internal to the library; the public
+// C ABI is include/bri.h).  Precision codes: 0 = FP64, 1 = FP32, 2 = FP16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace bri {
+
+// apply.hip
+hipError_t apply_stored(const Geom &g, int noff, int wp, int sp, const void *W, const void *in,
+                        void *out, double diag, int nrhs, int rblk, bool dag, hipStream_t st);
+hipError_t apply_recompute(const Geom &g, int up, int sp, const void *U, const void *in, void *out,
+                           double diag, int nrhs, bool dag, hipStream_t st);
+
+// build.hip: FP64 40-offset store, then conversion
+hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st);
+hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st);
+
+// pack.hip
+hipError_t pack_links(const Geom &g, const double2 *canon, void *soa, int p, hipStream_t st);
+hipError_t pack_spinor(const Geom &g, int nrhs, const double2 *canon, void *soa, int p,
+                       hipStream_t st);
+hipError_t unpack_spinor(const Geom &g, int nrhs, const void *soa, int p, double2 *canon,
+                         hipStream_t st);
+
+// blas.hip: fields are nrhs blocks of n complex numbers each (n = 12 V)
+// convert between precisions: dst(p_dst) = src(p_src) * scale[rhs] (scale may be null)
+hipError_t convert_field(size_t n, int nrhs, const void *src, int ps, void *dst, int pd,
+                         const double *scale, hipStream_t st);
+// per-rhs partial sums of <a,b> (complex) and |b|^2 into part[rhs][nblk][3]; then finish
+hipError_t dot_partials(size_t n, int nrhs, const void *a, const void *b, int p, double *part,
+                        int nblk, hipStream_t st);
+hipError_t dot_finish(int nrhs, const double *part, int nblk, double *out3, hipStream_t st);
+int dot_blocks(size_t n);
+
+// grad.hip
+hipError_t grad_links_f64(const Geom &g, const double2 *U, const double2 *W40, const double2 *chi,
+                          const double2 *psi, int nrhs, double2 *GW, double2 *gradU,
+                          hipStream_t st);
+
+}  // namespace bri

@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads and exports
+every function declared in include/bri.h, and the pure size queries agree
+with the documented layouts."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bri.h")
+LIB = os.path.join(ROOT, "paper_1012_3615_amd", "libbri.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(bri_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libbri.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["bri_build_transporters", "bri_apply", "bri_apply_dag", "bri_solve_cgne",
+                     "bri_grad_links", "bri_pack_links", "bri_pack_spinor", "bri_unpack_spinor"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_python_prototypes_cover_header():
+    from paper_1012_3615_amd import _lib as plib
+    assert set(declared_functions()) <= set(plib.PROTOTYPES)
+
+
+def test_size_queries(lib):
+    from paper_1012_3615_amd import _lib as plib
+    for name, (res, args) in plib.PROTOTYPES.items():
+        getattr(lib, name).restype = res
+        getattr(lib, name).argtypes = args
+    d = plib.bri_dims()
+    for i, v in enumerate((32, 32, 32, 64)):
+        d.L[i] = v
+    V = 32 ** 3 * 64
+    assert lib.bri_spinor_bytes(d, 1, 1) == V * 12 * 8
+    assert lib.bri_spinor_bytes(d, 0, 12) == V * 12 * 16 * 12
+    assert lib.bri_links_bytes(d, 0) == V * 36 * 16
+    assert lib.bri_transporter_bytes(d, 1, 80) == V * 80 * 9 * 8
+    assert lib.bri_transporter_bytes(d, 2, 40) == V * 40 * 9 * 4
+    assert lib.bri_transporter_bytes(d, 1, 39) == 0
+    assert lib.bri_build_workspace_bytes(d, 0, 40) == 0
+    assert lib.bri_build_workspace_bytes(d, 1, 80) == V * 40 * 9 * 16
+    assert lib.bri_abi_version() == 1
+    d.L[3] = 1
+    assert lib.bri_spinor_bytes(d, 1, 1) == 0
+
+
+def test_argument_errors_without_device(lib):
+    """Argument validation happens before any device work: null pointers and
+    bad extents are rejected with BRI_E_ARG and a message."""
+    from paper_1012_3615_amd import _lib as plib
+    for name, (res, args) in plib.PROTOTYPES.items():
+        getattr(lib, name).restype = res
+        getattr(lib, name).argtypes = args
+    d = plib.bri_dims()
+    for i in range(4):
+        d.L[i] = 4
+    st = lib.bri_apply(d, 0, None, 1, 80, 1, 0.1, None, None, 1, None)
+    assert st == -1
+    assert b"pointer" in lib.bri_last_error()
+    d.L[0] = 1
+    st = lib.bri_build_transporters(d, None, None, 0, 80, None, 0, None)
+    assert st == -1
