@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark: Brillouin operator applications per second at 32^3 x 64.
+
+One step = one application out = D_B psi of the 81-point Brillouin operator
+(Eq. def_pref, c_SW = 0) on a 32^3 x 64 lattice, FP32 storage and FP32
+arithmetic, with the 80 stored hypercube-averaged transporters (built once,
+in FP64, before the timed region).  Inputs are seeded synthetic fields
+resident in HBM: SU(3) links U = exp(i 0.3 H) (seed 4001), Gaussian spinor
+(seed 4002), m = 0.1.
+
+Printed (one JSON line): applications/s, the roofline of the apply kernel
+(algorithmic bytes per launch over its mean launch time, measured with HIP
+events on the library's stream), the CPU oracle timed on a bounded sample of
+the same workload, and side measurements of the other variants.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DIMS = (32, 32, 32, 64)
+MASS = 0.1
+EPS = 0.3
+SEED_U, SEED_PSI = 4001, 4002
+HBM_PEAK_GBS = 8000.0
+FLOPS_PER_SITE = 35376           # nominal flops per site and right-hand side
+KERNEL_SOURCES = ["paper_1012_3615_amd/csrc/apply_kernels.h", "paper_1012_3615_amd/csrc/common.h"]
+PMC_FILE = os.path.join(ROOT, "profiles", "apply_stored_f32_w80_32x32x32x64.pmc.json")
+
+
+def bytes_per_site(n_off, wbytes, sbytes, nrhs=1):
+    """Algorithmic HBM bytes per site: every stored transporter read once,
+    each input spinor read once and each output spinor written once."""
+    return n_off * 9 * wbytes + nrhs * 2 * 12 * sbytes
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def timed_launches(torch, fn, steps, warmup):
+    """Run fn warmup times, then time `steps` launches with one event pair per
+    launch on the current stream (where the library launches).  Returns
+    (total seconds, list of per-launch ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record()
+        fn()
+        e.record()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return total, [s.elapsed_time(e) for s, e in ev]
+
+
+def cpu_baseline(u, psi, target_s=15.0):
+    """The CPU oracle as it stands (plain numpy, FP64), on sampled sites of the
+    same 32^3 x 64 workload, scaled to applications/s of the whole lattice."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import dirac
+    V = int(np.prod(DIMS))
+    rng = np.random.default_rng(99)
+    with threadpool_limits(limits=1):
+        probe = np.stack([rng.integers(0, L, 256) for L in DIMS], axis=1)
+        t0 = time.perf_counter()
+        dirac.apply_at(u, psi, MASS, probe)
+        dt0 = time.perf_counter() - t0
+        n = int(min(1 << 16, max(256, 256 * target_s / max(dt0, 1e-3))))
+        sites = np.stack([rng.integers(0, L, n) for L in DIMS], axis=1)
+        t0 = time.perf_counter()
+        dirac.apply_at(u, psi, MASS, sites)
+        dt = time.perf_counter() - t0
+    return {"value": (n / dt) / V, "unit": "applies/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} random sites of the 32^3x64 lattice via the pointwise oracle "
+                      f"(FP64 numpy, single thread), {dt:.1f} s, scaled by sites/V"}
+
+
+def traffic_from_profile(launch_bytes_alg):
+    if not os.path.exists(PMC_FILE):
+        return None
+    with open(PMC_FILE) as f:
+        p = json.load(f)
+    if p.get("kernel_hash") != kernel_hash():
+        return None
+    return p.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the multi-GPU decomposition is a design, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1012_3615_amd as bri
+
+    V = bri.volume(DIMS)
+    t0 = time.perf_counter()
+    u = synth.gauge_links(DIMS, EPS, SEED_U)
+    psi = synth.gaussian_spinor(DIMS, SEED_PSI, nrhs=1)
+    gen_s = time.perf_counter() - t0
+
+    dev = torch.device("cuda:0")
+    U64 = bri.bri_pack_links(DIMS, torch.from_numpy(u).to(dev), bri.F64)
+    x32 = bri.bri_pack_spinor(DIMS, torch.from_numpy(psi).to(dev), bri.F32)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    W = bri.bri_build_transporters(DIMS, U64, bri.F32, 80)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb) * 1e3
+    out = torch.empty_like(x32)
+
+    # calibration copy of known size (for the PMC traffic scale factor)
+    cal = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    cal2 = torch.empty_like(cal)
+    cal2.copy_(cal)
+    torch.cuda.synchronize()
+
+    total_s, per = timed_launches(torch, lambda: bri.bri_apply(DIMS, W, x32, MASS, out=out),
+                                  a.steps, a.warmup)
+    per_ms = float(np.mean(per))
+    value = a.steps / total_s
+    bps = bytes_per_site(80, 8, 8)
+    launch_bytes = bps * V
+    achieved = launch_bytes / (per_ms * 1e-3) / 1e9
+
+    # spot parity of the timed configuration against the pointwise oracle
+    from oracle import dirac
+    rng = np.random.default_rng(5)
+    sites = np.stack([rng.integers(0, L, 64) for L in DIMS], axis=1)
+    got = bri.bri_unpack_spinor(DIMS, out).cpu().numpy()[0]
+    ref = dirac.apply_at(u, psi[0], MASS, sites)
+    gs = np.stack([got[t, z, y, x] for x, y, z, t in sites])
+    spot_err = float(np.linalg.norm(gs - ref) / np.linalg.norm(ref))
+
+    res = {
+        "metric": "D_B applies/sec at 32^3x64 (FP32, stored 80 transporters)",
+        "value": value,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": total_s / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "brillouin_apply_32x32x32x64", "lattice": list(DIMS),
+                   "variant": "stored", "n_offsets": 80, "w_prec": "f32", "s_prec": "f32",
+                   "nrhs": 1, "mass": MASS, "links": f"exp(i*{EPS}*H), seed {SEED_U}",
+                   "spinor": f"gaussian, seed {SEED_PSI}"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(launch_bytes),
+                     "kernel": "k_apply_stored<80,float2,float2,float,false,1>",
+                     "alg_bytes_per_site": bps, "alg_bytes_per_launch": launch_bytes,
+                     "kernel_ms": per_ms},
+        "gflops": FLOPS_PER_SITE * V / (per_ms * 1e-3) / 1e9,
+        "spot_parity_rel_err": spot_err,
+        "build_transporters_ms": build_ms,
+        "input_generation_s": gen_s,
+    }
+
+    if not a.no_extras:
+        extras = {}
+
+        def bench_variant(name, Wv, xv, n_off, wb, sb, variant=bri.STORED, dag=False, steps=20):
+            fn = (lambda: bri.bri_apply_dag(DIMS, Wv, xv, MASS, variant=variant)) if dag else \
+                 (lambda: bri.bri_apply(DIMS, Wv, xv, MASS, variant=variant))
+            _, p = timed_launches(torch, fn, steps, 3)
+            ms = float(np.mean(p))
+            d = {"ms": ms, "applies_s": 1e3 / ms}
+            if wb:
+                byts = bytes_per_site(n_off, wb, sb, xv.shape[0]) * V
+                d["alg_GBs"] = byts / (ms * 1e-3) / 1e9
+                d["hbm_frac"] = d["alg_GBs"] / HBM_PEAK_GBS
+                d["frac_vs_w40_min"] = bytes_per_site(40, wb, sb, xv.shape[0]) * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+            extras[name] = d
+
+        bench_variant("stored_w80_f32_dag", W, x32, 80, 8, 8, dag=True)
+        W40 = bri.bri_build_transporters(DIMS, U64, bri.F32, 40)
+        bench_variant("stored_w40_f32", W40, x32, 40, 8, 8)
+        del W40
+        W16 = bri.bri_build_transporters(DIMS, U64, bri.F16, 80)
+        bench_variant("stored_w80_f16w_f32s", W16, x32, 80, 4, 8)
+        x16 = bri.bri_pack_spinor(DIMS, torch.from_numpy(psi).to(dev), bri.F16)
+        bench_variant("stored_w80_f16w_f16s", W16, x16, 80, 4, 4)
+        del W16, x16
+        x64 = bri.bri_pack_spinor(DIMS, torch.from_numpy(psi).to(dev), bri.F64)
+        W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
+        bench_variant("stored_w80_f64", W64, x64, 80, 16, 16)
+        del W64
+        U32 = bri.bri_pack_links(DIMS, torch.from_numpy(u).to(dev), bri.F32)
+        bench_variant("recompute_f32", U32, x32, 0, 0, 0, variant=bri.RECOMPUTE, steps=5)
+        bench_variant("recompute_f64", U64, x64, 0, 0, 0, variant=bri.RECOMPUTE, steps=5)
+        del U32, x64
+        # 12 spin-colour point sources in one fused launch
+        src = synth.point_sources(DIMS)
+        x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F32)
+        del src
+        bench_variant("stored_w80_f32_12rhs", W, x12, 80, 8, 8, steps=5)
+        extras["stored_w80_f32_12rhs"]["rhs_per_thread"] = bri.bri_get_rhs_block(bri.F32, bri.F32)
+        del x12
+        torch.cuda.empty_cache()
+        res["extras"] = extras
+
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(u, psi[0])
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,6 +134,14 @@ bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W_or_U, bri_prec
 bri_status bri_set_rhs_block(bri_prec w_prec, bri_prec s_prec, int32_t rhs_per_thread);
 int32_t bri_get_rhs_block(bri_prec w_prec, bri_prec s_prec);
 
+/* Choose the stored-variant kernel used when one right-hand side is held per
+ * thread: 1 = LDS tiles (default; each workgroup stages the spinor of its
+ * x-y tile plus halo layer by layer in LDS), 0 = direct neighbour gathers
+ * through the caches.  Both compute the same sums in the same order per
+ * site.  Host-side state, not thread-safe against concurrent applies. */
+bri_status bri_set_apply_kernel(bri_prec w_prec, bri_prec s_prec, int32_t kernel);
+int32_t bri_get_apply_kernel(bri_prec w_prec, bri_prec s_prec);
+
 /* ---- solver: CG on the normal equations D^dag D x = D^dag b ----------------
  * The paper inverts D for propagators (Sec. 6.4, BiCGstab to 1e-7); here the
  * solver is CGNE, stopped on the true relative residual ||b - D x||/||b||

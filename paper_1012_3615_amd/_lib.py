@@ -60,6 +60,8 @@ PROTOTYPES = {
     "bri_apply_dag": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
     "bri_set_rhs_block": (_i32, [_i32, _i32, _i32]),
     "bri_get_rhs_block": (_i32, [_i32, _i32]),
+    "bri_set_apply_kernel": (_i32, [_i32, _i32, _i32]),
+    "bri_get_apply_kernel": (_i32, [_i32, _i32]),
     "bri_solve_workspace_bytes": (_sz, [_D, ctypes.POINTER(bri_solve_params), _i32]),
     "bri_solve_cgne": (_i32, [_D, ctypes.POINTER(bri_solve_params), _vp, _vp, _dbl, _vp, _vp,
                               _i32, _vp, _sz, ctypes.POINTER(bri_solve_stats), _vp]),

@@ -182,6 +182,14 @@ def bri_get_rhs_block(w_prec, s_prec):
     return _lib_handle.bri_get_rhs_block(w_prec, s_prec)
 
 
+def bri_set_apply_kernel(w_prec, s_prec, kernel):
+    _check(_lib_handle.bri_set_apply_kernel(w_prec, s_prec, kernel), "bri_set_apply_kernel")
+
+
+def bri_get_apply_kernel(w_prec, s_prec):
+    return _lib_handle.bri_get_apply_kernel(w_prec, s_prec)
+
+
 # ------------------------------------------------------------------ solver
 def solve_params(tol=1e-10, inner_tol=1e-4, max_iter=20000, max_outer=100, n_offsets=80,
                  inner_prec=F64, check_every=8, use_initial_guess=False):

@@ -53,6 +53,8 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 namespace {
 // rhs-per-thread setting of the fused multi-RHS apply, per (w_prec, s_prec)
 int g_rhs_block[3][3] = {{2, 2, 2}, {4, 4, 4}, {4, 4, 4}};
+// apply kernel per (w_prec, s_prec): 0 = register-blocked gather, 1 = LDS tiles
+int g_apply_kernel[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};
 
 int snap_rblk(int want, int nrhs) {
     static const int allowed[] = {12, 6, 4, 3, 2, 1};
@@ -81,7 +83,8 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
         const bool combo = (wp == BRI_F64 && sp == BRI_F64) || (wp == BRI_F32 && sp == BRI_F32) ||
                            (wp == BRI_F16 && (sp == BRI_F32 || sp == BRI_F16));
         if (!combo) return fail(BRI_E_UNSUPPORTED, "unsupported (w_prec, s_prec) combination");
-        const int rblk = nrhs == 1 ? 1 : snap_rblk(g_rhs_block[wp][sp], nrhs);
+        int rblk = nrhs == 1 ? 1 : snap_rblk(g_rhs_block[wp][sp], nrhs);
+        if (rblk == 1 && g_apply_kernel[wp][sp] == 1) rblk = 0;  // 0 selects the LDS-tiled kernel
         return hip_check(apply_stored(g, noff, (int)wp, (int)sp, W, in, out, diag, nrhs, rblk, dag, st),
                          "apply (stored)");
     }
@@ -207,6 +210,19 @@ bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
         return fail(BRI_E_ARG, "rhs_per_thread must be 1, 2, 3, 4, 6 or 12");
     g_rhs_block[wp][sp] = r;
     return BRI_OK;
+}
+
+bri_status bri_set_apply_kernel(bri_prec wp, bri_prec sp, int32_t kernel) {
+    g_last_error.clear();
+    if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
+    if (kernel != 0 && kernel != 1) return fail(BRI_E_ARG, "kernel must be 0 (gather) or 1 (LDS tiles)");
+    g_apply_kernel[wp][sp] = kernel;
+    return BRI_OK;
+}
+
+int32_t bri_get_apply_kernel(bri_prec wp, bri_prec sp) {
+    if (!prec_ok(wp) || !prec_ok(sp)) return -1;
+    return g_apply_kernel[wp][sp];
 }
 
 int32_t bri_get_rhs_block(bri_prec wp, bri_prec sp) {

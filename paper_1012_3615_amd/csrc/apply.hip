@@ -31,9 +31,28 @@ hipError_t launch_stored_r(const Geom &g, const void *W, const void *in, void *o
     return hipGetLastError();
 }
 
+template <int NOFF, typename WS, typename SS, typename A, int TX, int TY>
+hipError_t launch_tiled_t(const Geom &g, const void *W, const void *in, void *out, double diag,
+                          int nrhs, bool dag, hipStream_t st) {
+    const int ntx = (g.L[0] + TX - 1) / TX, nty = (g.L[1] + TY - 1) / TY;
+    dim3 grid(ntx * nty * g.L[2] * g.L[3], nrhs);
+    if (dag)
+        hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY>), grid, dim3(TX * TY), 0, st,
+                           g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out, (A)diag);
+    else
+        hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY>), grid, dim3(TX * TY), 0,
+                           st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out, (A)diag);
+    return hipGetLastError();
+}
+
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t launch_stored(const Geom &g, const void *W, const void *in, void *out, double diag,
                          int nrhs, int rblk, bool dag, hipStream_t st) {
+    if (rblk == 0) {  // LDS-tiled kernel, one right-hand side per thread
+        if (g.L[0] <= 16)
+            return launch_tiled_t<NOFF, WS, SS, A, 16, 16>(g, W, in, out, diag, nrhs, dag, st);
+        return launch_tiled_t<NOFF, WS, SS, A, 32, 8>(g, W, in, out, diag, nrhs, dag, st);
+    }
     switch (rblk) {
         case 1: return launch_stored_r<NOFF, WS, SS, A, 1>(g, W, in, out, diag, nrhs, dag, st);
         case 2: return launch_stored_r<NOFF, WS, SS, A, 2>(g, W, in, out, diag, nrhs, dag, st);

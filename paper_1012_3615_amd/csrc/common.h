@@ -78,6 +78,26 @@ __device__ __forceinline__ cx<A> ld(const __half2 *p) {
     float2 v = __half22float2(*p);
     return {(A)v.x, (A)v.y};
 }
+// streaming loads (data read exactly once per launch: the 80-offset store)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename A>
+__device__ __forceinline__ cx<A> ldnt(const double2 *p) {
+    f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+    return {(A)v.x, (A)v.y};
+}
+template <typename A>
+__device__ __forceinline__ cx<A> ldnt(const float2 *p) {
+    f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(p));
+    return {(A)v.x, (A)v.y};
+}
+template <typename A>
+__device__ __forceinline__ cx<A> ldnt(const __half2 *p) {
+    unsigned int u = __builtin_nontemporal_load(reinterpret_cast<const unsigned int *>(p));
+    __half2 h = *reinterpret_cast<__half2 *>(&u);
+    float2 v = __half22float2(h);
+    return {(A)v.x, (A)v.y};
+}
 // cached (reused) loads: spinor neighbours
 template <typename A>
 __device__ __forceinline__ cx<A> ldc(const double2 *p) {
