@@ -192,12 +192,6 @@ bri_status bri_grad_links(bri_dims d, const double *U_soa, const double *chi, co
                           int32_t nrhs, double *gradU, void *work, size_t work_bytes,
                           void *stream);
 
-/* ---- BLAS-1 on SoA FP64 fields (deterministic) ---------------------------
- * Per-RHS inner products <a_r, b_r> (complex, written to host array dots of
- * 2*nrhs doubles) over n = 12*V complex numbers per RHS. */
-bri_status bri_dot(bri_dims d, int32_t nrhs, const double *a, const double *b,
-                   double *dots /* host */, void *stream);
-
 #ifdef __cplusplus
 }
 #endif

@@ -10,5 +10,5 @@ from .api import (  # noqa: F401
     bri_pack_links, bri_pack_spinor, bri_unpack_spinor,
     bri_build_transporters, bri_apply, bri_apply_dag,
     bri_set_rhs_block, bri_get_rhs_block, bri_set_apply_kernel, bri_get_apply_kernel,
-    solve_params, bri_solve_cgne, bri_grad_links, bri_dot,
+    solve_params, bri_solve_cgne, bri_grad_links,
 )

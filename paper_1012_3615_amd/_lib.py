@@ -67,7 +67,6 @@ PROTOTYPES = {
                               _i32, _vp, _sz, ctypes.POINTER(bri_solve_stats), _vp]),
     "bri_grad_workspace_bytes": (_sz, [_D]),
     "bri_grad_links": (_i32, [_D, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
-    "bri_dot": (_i32, [_D, _i32, _vp, _vp, _vp, _vp]),
 }
 
 

@@ -234,12 +234,3 @@ def bri_grad_links(dims, U_soa, chi, psi):
     _check(_lib_handle.bri_grad_links(_dims(dims), _ptr(U_soa), _ptr(chi), _ptr(psi), chi.shape[0],
                                       _ptr(g), _ptr(work), nbytes, _stream()), "bri_grad_links")
     return g
-
-
-def bri_dot(dims, a, b):
-    """Per-RHS complex inner products <a_r, b_r> of FP64 SoA fields (host result)."""
-    _need_cuda(a, b)
-    nrhs = a.shape[0]
-    res = (ctypes.c_double * (2 * nrhs))()
-    _check(_lib_handle.bri_dot(_dims(dims), nrhs, _ptr(a), _ptr(b), res, _stream()), "bri_dot")
-    return [complex(res[2 * i], res[2 * i + 1]) for i in range(nrhs)]

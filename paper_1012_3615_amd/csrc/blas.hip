@@ -1,2 +1,260 @@
-// BLAS-1 kernels (placeholder).
-#include "kernels.h"
+// BLAS-1 kernels for the solver: every field is nrhs blocks of n real
+// numbers (n = 24 V: 12 complex components per site).  Reductions are
+// deterministic: each workgroup sums a fixed slice in a fixed tree order into
+// its own partial (FP64), and a second kernel adds the partials of each
+// right-hand side in a fixed order.  No atomics.
+#include "blas.h"
+
+namespace bri {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kMaxBlocks = 1024;
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) { return (double)v; }
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = kB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[rhs][blk][0..1] = (sum a_i b_i over real and imaginary parts, sum a_re b_im - a_im b_re)
+// over this block's slice, treating consecutive pairs as complex numbers.
+template <typename T>
+__global__ __launch_bounds__(kB) void k_dot_partial(size_t ncx, const T *__restrict__ a,
+                                                    const T *__restrict__ b, double *partial) {
+    __shared__ double sh[kB];
+    const size_t rhs = blockIdx.y;
+    const T *pa = a + rhs * 2 * ncx;
+    const T *pb = b + rhs * 2 * ncx;
+    double re = 0.0, im = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < ncx; i += (size_t)gridDim.x * kB) {
+        const double ar = to_d(pa[2 * i]), ai = to_d(pa[2 * i + 1]);
+        const double br = to_d(pb[2 * i]), bi = to_d(pb[2 * i + 1]);
+        re = fma(ar, br, fma(ai, bi, re));
+        im = fma(ar, bi, fma(-ai, br, im));
+    }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (threadIdx.x == 0) {
+        partial[(rhs * gridDim.x + blockIdx.x) * 2 + 0] = re;
+        partial[(rhs * gridDim.x + blockIdx.x) * 2 + 1] = im;
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_dot_finish(int nblk, const double *partial, double *out) {
+    __shared__ double sh[kB];
+    const int rhs = blockIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kB) {
+        re += partial[((size_t)rhs * nblk + i) * 2 + 0];
+        im += partial[((size_t)rhs * nblk + i) * 2 + 1];
+    }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (threadIdx.x == 0) {
+        out[2 * rhs + 0] = re;
+        out[2 * rhs + 1] = im;
+    }
+}
+
+// x += alpha p ; r -= alpha q  (per-rhs real alpha), and |r|^2 partials
+template <typename T>
+__global__ __launch_bounds__(kB) void k_update_xr(size_t n, const double *__restrict__ alpha,
+                                                  T *__restrict__ x, const T *__restrict__ p,
+                                                  T *__restrict__ r, const T *__restrict__ q,
+                                                  double *partial) {
+    __shared__ double sh[kB];
+    const size_t rhs = blockIdx.y;
+    const double al = alpha[rhs];
+    const size_t off = rhs * n;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB) {
+        const size_t j = off + i;
+        x[j] = (T)((double)x[j] + al * (double)p[j]);
+        const T rv = (T)((double)r[j] - al * (double)q[j]);
+        r[j] = rv;
+        acc = fma((double)rv, (double)rv, acc);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        partial[(rhs * gridDim.x + blockIdx.x) * 2 + 0] = acc;
+        partial[(rhs * gridDim.x + blockIdx.x) * 2 + 1] = 0.0;
+    }
+}
+
+// p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(kB) void k_update_p(size_t n, const double *__restrict__ beta,
+                                                 const T *__restrict__ z, T *__restrict__ p) {
+    const size_t rhs = blockIdx.y;
+    const double be = beta[rhs];
+    const size_t off = rhs * n;
+    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB)
+        p[off + i] = (T)((double)z[off + i] + be * (double)p[off + i]);
+}
+
+// dst = src * scale[rhs] (precision conversion), scale may be null (= 1)
+template <typename S, typename D>
+__global__ __launch_bounds__(kB) void k_convert(size_t n, const S *__restrict__ src,
+                                                D *__restrict__ dst, const double *scale) {
+    const size_t rhs = blockIdx.y;
+    const double sc = scale ? scale[rhs] : 1.0;
+    const size_t off = rhs * n;
+    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB)
+        dst[off + i] = (D)((double)src[off + i] * sc);
+}
+
+// x += scale[rhs] * e  (FP64 x, e of type S)
+template <typename S>
+__global__ __launch_bounds__(kB) void k_accum(size_t n, const S *__restrict__ e,
+                                              double *__restrict__ x, const double *scale) {
+    const size_t rhs = blockIdx.y;
+    const double sc = scale[rhs];
+    const size_t off = rhs * n;
+    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB)
+        x[off + i] = fma(sc, (double)e[off + i], x[off + i]);
+}
+
+// r = b - Dx and |r|^2 partials (FP64)
+__global__ __launch_bounds__(kB) void k_residual(size_t n, const double *__restrict__ b,
+                                                 const double *__restrict__ dx,
+                                                 double *__restrict__ r, double *partial) {
+    __shared__ double sh[kB];
+    const size_t rhs = blockIdx.y;
+    const size_t off = rhs * n;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB) {
+        const double v = b[off + i] - dx[off + i];
+        r[off + i] = v;
+        acc = fma(v, v, acc);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        partial[(rhs * gridDim.x + blockIdx.x) * 2 + 0] = acc;
+        partial[(rhs * gridDim.x + blockIdx.x) * 2 + 1] = 0.0;
+    }
+}
+
+// CG scalars, one thread per rhs.  State arrays of nrhs doubles each, at
+// st + k * nrhs for k = 0 zz, 1 qq, 2 rr, 3 alpha, 4 beta, 5 active, 6 thr2.
+__global__ void k_alpha(int nrhs, double *st, const double *qq2) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double *zz = st, *qq = st + nrhs, *alpha = st + 3 * nrhs, *active = st + 5 * nrhs;
+    qq[r] = qq2[2 * r];
+    const bool ok = active[r] != 0.0 && qq[r] > 0.0;
+    alpha[r] = ok ? zz[r] / qq[r] : 0.0;
+}
+
+__global__ void k_beta(int nrhs, double *st, const double *rr2, const double *zz2) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double *zz = st, *rr = st + 2 * nrhs, *beta = st + 4 * nrhs, *active = st + 5 * nrhs,
+           *thr2 = st + 6 * nrhs;
+    rr[r] = rr2[2 * r];
+    const double znew = zz2[2 * r];
+    const bool ok = active[r] != 0.0 && zz[r] > 0.0;
+    beta[r] = ok ? znew / zz[r] : 0.0;
+    zz[r] = znew;
+    // freeze converged (or broken-down) columns
+    if (!(rr[r] > thr2[r]) || !(znew > 0.0)) active[r] = 0.0;
+}
+
+__global__ void k_init(int nrhs, double *st, const double *rr2, const double *zz2, double rel2) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double *zz = st, *rr = st + 2 * nrhs, *alpha = st + 3 * nrhs, *beta = st + 4 * nrhs,
+           *active = st + 5 * nrhs, *thr2 = st + 6 * nrhs;
+    rr[r] = rr2[2 * r];
+    zz[r] = zz2[2 * r];
+    thr2[r] = rel2 * rr[r];
+    alpha[r] = beta[r] = 0.0;
+    active[r] = (rr[r] > 0.0 && zz[r] > 0.0) ? 1.0 : 0.0;
+}
+
+int nblocks(size_t n) {
+    size_t b = (n + kB - 1) / kB;
+    return (int)(b < (size_t)kMaxBlocks ? b : (size_t)kMaxBlocks);
+}
+
+}  // namespace
+
+int dot_blocks(size_t n) { return nblocks(n); }
+
+template <typename T>
+hipError_t dot_partials_t(size_t n, int nrhs, const T *a, const T *b, double *part, int nblk,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(nblk, nrhs), dim3(kB), 0, st, n / 2, a, b, part);
+    return hipGetLastError();
+}
+template hipError_t dot_partials_t<double>(size_t, int, const double *, const double *, double *, int, hipStream_t);
+template hipError_t dot_partials_t<float>(size_t, int, const float *, const float *, double *, int, hipStream_t);
+
+hipError_t dot_finish(int nrhs, const double *part, int nblk, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_finish, dim3(nrhs), dim3(kB), 0, st, nblk, part, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t update_xr(size_t n, int nrhs, const double *alpha, T *x, const T *p, T *r, const T *q,
+                     double *part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_xr<T>, dim3(nblk, nrhs), dim3(kB), 0, st, n, alpha, x, p, r, q, part);
+    return hipGetLastError();
+}
+template hipError_t update_xr<double>(size_t, int, const double *, double *, const double *, double *, const double *, double *, int, hipStream_t);
+template hipError_t update_xr<float>(size_t, int, const double *, float *, const float *, float *, const float *, double *, int, hipStream_t);
+
+template <typename T>
+hipError_t update_p(size_t n, int nrhs, const double *beta, const T *z, T *p, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_p<T>, dim3(nblocks(n), nrhs), dim3(kB), 0, st, n, beta, z, p);
+    return hipGetLastError();
+}
+template hipError_t update_p<double>(size_t, int, const double *, const double *, double *, hipStream_t);
+template hipError_t update_p<float>(size_t, int, const double *, const float *, float *, hipStream_t);
+
+template <typename S, typename D>
+hipError_t convert(size_t n, int nrhs, const S *src, D *dst, const double *scale, hipStream_t st) {
+    hipLaunchKernelGGL((k_convert<S, D>), dim3(nblocks(n), nrhs), dim3(kB), 0, st, n, src, dst, scale);
+    return hipGetLastError();
+}
+template hipError_t convert<double, float>(size_t, int, const double *, float *, const double *, hipStream_t);
+template hipError_t convert<double, double>(size_t, int, const double *, double *, const double *, hipStream_t);
+
+template <typename S>
+hipError_t accum(size_t n, int nrhs, const S *e, double *x, const double *scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_accum<S>, dim3(nblocks(n), nrhs), dim3(kB), 0, st, n, e, x, scale);
+    return hipGetLastError();
+}
+template hipError_t accum<float>(size_t, int, const float *, double *, const double *, hipStream_t);
+template hipError_t accum<double>(size_t, int, const double *, double *, const double *, hipStream_t);
+
+hipError_t residual(size_t n, int nrhs, const double *b, const double *dx, double *r, double *part,
+                    int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual, dim3(nblk, nrhs), dim3(kB), 0, st, n, b, dx, r, part);
+    return hipGetLastError();
+}
+
+hipError_t cg_init(int nrhs, double *stv, const double *rr2, const double *zz2, double rel2, hipStream_t st) {
+    hipLaunchKernelGGL(k_init, dim3((nrhs + 63) / 64), dim3(64), 0, st, nrhs, stv, rr2, zz2, rel2);
+    return hipGetLastError();
+}
+hipError_t cg_alpha(int nrhs, double *stv, const double *qq2, hipStream_t st) {
+    hipLaunchKernelGGL(k_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, st, nrhs, stv, qq2);
+    return hipGetLastError();
+}
+hipError_t cg_beta(int nrhs, double *stv, const double *rr2, const double *zz2, hipStream_t st) {
+    hipLaunchKernelGGL(k_beta, dim3((nrhs + 63) / 64), dim3(64), 0, st, nrhs, stv, rr2, zz2);
+    return hipGetLastError();
+}
+
+}  // namespace bri

@@ -25,16 +25,6 @@ hipError_t pack_spinor(const Geom &g, int nrhs, const double2 *canon, void *soa,
 hipError_t unpack_spinor(const Geom &g, int nrhs, const void *soa, int p, double2 *canon,
                          hipStream_t st);
 
-// blas.hip: fields are nrhs blocks of n complex numbers each (n = 12 V)
-// convert between precisions: dst(p_dst) = src(p_src) * scale[rhs] (scale may be null)
-hipError_t convert_field(size_t n, int nrhs, const void *src, int ps, void *dst, int pd,
-                         const double *scale, hipStream_t st);
-// per-rhs partial sums of <a,b> (complex) and |b|^2 into part[rhs][nblk][3]; then finish
-hipError_t dot_partials(size_t n, int nrhs, const void *a, const void *b, int p, double *part,
-                        int nblk, hipStream_t st);
-hipError_t dot_finish(int nrhs, const double *part, int nblk, double *out3, hipStream_t st);
-int dot_blocks(size_t n);
-
 // grad.hip
 hipError_t grad_links_f64(const Geom &g, const double2 *U, const double2 *W40, const double2 *chi,
                           const double2 *psi, int nrhs, double2 *GW, double2 *gradU,

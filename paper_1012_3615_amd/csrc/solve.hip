@@ -1,19 +1,262 @@
-// CG on the normal equations (placeholder until the solver lands).
+// CG on the normal equations D^dag D x = D^dag b, with FP64 defect
+// correction around a lower-precision inner solve.
+//
+// Outer loop (FP64, W_hi):  r = b - D x;  stop when |r_i|/|b_i| <= tol for
+//   every right-hand side i;  otherwise solve D e = r/|r| approximately and
+//   set x += |r| e.
+// Inner loop (CGNE, FP32 storage with W_lo in FP32 or FP16, or FP64 with
+//   W_hi for the plain solver), per right-hand side i:
+//     z = D^dag r, p = z, zz = |z|^2
+//     repeat: q = D p; alpha = zz/|q|^2; e += alpha p; r -= alpha q;
+//             z = D^dag r; beta = |z|^2/zz; p = z + beta p
+//   until |r| <= inner_tol |r_0|.  All right-hand sides share each fused
+//   apply; a converged column is frozen on the device (alpha = 0).  The host
+//   reads the per-column state every check_every iterations.
+// The paper solves with BiCGstab (Sec. 6.4); CGNE is the solver of this
+// library, stopped on the FP64 true residual.
+#include <cmath>
+#include <vector>
+
 #include "abi_internal.h"
+#include "blas.h"
 #include "kernels.h"
+
+namespace bri {
+namespace {
+
+__global__ void k_zero(size_t n, float *p) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+__global__ void k_zero(size_t n, double *p) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+template <typename T>
+hipError_t zero(size_t n, T *p, hipStream_t st) {
+    size_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)b), dim3(256), 0, st, n, p);
+    return hipGetLastError();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t r_hi, dx_hi, e, r, p, q, z, part, red, stv, scale, unscale, total;
+};
+
+Layout layout(size_t n, int nrhs, size_t tbytes) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    const size_t hv = n * nrhs * sizeof(double), lv = n * nrhs * tbytes;
+    L.r_hi = take(hv);
+    L.dx_hi = take(hv);
+    L.e = take(lv);
+    L.r = take(lv);
+    L.p = take(lv);
+    L.q = take(lv);
+    L.z = take(lv);
+    L.part = take((size_t)nrhs * 1024 * 2 * sizeof(double));
+    L.red = take((size_t)3 * nrhs * 2 * sizeof(double));
+    L.stv = take((size_t)7 * nrhs * sizeof(double));
+    L.scale = take((size_t)nrhs * sizeof(double));
+    L.unscale = take((size_t)nrhs * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+struct Ctx {
+    bri_dims d;
+    Geom g;
+    size_t n;  // reals per rhs
+    int nrhs;
+    int noff;
+    double mass;
+    hipStream_t st;
+    char *w;
+    Layout L;
+};
+
+#define BRI_TRY(expr)                       \
+    do {                                    \
+        bri_status _s = (expr);             \
+        if (_s != BRI_OK) return _s;        \
+    } while (0)
+#define BRI_HIP(expr, what) BRI_TRY(hip_check((expr), what))
+
+template <typename T>
+bri_status norm2(const Ctx &c, const T *a, double *out2) {
+    const int nb = dot_blocks(c.n);
+    double *part = (double *)(c.w + c.L.part);
+    BRI_HIP(dot_partials_t<T>(c.n, c.nrhs, a, a, part, nb, c.st), "norm partials");
+    BRI_HIP(dot_finish(c.nrhs, part, nb, out2, c.st), "norm finish");
+    return BRI_OK;
+}
+
+bri_status fetch(const Ctx &c, const double *dev, double *host, size_t count) {
+    BRI_HIP(hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy to host");
+    BRI_HIP(hipStreamSynchronize(c.st), "synchronize");
+    return BRI_OK;
+}
+
+// inner CGNE on D e = r with e = 0 initially; r holds the right-hand side.
+template <typename T>
+bri_status inner_cgne(const Ctx &c, const void *W, bri_prec wp, bri_prec sp, double rel, int max_it,
+                      int check_every, int *iters, int *applies) {
+    T *e = (T *)(c.w + c.L.e), *r = (T *)(c.w + c.L.r), *p = (T *)(c.w + c.L.p);
+    T *q = (T *)(c.w + c.L.q), *z = (T *)(c.w + c.L.z);
+    double *part = (double *)(c.w + c.L.part);
+    double *qq2 = (double *)(c.w + c.L.red), *rr2 = qq2 + 2 * c.nrhs, *zz2 = rr2 + 2 * c.nrhs;
+    double *stv = (double *)(c.w + c.L.stv);
+    const int nb = dot_blocks(c.n);
+    const size_t bytes = c.n * c.nrhs * sizeof(T);
+
+    BRI_HIP(zero(c.n * c.nrhs, e, c.st), "zero");
+    BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, true));
+    ++*applies;
+    BRI_TRY(norm2<T>(c, r, rr2));
+    BRI_TRY(norm2<T>(c, z, zz2));
+    BRI_HIP(cg_init(c.nrhs, stv, rr2, zz2, rel * rel, c.st), "cg init");
+    BRI_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, c.st), "copy");
+    std::vector<double> hs(7 * c.nrhs);
+    for (int it = 1; it <= max_it; ++it) {
+        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, p, q, c.nrhs, c.st, false));
+        BRI_TRY(norm2<T>(c, q, qq2));
+        BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
+        BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
+        BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
+        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, true));
+        BRI_TRY(norm2<T>(c, z, zz2));
+        BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
+        BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
+        *applies += 2;
+        *iters = it;
+        if (it % check_every == 0 || it == max_it) {
+            BRI_TRY(fetch(c, stv, hs.data(), hs.size()));
+            bool any = false;
+            const int R = c.nrhs;
+            for (int i = 0; i < R; ++i) {
+                if (!std::isfinite(hs[2 * R + i]) || !std::isfinite(hs[i]))
+                    return fail(BRI_E_NOCONV, "non-finite residual in the inner solve (rhs %d)", i);
+                any = any || hs[5 * R + i] != 0.0;
+            }
+            if (!any) return BRI_OK;
+        }
+    }
+    return BRI_OK;  // the outer loop decides convergence
+}
+
+}  // namespace
+}  // namespace bri
 
 using namespace bri;
 
 extern "C" {
-size_t bri_solve_workspace_bytes(bri_dims, const bri_solve_params *, int32_t) { return 0; }
-bri_status bri_solve_cgne(bri_dims, const bri_solve_params *, const void *, const void *, double,
-                          const double *, double *, int32_t, void *, size_t, bri_solve_stats *,
-                          void *) {
+
+size_t bri_solve_workspace_bytes(bri_dims d, const bri_solve_params *p, int32_t nrhs) {
+    Geom g;
+    if (!p || !dims_ok(d, &g) || nrhs < 1 || nrhs > BRI_MAX_RHS) return 0;
+    const size_t tb = p->inner_prec == BRI_F64 ? sizeof(double) : sizeof(float);
+    return layout((size_t)24 * g.V, nrhs, tb).total;
+}
+
+bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_hi, const void *W_lo,
+                          double mass, const double *b, double *x, int32_t nrhs, void *work,
+                          size_t work_bytes, bri_solve_stats *stats, void *stream) {
     g_last_error.clear();
-    return fail(BRI_E_UNSUPPORTED, "solver not built");
+    Geom g;
+    if (!p || !stats) return fail(BRI_E_ARG, "null params or stats");
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (nrhs < 1 || nrhs > BRI_MAX_RHS) return fail(BRI_E_ARG, "nrhs must be in [1, %d]", BRI_MAX_RHS);
+    if (p->n_offsets != 40 && p->n_offsets != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
+    if (!(p->tol > 0.0) || p->max_iter < 1 || p->max_outer < 1 || p->check_every < 1)
+        return fail(BRI_E_ARG, "invalid solver parameters");
+    const bool mixed = p->inner_prec != BRI_F64;
+    if (mixed && p->inner_prec != BRI_F32 && p->inner_prec != BRI_F16)
+        return fail(BRI_E_ARG, "invalid inner precision");
+    if (mixed && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
+        return fail(BRI_E_ARG, "inner_tol must be in (0, 1)");
+    if (!aligned(W_hi) || !aligned(b) || !aligned(x) || (mixed && !aligned(W_lo)))
+        return fail(BRI_E_ARG, "null or misaligned pointer");
+    const size_t n = (size_t)24 * g.V;
+    const Layout L = layout(n, nrhs, mixed ? sizeof(float) : sizeof(double));
+    if (!aligned(work) || work_bytes < L.total)
+        return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", L.total);
+    const size_t vb = n * nrhs * sizeof(double);
+    if (overlap(b, vb, x, vb) || overlap(work, L.total, x, vb) || overlap(work, L.total, b, vb))
+        return fail(BRI_E_ARG, "b, x and the workspace must not overlap");
+
+    Ctx c{d, g, n, nrhs, p->n_offsets, mass, (hipStream_t)stream, (char *)work, L};
+    *stats = bri_solve_stats{};
+    double *r_hi = (double *)(c.w + L.r_hi), *dx = (double *)(c.w + L.dx_hi);
+    double *part = (double *)(c.w + L.part), *red = (double *)(c.w + L.red);
+    double *scale = (double *)(c.w + L.scale), *unscale = (double *)(c.w + L.unscale);
+    const int nb = dot_blocks(n);
+
+    std::vector<double> bb(2 * nrhs), rr(2 * nrhs), sc(nrhs), usc(nrhs);
+    BRI_TRY(norm2<double>(c, b, red));
+    BRI_TRY(fetch(c, red, bb.data(), bb.size()));
+    if (!p->use_initial_guess) BRI_HIP(zero(n * nrhs, x, c.st), "zero x");
+
+    int iters = 0, applies = 0;
+    bool converged = false;
+    for (int outer = 0;; ++outer) {
+        BRI_TRY(apply_impl(d, BRI_STORED, W_hi, BRI_F64, c.noff, BRI_F64, mass, x, dx, nrhs, c.st, false));
+        ++applies;
+        BRI_HIP(residual(n, nrhs, b, dx, r_hi, part, nb, c.st), "residual");
+        BRI_HIP(dot_finish(nrhs, part, nb, red, c.st), "residual finish");
+        BRI_TRY(fetch(c, red, rr.data(), rr.size()));
+        converged = true;
+        for (int i = 0; i < nrhs; ++i) {
+            const double rel = bb[2 * i] > 0.0 ? std::sqrt(rr[2 * i] / bb[2 * i]) : std::sqrt(rr[2 * i]);
+            stats->true_residual[i] = rel;
+            if (!std::isfinite(rel)) {
+                stats->outer = outer;
+                stats->iterations = iters;
+                stats->applies = applies;
+                return fail(BRI_E_NOCONV, "non-finite true residual (rhs %d)", i);
+            }
+            const bool done = rel <= p->tol;
+            converged = converged && done;
+            sc[i] = (done || rr[2 * i] == 0.0) ? 0.0 : 1.0 / std::sqrt(rr[2 * i]);
+            usc[i] = done ? 0.0 : std::sqrt(rr[2 * i]);
+        }
+        stats->outer = outer;
+        if (converged || outer >= p->max_outer || iters >= p->max_iter) break;
+        BRI_HIP(hipMemcpyAsync(scale, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c.st), "copy");
+        BRI_HIP(hipMemcpyAsync(unscale, usc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c.st), "copy");
+        int it = 0;
+        if (mixed) {
+            float *r_lo = (float *)(c.w + L.r);
+            BRI_HIP((convert<double, float>(n, nrhs, r_hi, r_lo, scale, c.st)), "convert");
+            BRI_TRY(inner_cgne<float>(c, W_lo, p->inner_prec, BRI_F32, p->inner_tol,
+                                      p->max_iter - iters, p->check_every, &it, &applies));
+            BRI_HIP(accum<float>(n, nrhs, (const float *)(c.w + L.e), x, unscale, c.st), "accumulate");
+        } else {
+            // plain FP64: aim the inner solve at the final tolerance of the worst column
+            double worst = 0.0;
+            for (int i = 0; i < nrhs; ++i)
+                if (sc[i] > 0.0) worst = std::fmax(worst, std::sqrt(rr[2 * i] / std::fmax(bb[2 * i], 1e-300)));
+            const double rel = worst > 0.0 ? std::fmin(0.5, 0.5 * p->tol / worst) : 0.5;
+            BRI_HIP((convert<double, double>(n, nrhs, r_hi, (double *)(c.w + L.r), scale, c.st)), "convert");
+            BRI_TRY(inner_cgne<double>(c, W_hi, BRI_F64, BRI_F64, rel, p->max_iter - iters,
+                                       p->check_every, &it, &applies));
+            BRI_HIP(accum<double>(n, nrhs, (const double *)(c.w + L.e), x, unscale, c.st), "accumulate");
+        }
+        iters += it;
+        stats->iterations = iters;
+    }
+    stats->iterations = iters;
+    stats->applies = applies;
+    stats->converged = converged ? 1 : 0;
+    if (!converged) return fail(BRI_E_NOCONV, "not converged after %d iterations, %d outer cycles", iters, stats->outer);
+    return BRI_OK;
 }
-bri_status bri_dot(bri_dims, int32_t, const double *, const double *, double *, void *) {
-    g_last_error.clear();
-    return fail(BRI_E_UNSUPPORTED, "dot not built");
-}
-}
+
+}  // extern "C"

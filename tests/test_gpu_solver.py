@@ -1,0 +1,144 @@
+"""GPU solver (CGNE, plain FP64 and FP64 defect correction around FP32/FP16
+inner solves) against the oracle: the true residual ||b - D x||/||b|| is
+recomputed with the oracle's own FP64 operator, and the solution is compared
+with a dense LU solve (4^4) or the free-field FFT propagator."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, free
+from tests.helpers import dev, log, soa_to_canon
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bri():
+    import paper_1012_3615_amd as m
+    return m
+
+
+def oracle_residual(u, x, b, mass):
+    return float(np.linalg.norm(b - dirac.apply(u, x, mass)) / np.linalg.norm(b))
+
+
+def solve(bri, dims, u, b, mass, inner, tol=1e-10, inner_tol=1e-4, noff=80, **kw):
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    W_hi = bri.bri_build_transporters(dims, U, bri.F64, noff)
+    W_lo = None if inner == bri.F64 else bri.bri_build_transporters(dims, U, inner, noff)
+    bs = bri.bri_pack_spinor(dims, dev(b), bri.F64)
+    p = bri.solve_params(tol=tol, inner_tol=inner_tol, n_offsets=noff, inner_prec=inner, **kw)
+    x, info = bri.bri_solve_cgne(dims, W_hi, bs, mass, p, W_lo=W_lo)
+    return soa_to_canon(dims, x), info
+
+
+@pytest.mark.parametrize("inner,noff", [(0, 80), (0, 40), (1, 80), (1, 40), (2, 80)])
+def test_cfg1_solve_matches_dense_lu(bri, inner, noff):
+    dims = (4, 4, 4, 4)
+    u = synth.gauge_links(dims, 0.3, 1001)
+    b = synth.gaussian_spinor(dims, 1003, nrhs=1)
+    log(f"solve 4^4 inner={inner} noff={noff}")
+    x, info = solve(bri, dims, u, b, 0.1, inner, noff=noff,
+                    inner_tol=1e-2 if inner == 2 else 1e-4)
+    assert info["converged"]
+    res = oracle_residual(u, x[0], b[0], 0.1)
+    assert res <= 1.05e-10, res
+    assert info["true_residual"][0] <= 1e-10
+    d = dirac.dense_matrix(u, 0.1)
+    xd = np.linalg.solve(d, b[0].reshape(-1)).reshape(b[0].shape)
+    assert np.linalg.norm(x[0] - xd) / np.linalg.norm(xd) < 1e-8
+
+
+def test_free_field_propagator(bri):
+    dims = (4, 4, 4, 8)
+    u = synth.unit_links(dims)
+    b = synth.point_sources(dims)[[0, 7]]
+    log("solve free field")
+    x, info = solve(bri, dims, u, b, 0.2, bri.F32)
+    for r in range(2):
+        xf = free.propagator_solve(dims, b[r], 0.2)
+        assert np.linalg.norm(x[r] - xf) / np.linalg.norm(xf) < 1e-8
+
+
+def test_12_point_sources_mixed(bri):
+    dims = (4, 4, 4, 6)
+    u = synth.gauge_links(dims, 0.3, 4001)
+    b = synth.point_sources(dims, site=(1, 0, 2, 3))
+    log("solve 12 point sources mixed FP32")
+    x, info = solve(bri, dims, u, b, 0.1, bri.F32)
+    assert info["converged"] and info["outer"] >= 1
+    for r in range(12):
+        assert oracle_residual(u, x[r], b[r], 0.1) <= 1.05e-10
+    # one column solved alone gives the same solution (x is unique)
+    x1, _ = solve(bri, dims, u, b[4:5], 0.1, bri.F32)
+    assert np.linalg.norm(x1[0] - x[4]) / np.linalg.norm(x[4]) < 1e-8
+
+
+def test_ragged_lattice_and_initial_guess(bri):
+    dims = (5, 3, 2, 6)
+    u = synth.gauge_links(dims, 0.4, 71)
+    b = synth.gaussian_spinor(dims, 72, nrhs=3)
+    log("solve ragged lattice, 3 rhs, initial guess")
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    W = bri.bri_build_transporters(dims, U, bri.F64, 80)
+    bs = bri.bri_pack_spinor(dims, dev(b), bri.F64)
+    p = bri.solve_params(tol=1e-11, inner_prec=bri.F64)
+    x, info = bri.bri_solve_cgne(dims, W, bs, 0.3, p)
+    xc = soa_to_canon(dims, x)
+    for r in range(3):
+        assert oracle_residual(u, xc[r], b[r], 0.3) <= 1.05e-11
+    # restart from the solution: converges at once
+    p2 = bri.solve_params(tol=1e-10, inner_prec=bri.F64, use_initial_guess=True)
+    x2, info2 = bri.bri_solve_cgne(dims, W, bs, 0.3, p2, x=x.clone())
+    assert info2["iterations"] == 0 and info2["converged"]
+
+
+def test_failure_paths_forced_from_host(bri):
+    dims = (4, 4, 4, 4)
+    u = synth.gauge_links(dims, 0.3, 1001)
+    b = synth.gaussian_spinor(dims, 1003, nrhs=1)
+    log("solver failure paths")
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    W = bri.bri_build_transporters(dims, U, bri.F64, 80)
+    bs = bri.bri_pack_spinor(dims, dev(b), bri.F64)
+    p = bri.solve_params(tol=1e-10, inner_prec=bri.F64, max_iter=1, max_outer=1)
+    x, info = bri.bri_solve_cgne(dims, W, bs, 0.1, p, raise_on_noconv=False)
+    assert info["status"] == -4 and not info["converged"]
+    assert 0 < info["true_residual"][0] < 1.0
+    bad = bs.clone()
+    bad[0, 3, 7, 0] = float("nan")
+    p = bri.solve_params(tol=1e-10, inner_prec=bri.F64)
+    with pytest.raises(bri.BriError) as e:
+        bri.bri_solve_cgne(dims, W, bad, 0.1, p)
+    assert e.value.status == -4
+    with pytest.raises(bri.BriError) as e:
+        bri.bri_solve_cgne(dims, W, bs, 0.1, bri.solve_params(tol=-1.0))
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("mass", [0.05, 0.5])
+def test_24x48_mixed_sampled_residual(bri, mass):
+    """Full cfg3 lattice (24^3 x 48, eps 0.4): mixed FP16-transporter solve to
+    1e-10; the residual is checked at sampled sites with the pointwise oracle
+    and in full with the library's own FP64 apply."""
+    dims = (24, 24, 24, 48)
+    u = _big_links(dims)
+    b = synth.gaussian_spinor(dims, 3002, nrhs=1)
+    log(f"solve 24^3x48 mixed FP16 m={mass}")
+    x, info = solve(bri, dims, u, b, mass, bri.F16, inner_tol=1e-2)
+    assert info["converged"] and max(info["true_residual"]) <= 1e-10
+    rng = np.random.default_rng(9)
+    sites = np.stack([rng.integers(0, L, 128) for L in dims], axis=1)
+    dx = dirac.apply_at(u, x[0], mass, sites)
+    bs = np.stack([b[0][t, z, y, xx] for xx, y, z, t in sites])
+    # a residual of 1e-10 over the lattice bounds the sampled one loosely
+    assert np.linalg.norm(bs - dx) / np.linalg.norm(bs) < 1e-8
+
+
+_big = {}
+
+
+def _big_links(dims):
+    if dims not in _big:
+        _big[dims] = synth.gauge_links(dims, 0.4, 3001)
+    return _big[dims]
