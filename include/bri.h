@@ -95,6 +95,9 @@ bri_status bri_pack_spinor(bri_dims d, int32_t nrhs, const double *psi_canon, vo
                            bri_prec p, void *stream);
 bri_status bri_unpack_spinor(bri_dims d, int32_t nrhs, const void *psi_soa, bri_prec p,
                              double *psi_canon, void *stream);
+/* SoA links (or a link-shaped gradient) back to the canonical layout. */
+bri_status bri_unpack_links(bri_dims d, const void *U_soa, bri_prec p, double *U_canon,
+                            void *stream);
 
 /* ---- transporter construction (Sec. 5.1) ---------------------------------
  * W(x, x+n) for n_offsets = 80 (all) or 40 (hermitian half) offsets, built in
@@ -146,6 +149,7 @@ int32_t bri_get_apply_kernel(bri_prec w_prec, bri_prec s_prec);
  * The paper inverts D for propagators (Sec. 6.4, BiCGstab to 1e-7); here the
  * solver is CGNE, stopped on the true relative residual ||b - D x||/||b||
  * computed in FP64 for every right-hand side.
+ * With dagger = 1 the same machinery solves D^dag x = b (D and D^dag swap).
  * inner_prec == BRI_F64: plain FP64 CGNE with W_hi (FP64 transporters).
  * inner_prec == BRI_F32 / BRI_F16: defect correction; the outer loop forms
  * r = b - D x in FP64 with W_hi, the inner CGNE solves D e = r in FP32
@@ -163,6 +167,7 @@ typedef struct {
     bri_prec inner_prec;     /* F64 (plain), F32 or F16 (transporters of W_lo)   */
     int32_t check_every;     /* iterations between host convergence checks (>=1) */
     int32_t use_initial_guess; /* 0: x is zeroed first                           */
+    int32_t dagger;          /* 1: solve D^dag x = b (CG on D D^dag) instead     */
 } bri_solve_params;
 
 #define BRI_MAX_RHS 64
@@ -182,15 +187,15 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
 
 /* ---- gradient with respect to the links -----------------------------------
  * For S = Re sum_rhs <chi, D psi> (FP64 SoA spinors, nrhs fields each) writes
- * gradU = dS/dRe U + i dS/dIm U in the FP64 SoA link layout, treating link
+ * gradU = scale * (dS/dRe U + i dS/dIm U) in the FP64 SoA link layout, treating link
  * entries as unconstrained complex numbers, through the path averaging of
  * the transporters.  The transporters are rebuilt from U inside the call
  * (not stored across calls).  The psi gradient is D^dag chi (bri_apply_dag).
  * work: bri_grad_workspace_bytes(d). */
 size_t bri_grad_workspace_bytes(bri_dims d);
 bri_status bri_grad_links(bri_dims d, const double *U_soa, const double *chi, const double *psi,
-                          int32_t nrhs, double *gradU, void *work, size_t work_bytes,
-                          void *stream);
+                          int32_t nrhs, double scale, double *gradU, void *work,
+                          size_t work_bytes, void *stream);
 
 #ifdef __cplusplus
 }

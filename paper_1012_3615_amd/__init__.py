@@ -7,7 +7,7 @@ not been built.
 from .api import (  # noqa: F401
     F64, F32, F16, STORED, RECOMPUTE, BriError, volume,
     spinor_empty, links_empty, transporters_empty,
-    bri_pack_links, bri_pack_spinor, bri_unpack_spinor,
+    bri_pack_links, bri_pack_spinor, bri_unpack_spinor, bri_unpack_links,
     bri_build_transporters, bri_apply, bri_apply_dag,
     bri_set_rhs_block, bri_get_rhs_block, bri_set_apply_kernel, bri_get_apply_kernel,
     solve_params, bri_solve_cgne, bri_grad_links,

@@ -22,6 +22,7 @@ class bri_solve_params(ctypes.Structure):
         ("inner_prec", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
         ("use_initial_guess", ctypes.c_int32),
+        ("dagger", ctypes.c_int32),
     ]
 
 
@@ -54,6 +55,7 @@ PROTOTYPES = {
     "bri_pack_links": (_i32, [_D, _vp, _vp, _i32, _vp]),
     "bri_pack_spinor": (_i32, [_D, _i32, _vp, _vp, _i32, _vp]),
     "bri_unpack_spinor": (_i32, [_D, _i32, _vp, _i32, _vp, _vp]),
+    "bri_unpack_links": (_i32, [_D, _vp, _i32, _vp, _vp]),
     "bri_build_workspace_bytes": (_sz, [_D, _i32, _i32]),
     "bri_build_transporters": (_i32, [_D, _vp, _vp, _i32, _i32, _vp, _sz, _vp]),
     "bri_apply": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
@@ -66,7 +68,7 @@ PROTOTYPES = {
     "bri_solve_cgne": (_i32, [_D, ctypes.POINTER(bri_solve_params), _vp, _vp, _dbl, _vp, _vp,
                               _i32, _vp, _sz, ctypes.POINTER(bri_solve_stats), _vp]),
     "bri_grad_workspace_bytes": (_sz, [_D]),
-    "bri_grad_links": (_i32, [_D, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "bri_grad_links": (_i32, [_D, _vp, _vp, _vp, _i32, _dbl, _vp, _vp, _sz, _vp]),
 }
 
 

@@ -123,6 +123,16 @@ def bri_unpack_spinor(dims, soa):
     return out
 
 
+def bri_unpack_links(dims, soa):
+    _need_cuda(soa)
+    _shape(soa, (4, 9, volume(dims), 2), "links")
+    lx, ly, lz, lt = dims
+    out = torch.empty((4, lt, lz, ly, lx, 3, 3), dtype=torch.complex128, device=soa.device)
+    _check(_lib_handle.bri_unpack_links(_dims(dims), _ptr(soa), prec_of(soa), _ptr(out), _stream()),
+           "bri_unpack_links")
+    return out
+
+
 # ------------------------------------------------------------------ transporters
 def bri_build_transporters(dims, U_soa, prec=F64, n_offsets=80, out=None):
     _need_cuda(U_soa)
@@ -192,18 +202,31 @@ def bri_get_apply_kernel(w_prec, s_prec):
 
 # ------------------------------------------------------------------ solver
 def solve_params(tol=1e-10, inner_tol=1e-4, max_iter=20000, max_outer=100, n_offsets=80,
-                 inner_prec=F64, check_every=8, use_initial_guess=False):
+                 inner_prec=F64, check_every=8, use_initial_guess=False, dagger=False):
     p = _lib.bri_solve_params()
     p.tol, p.inner_tol = tol, inner_tol
     p.max_iter, p.max_outer = max_iter, max_outer
     p.n_offsets, p.inner_prec = n_offsets, inner_prec
     p.check_every, p.use_initial_guess = check_every, int(bool(use_initial_guess))
+    p.dagger = int(bool(dagger))
     return p
 
 
 def bri_solve_cgne(dims, W_hi, b, mass, params, W_lo=None, x=None, raise_on_noconv=True):
-    """Solve D x = b (FP64 SoA spinors).  Returns (x, stats dict)."""
+    """Solve D x = b (or D^dag x = b with params.dagger) for FP64 SoA spinors.
+    Returns (x, stats dict)."""
     _need_cuda(W_hi, b, W_lo, x)
+    V = volume(dims)
+    _shape(b, (b.shape[0], 12, V, 2), "b")
+    _shape(W_hi, (params.n_offsets, 9, V, 2), "W_hi")
+    if W_lo is not None:
+        _shape(W_lo, (params.n_offsets, 9, V, 2), "W_lo")
+    if x is not None:
+        _shape(x, b.shape, "x")
+    if prec_of(b) != F64 or prec_of(W_hi) != F64:
+        raise ValueError("b and W_hi must be FP64")
+    if params.inner_prec != F64 and (W_lo is None or prec_of(W_lo) != params.inner_prec):
+        raise ValueError("W_lo must be given in the inner precision")
     nrhs = b.shape[0]
     if x is None:
         x = torch.zeros_like(b)
@@ -225,12 +248,19 @@ def bri_solve_cgne(dims, W_hi, b, mass, params, W_lo=None, x=None, raise_on_noco
 
 
 # ------------------------------------------------------------------ gradient
-def bri_grad_links(dims, U_soa, chi, psi):
-    """dS/dU (FP64 SoA links) for S = Re sum_rhs <chi, D psi>."""
+def bri_grad_links(dims, U_soa, chi, psi, scale=1.0):
+    """scale * dS/dU (FP64 SoA links) for S = Re sum_rhs <chi, D psi>."""
     _need_cuda(U_soa, chi, psi)
+    V = volume(dims)
+    _shape(U_soa, (4, 9, V, 2), "links")
+    _shape(chi, (chi.shape[0], 12, V, 2), "chi")
+    _shape(psi, chi.shape, "psi")
+    if prec_of(U_soa) != F64 or prec_of(chi) != F64 or prec_of(psi) != F64:
+        raise ValueError("the link gradient is FP64")
     nbytes = _lib_handle.bri_grad_workspace_bytes(_dims(dims))
     work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=U_soa.device)
     g = torch.empty_like(U_soa)
     _check(_lib_handle.bri_grad_links(_dims(dims), _ptr(U_soa), _ptr(chi), _ptr(psi), chi.shape[0],
-                                      _ptr(g), _ptr(work), nbytes, _stream()), "bri_grad_links")
+                                      float(scale), _ptr(g), _ptr(work), nbytes, _stream()),
+           "bri_grad_links")
     return g

@@ -165,6 +165,15 @@ bri_status bri_unpack_spinor(bri_dims d, int32_t nrhs, const void *soa, bri_prec
                      "unpack_spinor");
 }
 
+bri_status bri_unpack_links(bri_dims d, const void *soa, bri_prec p, double *U, void *stream) {
+    g_last_error.clear();
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (!prec_ok(p)) return fail(BRI_E_ARG, "invalid precision");
+    if (!aligned(U) || !aligned(soa)) return fail(BRI_E_ARG, "null or misaligned pointer");
+    return hip_check(unpack_links(g, soa, (int)p, (double2 *)U, (hipStream_t)stream), "unpack_links");
+}
+
 bri_status bri_build_transporters(bri_dims d, const double *U, void *W, bri_prec wp, int32_t noff,
                                   void *work, size_t work_bytes, void *stream) {
     g_last_error.clear();

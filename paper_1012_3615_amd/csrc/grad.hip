@@ -1,14 +1,262 @@
-// Link gradient (placeholder until the adjoint lands).
+// Gradient of S = Re sum_rhs <chi, D psi> with respect to the links, through
+// the path averaging of the transporters (FP64).  g = dS/dRe U + i dS/dIm U.
+//
+// 1. Per site x and offset n the transporter receives
+//      G_n(x) = sum_rhs sum_s (C(n)^dag chi(x))_s psi_s(x+n)^dag,
+//    C(n) = lambda_k + rho_k sum_mu n_mu gamma_mu (Hermitian, so C^dag = C).
+// 2. Every transporter obeys the same-site recursion used to build it,
+//      W(x,n) = (1/k) sum_{mu in supp n} W(x, n - s_mu mu) L(x,n,mu),
+//      L = U_mu(x+n-mu) (s_mu = +1) or U_mu(x+n)^dag (s_mu = -1),
+//    so in reverse hop order (4 -> 2) each thread adds
+//      G_{n - s_mu mu}(x) += (1/k) G_n(x) L^dag
+//    to the lower-level transporters of its own site.
+// 3. Each link collects, without atomics, the product-rule terms of every
+//    (x, n, mu) whose last step runs over it:
+//      s_mu = +1: U_mu(y), y = x+n-mu:  += (1/k) W(x, n-mu)^dag G_n(x)
+//      s_mu = -1: U_mu(y), y = x+n:     += (1/k) G_n(x)^dag W(x, n+mu)
+//    with W(x, 0) = 1.
 #include "abi_internal.h"
+#include "apply_kernels.h"
 #include "kernels.h"
+
+namespace bri {
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ int plane80_rt(int i) { return i < 40 ? i : i - 1; }
+
+__device__ __forceinline__ void ldm(const double2 *p, size_t V, cx<double> m[3][3]) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e / 3][e % 3] = ldc<double>(p + e * V);
+}
+__device__ __forceinline__ void stm(double2 *p, size_t V, const cx<double> m[3][3]) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) st(p + e * V, m[e / 3][e % 3]);
+}
+
+// step 1: direct transporter gradients for all 80 offsets
+__global__ __launch_bounds__(kB) void k_grad_direct(Geom g, const double2 *__restrict__ chi,
+                                                    const double2 *__restrict__ psi, int nrhs,
+                                                    double2 *__restrict__ G80) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= g.V) return;
+    const size_t V = (size_t)g.V;
+    int c[4];
+    coords(g, site, c);
+    const Nbr nb = make_nbr(g, c);
+#pragma unroll 1
+    for (int j = 0; j < 80; ++j) {
+        const int i = j < 40 ? j : j + 1;
+        const int nx = i % 3 - 1, ny = (i / 3) % 3 - 1, nz = (i / 9) % 3 - 1, nt = i / 27 - 1;
+        const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
+        const double lam = lam_rt<double>(k), rho = rho_rt<double>(k);
+        const int y = nbr_rt(nb, nx, ny, nz, nt);
+        cx<double> G[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) G[a][b] = cmake(0.0, 0.0);
+        for (int r = 0; r < nrhs; ++r) {
+            const double2 *xc = chi + (size_t)r * 12 * V + site;
+            const double2 *ps = psi + (size_t)r * 12 * V + y;
+            cx<double> ch[4][3], pp[4][3];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    ch[s][a] = ldc<double>(xc + (3 * s + a) * V);
+                    pp[s][a] = ldc<double>(ps + (3 * s + a) * V);
+                }
+            // phi = C(n) chi, colour by colour
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cx<double> in4[4] = {ch[0][a], ch[1][a], ch[2][a], ch[3][a]};
+                cx<double> o[4] = {cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0)};
+                spin_accum_rt(o, in4, lam, rho, nx, ny, nz, nt);
+                // G[a][b] += sum_s phi_s[a] conj(psi_s[b])
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) G[a][b] = cmac(G[a][b], o[s], cconj(pp[s][b]));
+            }
+        }
+        stm(G80 + (size_t)j * 9 * V + site, V, G);
+    }
+}
+
+// step 2: reverse hop-order recursion at each site, levels 4 -> 2
+__global__ __launch_bounds__(kB) void k_grad_recursion(Geom g, const double2 *__restrict__ U,
+                                                       double2 *__restrict__ G80) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= g.V) return;
+    const size_t V = (size_t)g.V;
+    int c[4];
+    coords(g, site, c);
+    const Nbr nb = make_nbr(g, c);
+#pragma unroll 1
+    for (int k = 4; k >= 2; --k) {
+#pragma unroll 1
+        for (int i = 0; i < 81; ++i) {
+            const int n[4] = {i % 3 - 1, (i / 3) % 3 - 1, (i / 9) % 3 - 1, i / 27 - 1};
+            if ((n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0) != k) continue;
+            cx<double> Gn[3][3];
+            ldm(G80 + (size_t)plane80_rt(i) * 9 * V + site, V, Gn);
+            const double inv = 1.0 / k;
+#pragma unroll 1
+            for (int mu = 0; mu < 4; ++mu) {
+                if (n[mu] == 0) continue;
+                int d[4] = {n[0], n[1], n[2], n[3]};
+                if (n[mu] > 0) d[mu] -= 1;  // link base site x+n-mu (forward) or x+n (backward)
+                const int yl = nbr_rt(nb, d[0], d[1], d[2], d[3]);
+                cx<double> l[3][3];
+                const double2 *pu = U + (size_t)mu * 9 * V + yl;
+#pragma unroll
+                for (int e = 0; e < 9; ++e) {
+                    cx<double> v = ldc<double>(pu + e * V);
+                    if (n[mu] > 0) l[e / 3][e % 3] = v; else l[e % 3][e / 3] = cconj(v);
+                }
+                // G_P += inv * Gn * l^dag
+                int m[4] = {n[0], n[1], n[2], n[3]};
+                m[mu] = 0;
+                const int im = (m[0] + 1) + 3 * (m[1] + 1) + 9 * (m[2] + 1) + 27 * (m[3] + 1);
+                double2 *pg = G80 + (size_t)plane80_rt(im) * 9 * V + site;
+                cx<double> P[3][3];
+                ldm(pg, V, P);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        cx<double> t = cmake(0.0, 0.0);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) t = cmac(t, Gn[a][q], cconj(l[b][q]));
+                        P[a][b] = caxpy(inv, t, P[a][b]);
+                    }
+                stm(pg, V, P);
+            }
+        }
+    }
+}
+
+// step 3: gather onto the links
+__global__ __launch_bounds__(kB) void k_grad_gather(Geom g, const double2 *__restrict__ W80,
+                                                    const double2 *__restrict__ G80,
+                                                    double2 *__restrict__ gradU, double scale) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= g.V) return;
+    const int mu = blockIdx.y;
+    const size_t V = (size_t)g.V;
+    int c[4];
+    coords(g, site, c);
+    cx<double> acc[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a][b] = cmake(0.0, 0.0);
+#pragma unroll 1
+    for (int i = 0; i < 81; ++i) {
+        const int n[4] = {i % 3 - 1, (i / 3) % 3 - 1, (i / 9) % 3 - 1, i / 27 - 1};
+        if (n[mu] == 0) continue;
+        const int k = (n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0);
+        // site x of the transporter: y = x+n-mu (forward) or y = x+n (backward)
+        int xc[4];
+        for (int nu = 0; nu < 4; ++nu) {
+            int v = c[nu] - n[nu] + ((nu == mu && n[mu] > 0) ? 1 : 0);
+            const int L = g.L[nu];
+            v = (v % L + L) % L;
+            xc[nu] = v;
+        }
+        const int x = xc[0] + g.L[0] * (xc[1] + g.L[1] * (xc[2] + g.L[2] * xc[3]));
+        cx<double> G[3][3], P[3][3];
+        ldm(G80 + (size_t)plane80_rt(i) * 9 * V + x, V, G);
+        int m[4] = {n[0], n[1], n[2], n[3]};
+        m[mu] = 0;
+        const int im = (m[0] + 1) + 3 * (m[1] + 1) + 9 * (m[2] + 1) + 27 * (m[3] + 1);
+        if (im == 40) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) P[a][b] = cmake(a == b ? 1.0 : 0.0, 0.0);
+        } else {
+            ldm(W80 + (size_t)plane80_rt(im) * 9 * V + x, V, P);
+        }
+        const double inv = 1.0 / k;
+        if (n[mu] > 0) {
+            // acc += inv * P^dag G
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    cx<double> t = cmake(0.0, 0.0);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) t = cmac(t, cconj(P[q][a]), G[q][b]);
+                    acc[a][b] = caxpy(inv, t, acc[a][b]);
+                }
+        } else {
+            // acc += inv * G^dag P
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    cx<double> t = cmake(0.0, 0.0);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) t = cmac(t, cconj(G[q][a]), P[q][b]);
+                    acc[a][b] = caxpy(inv, t, acc[a][b]);
+                }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a][b] = cscale(scale, acc[a][b]);
+    stm(gradU + (size_t)mu * 9 * V + site, V, acc);
+}
+
+}  // namespace
+}  // namespace bri
 
 using namespace bri;
 
 extern "C" {
-size_t bri_grad_workspace_bytes(bri_dims) { return 0; }
-bri_status bri_grad_links(bri_dims, const double *, const double *, const double *, int32_t,
-                          double *, void *, size_t, void *) {
+
+size_t bri_grad_workspace_bytes(bri_dims d) {
+    Geom g;
+    if (!dims_ok(d, &g)) return 0;
+    return (size_t)g.V * 9 * 16 * (80 + 40 + 80);
+}
+
+bri_status bri_grad_links(bri_dims d, const double *U, const double *chi, const double *psi,
+                          int32_t nrhs, double scale, double *gradU, void *work, size_t work_bytes,
+                          void *stream) {
     g_last_error.clear();
-    return fail(BRI_E_UNSUPPORTED, "gradient not built");
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
+    if (!aligned(U) || !aligned(chi) || !aligned(psi) || !aligned(gradU))
+        return fail(BRI_E_ARG, "null or misaligned pointer");
+    const size_t need = bri_grad_workspace_bytes(d);
+    if (!aligned(work) || work_bytes < need)
+        return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", need);
+    const size_t lb = (size_t)g.V * 36 * 16;
+    if (overlap(gradU, lb, U, lb) || overlap(work, need, gradU, lb))
+        return fail(BRI_E_ARG, "gradU overlaps its inputs or the workspace");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t V = g.V;
+    double2 *W80 = (double2 *)work;
+    double2 *W40 = W80 + (size_t)80 * 9 * V;
+    double2 *G80 = W40 + (size_t)40 * 9 * V;
+    // transporters rebuilt from the links (not kept from the forward pass)
+    bri_status s = hip_check(build_w40_f64(g, (const double2 *)U, W40, st), "build transporters");
+    if (s != BRI_OK) return s;
+    s = hip_check(convert_w40(g, W40, W80, 0, 80, st), "expand transporters");
+    if (s != BRI_OK) return s;
+    dim3 grid((g.V + kB - 1) / kB);
+    hipLaunchKernelGGL(k_grad_direct, grid, dim3(kB), 0, st, g, (const double2 *)chi,
+                       (const double2 *)psi, nrhs, G80);
+    hipLaunchKernelGGL(k_grad_recursion, grid, dim3(kB), 0, st, g, (const double2 *)U, G80);
+    hipLaunchKernelGGL(k_grad_gather, dim3(grid.x, 4), dim3(kB), 0, st, g, (const double2 *)W80,
+                       (const double2 *)G80, (double2 *)gradU, scale);
+    return hip_check(hipGetLastError(), "gradient kernels");
 }
-}
+
+}  // extern "C"

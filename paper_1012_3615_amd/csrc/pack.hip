@@ -57,6 +57,19 @@ hipError_t pack_spinor(const Geom &g, int nrhs, const double2 *canon, void *soa,
     return pack_any<12>(g, nrhs, canon, soa, p, st);
 }
 
+hipError_t unpack_links(const Geom &g, const void *soa, int p, double2 *canon, hipStream_t st) {
+    dim3 grid((g.V + kBlock - 1) / kBlock, 4);
+    if (p == 0)
+        hipLaunchKernelGGL((k_unpack<double2, 9>), grid, dim3(kBlock), 0, st, g.V, (const double2 *)soa, canon);
+    else if (p == 1)
+        hipLaunchKernelGGL((k_unpack<float2, 9>), grid, dim3(kBlock), 0, st, g.V, (const float2 *)soa, canon);
+    else if (p == 2)
+        hipLaunchKernelGGL((k_unpack<__half2, 9>), grid, dim3(kBlock), 0, st, g.V, (const __half2 *)soa, canon);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t unpack_spinor(const Geom &g, int nrhs, const void *soa, int p, double2 *canon,
                          hipStream_t st) {
     dim3 grid((g.V + kBlock - 1) / kBlock, nrhs);

@@ -78,6 +78,7 @@ struct Ctx {
     int nrhs;
     int noff;
     double mass;
+    bool dag;  // solve D^dag x = b
     hipStream_t st;
     char *w;
     Layout L;
@@ -118,7 +119,7 @@ bri_status inner_cgne(const Ctx &c, const void *W, bri_prec wp, bri_prec sp, dou
     const size_t bytes = c.n * c.nrhs * sizeof(T);
 
     BRI_HIP(zero(c.n * c.nrhs, e, c.st), "zero");
-    BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, true));
+    BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
     ++*applies;
     BRI_TRY(norm2<T>(c, r, rr2));
     BRI_TRY(norm2<T>(c, z, zz2));
@@ -126,12 +127,12 @@ bri_status inner_cgne(const Ctx &c, const void *W, bri_prec wp, bri_prec sp, dou
     BRI_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, c.st), "copy");
     std::vector<double> hs(7 * c.nrhs);
     for (int it = 1; it <= max_it; ++it) {
-        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, p, q, c.nrhs, c.st, false));
+        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, p, q, c.nrhs, c.st, c.dag));
         BRI_TRY(norm2<T>(c, q, qq2));
         BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
         BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
         BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
-        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, true));
+        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
         BRI_TRY(norm2<T>(c, z, zz2));
         BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
         BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
@@ -192,7 +193,7 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     if (overlap(b, vb, x, vb) || overlap(work, L.total, x, vb) || overlap(work, L.total, b, vb))
         return fail(BRI_E_ARG, "b, x and the workspace must not overlap");
 
-    Ctx c{d, g, n, nrhs, p->n_offsets, mass, (hipStream_t)stream, (char *)work, L};
+    Ctx c{d, g, n, nrhs, p->n_offsets, mass, p->dagger != 0, (hipStream_t)stream, (char *)work, L};
     *stats = bri_solve_stats{};
     double *r_hi = (double *)(c.w + L.r_hi), *dx = (double *)(c.w + L.dx_hi);
     double *part = (double *)(c.w + L.part), *red = (double *)(c.w + L.red);
@@ -207,7 +208,7 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     int iters = 0, applies = 0;
     bool converged = false;
     for (int outer = 0;; ++outer) {
-        BRI_TRY(apply_impl(d, BRI_STORED, W_hi, BRI_F64, c.noff, BRI_F64, mass, x, dx, nrhs, c.st, false));
+        BRI_TRY(apply_impl(d, BRI_STORED, W_hi, BRI_F64, c.noff, BRI_F64, mass, x, dx, nrhs, c.st, c.dag));
         ++applies;
         BRI_HIP(residual(n, nrhs, b, dx, r_hi, part, nb, c.st), "residual");
         BRI_HIP(dot_finish(nrhs, part, nb, red, c.st), "residual finish");

@@ -1,0 +1,180 @@
+"""GPU gradients (FP64) of S = Re<chi, D psi> and S2 = phi^dag (D^dag D)^{-1} phi
+with respect to the links (through the path averaging) and psi/phi, against
+the oracle's explicit path-enumeration adjoint and central finite
+differences (h = 1e-6).
+
+Tolerances: AD vs oracle gradient 1e-12 (relative, 2-norm); AD vs central
+differences 1e-6 relative to the largest gradient entry (FD truncation is
+O(h^2) and the rounding of S is ~1e-16 |S| / h)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, grad as ograd
+from tests.helpers import log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def ag():
+    from paper_1012_3615_amd import autograd
+    return autograd
+
+
+def _setup(dims, seed, eps=0.3):
+    u = synth.gauge_links(dims, eps, seed)
+    chi = synth.gaussian_spinor(dims, seed + 2, nrhs=1)
+    psi = synth.gaussian_spinor(dims, seed + 3, nrhs=1)
+    return u, chi, psi
+
+
+def _ad_S(torch, ag, u, chi, psi, mass):
+    U = torch.from_numpy(u).cuda().requires_grad_(True)
+    P = torch.from_numpy(psi).cuda().requires_grad_(True)
+    C = torch.from_numpy(chi).cuda()
+    out = ag.apply(U, P, mass)
+    S = torch.real(torch.vdot(C.reshape(-1), out.reshape(-1)))
+    S.backward()
+    return float(S), U.grad.cpu().numpy(), P.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 2, 4, 2), (8, 8, 8, 8)])
+def test_link_and_psi_gradient_match_oracle(torch, ag, dims):
+    mass = 0.1
+    u, chi, psi = _setup(dims, 5001)
+    log(f"grad vs oracle dims={dims}")
+    S, gU, gP = _ad_S(torch, ag, u, chi, psi, mass)
+    assert abs(S - ograd.action(u, chi[0], psi[0], mass)) <= 1e-12 * abs(S)
+    assert rel(gU, ograd.grad_links(u, chi[0], psi[0], mass)) < 1e-12
+    assert rel(gP[0], ograd.grad_psi(u, chi[0], mass)) < 1e-12
+
+
+def test_central_differences_8_4(torch, ag):
+    """cfg5 (8^4): AD against central differences of the GPU's own FP64 S."""
+    import paper_1012_3615_amd as bri
+    dims, mass, h = (8, 8, 8, 8), 0.1, 1e-6
+    u, chi, psi = _setup(dims, 5001)
+    log("grad FD 8^4")
+    S0, gU, gP = _ad_S(torch, ag, u, chi, psi, mass)
+    C = torch.from_numpy(chi).cuda()
+
+    def S_of(uu, pp):
+        out = ag.apply(torch.from_numpy(uu).cuda(), torch.from_numpy(pp).cuda(), mass)
+        return float(torch.real(torch.vdot(C.reshape(-1), out.reshape(-1))))
+
+    rng = np.random.default_rng(3)
+    gmax = np.abs(gU).max()
+    for _ in range(6):
+        idx = tuple(int(rng.integers(s)) for s in u.shape)
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            up, um = u.copy(), u.copy()
+            up[idx] += unit * h
+            um[idx] -= unit * h
+            fd = (S_of(up, psi) - S_of(um, psi)) / (2 * h)
+            an = gU[idx].real if part == "re" else gU[idx].imag
+            assert abs(fd - an) <= 1e-6 * gmax, (idx, part, fd, an)
+    pmax = np.abs(gP).max()
+    for _ in range(4):
+        idx = tuple(int(rng.integers(s)) for s in psi.shape)
+        pp, pm = psi.copy(), psi.copy()
+        pp[idx] += h
+        pm[idx] -= h
+        fd = (S_of(u, pp) - S_of(u, pm)) / (2 * h)
+        assert abs(fd - gP[idx].real) <= 1e-6 * pmax
+
+
+def test_local_differences_16_32(torch, ag):
+    """cfg5 (16^3 x 32): AD against central differences of S restricted to the
+    sites whose transporters contain the perturbed link, evaluated with the
+    pointwise oracle and summed with math.fsum."""
+    dims, mass, h = (16, 16, 16, 32), 0.1, 1e-6
+    u, chi, psi = _setup(dims, 5101)
+    log("grad local FD 16^3x32")
+    _, gU, _ = _ad_S(torch, ag, u, chi, psi, mass)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        mu = int(rng.integers(4))
+        y = [int(rng.integers(L)) for L in dims]
+        a, b = int(rng.integers(3)), int(rng.integers(3))
+        off = np.array(np.meshgrid(*[np.arange(-2, 3)] * 4, indexing="ij")).reshape(4, -1).T
+        sites = (np.array(y)[None, :] + off) % np.array(dims)[None, :]
+        idx = (mu, y[3], y[2], y[1], y[0], a, b)
+
+        def S_local(uu):
+            out = dirac.apply_at(uu, psi[0], mass, sites)
+            ch = np.stack([chi[0][t, z, yy, x] for x, yy, z, t in sites])
+            return math.fsum(np.real(np.conj(ch) * out).ravel())
+
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            up, um = u.copy(), u.copy()
+            up[idx] += unit * h
+            um[idx] -= unit * h
+            fd = (S_local(up) - S_local(um)) / (2 * h)
+            an = gU[idx].real if part == "re" else gU[idx].imag
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (idx, part, fd, an)
+
+
+def test_normal_solve_gradient_matches_oracle(torch, ag):
+    """S2 = phi^dag (D^dag D)^{-1} phi at 4^4: AD against the oracle's
+    closed form dS2/dU = grad of Re<-2 D X, D X> in the second factor
+    (X from a dense solve) and dS2/dphi = 2 X."""
+    dims, mass = (4, 4, 4, 4), 0.2
+    u = synth.gauge_links(dims, 0.3, 5201)
+    phi = synth.gaussian_spinor(dims, 5202, nrhs=1)
+    log("S2 gradient vs oracle 4^4")
+    U = torch.from_numpy(u).cuda().requires_grad_(True)
+    F = torch.from_numpy(phi).cuda().requires_grad_(True)
+    X = ag.normal_solve(U, F, mass)
+    S2 = torch.real(torch.vdot(F.reshape(-1), X.reshape(-1)))
+    S2.backward()
+    d = dirac.dense_matrix(u, mass)
+    Xo = np.linalg.solve(d.conj().T @ d, phi[0].reshape(-1)).reshape(phi[0].shape)
+    assert rel(X.detach().cpu().numpy()[0], Xo) < 1e-10
+    gU_o = ograd.grad_links(u, -2.0 * dirac.apply(u, Xo, mass), Xo, mass)
+    assert rel(U.grad.cpu().numpy(), gU_o) < 1e-9
+    assert rel(F.grad.cpu().numpy()[0], 2.0 * Xo) < 1e-10
+
+
+def test_normal_solve_central_differences_8_4(torch, ag):
+    dims, mass, h = (8, 8, 8, 8), 0.2, 1e-6
+    u = synth.gauge_links(dims, 0.3, 5301)
+    phi = synth.gaussian_spinor(dims, 5302, nrhs=1)
+    log("S2 gradient FD 8^4")
+    U = torch.from_numpy(u).cuda().requires_grad_(True)
+    F = torch.from_numpy(phi).cuda()
+    S2 = torch.real(torch.vdot(F.reshape(-1), ag.normal_solve(U, F, mass).reshape(-1)))
+    S2.backward()
+    gU = U.grad.cpu().numpy()
+
+    def S2_of(uu):
+        X = ag.normal_solve(torch.from_numpy(uu).cuda(), F, mass, tol=1e-14)
+        return float(torch.real(torch.vdot(F.reshape(-1), X.reshape(-1))))
+
+    rng = np.random.default_rng(6)
+    gmax = np.abs(gU).max()
+    for _ in range(3):
+        idx = tuple(int(rng.integers(s)) for s in u.shape)
+        up, um = u.copy(), u.copy()
+        up[idx] += h
+        um[idx] -= h
+        fd = (S2_of(up) - S2_of(um)) / (2 * h)
+        assert abs(fd - gU[idx].real) <= 1e-5 * gmax, (idx, fd, gU[idx].real)
+
+
+def test_torch_gradcheck_tiny(torch, ag):
+    dims = (2, 2, 2, 2)
+    u, chi, psi = _setup(dims, 5401, eps=0.5)
+    log("gradcheck 2^4")
+    U = torch.from_numpy(u).cuda().requires_grad_(True)
+    P = torch.from_numpy(psi).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, b: ag.apply(a, b, 0.3), (U, P), eps=1e-6,
+                                    atol=1e-7, rtol=1e-6, fast_mode=True)
