@@ -31,7 +31,8 @@ EPS = 0.3
 SEED_U, SEED_PSI = 4001, 4002
 HBM_PEAK_GBS = 8000.0
 FLOPS_PER_SITE = 35376           # nominal flops per site and right-hand side
-KERNEL_SOURCES = ["paper_1012_3615_amd/csrc/apply_kernels.h", "paper_1012_3615_amd/csrc/common.h"]
+KERNEL_SOURCES = ["paper_1012_3615_amd/csrc/common.h", "paper_1012_3615_amd/csrc/stencil.h",
+                  "paper_1012_3615_amd/csrc/apply_tiled.h"]
 PMC_FILE = os.path.join(ROOT, "profiles", "apply_stored_f32_w80_32x32x32x64.pmc.json")
 
 
@@ -101,6 +102,40 @@ def traffic_from_profile(launch_bytes_alg):
     return p.get("hbm_bytes_per_launch")
 
 
+def solve_comparison(torch, bri, U64, dev, tol=1e-10):
+    """Propagator solve: the 12 spin-colour point sources at the origin, to a
+    true FP64 relative residual of 1e-10, (a) batched mixed precision (FP32
+    inner CGNE with FP32 transporters, FP64 defect correction) and (b) twelve
+    plain FP64 CGNE solves one after the other."""
+    import numpy as np
+    import synth
+    src = synth.point_sources(DIMS)
+    b = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F64)
+    del src
+    W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
+    W32 = bri.bri_build_transporters(DIMS, U64, bri.F32, 80)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = bri.solve_params(tol=tol, inner_prec=bri.F32, inner_tol=1e-3, check_every=4)
+    _, im = bri.bri_solve_cgne(DIMS, W64, b, MASS, p, W_lo=W32)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    iters, worst = 0, 0.0
+    p = bri.solve_params(tol=tol, inner_prec=bri.F64, check_every=4)
+    for r in range(12):
+        _, ip = bri.bri_solve_cgne(DIMS, W64, b[r:r + 1].contiguous(), MASS, p)
+        iters += ip["iterations"]
+        worst = max(worst, ip["true_residual"][0])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    return {"tol": tol, "mixed_s": t_mixed, "plain_fp64_12x_s": t_plain,
+            "ratio_mixed_over_plain": t_mixed / t_plain,
+            "mixed_iterations": im["iterations"], "mixed_outer": im["outer"],
+            "mixed_max_true_residual": max(im["true_residual"][:12]),
+            "plain_iterations_total": iters, "plain_max_true_residual": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +143,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -177,7 +213,7 @@ def main():
                    "spinor": f"gaussian, seed {SEED_PSI}"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(launch_bytes),
-                     "kernel": "k_apply_stored<80,float2,float2,float,false,1>",
+                     "kernel": "k_apply_tiled<80,float2,float2,float,false,32,8>",
                      "alg_bytes_per_site": bps, "alg_bytes_per_launch": launch_bytes,
                      "kernel_ms": per_ms},
         "gflops": FLOPS_PER_SITE * V / (per_ms * 1e-3) / 1e9,
@@ -228,6 +264,9 @@ def main():
         del x12
         torch.cuda.empty_cache()
         res["extras"] = extras
+
+    if not a.no_extras and not a.no_solve:
+        res["solve_12rhs"] = solve_comparison(torch, bri, U64, dev)
 
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(u, psi[0])

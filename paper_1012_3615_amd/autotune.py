@@ -1,0 +1,105 @@
+"""Autotuner for the stored-transporter apply.
+
+For a lattice, precision pair, transporter store and number of right-hand
+sides it times every launch configuration the library offers (LDS tiles of
+32x8 or 16x8 sites with 1-4 right-hand sides per thread, tiles of 16x16 or
+64x4 sites with one, or the register-blocked gather form with 1, 2, 3, 4, 6
+or 12 right-hand sides per thread)
+with HIP events on the current stream, installs the fastest through
+bri_set_apply_kernel / bri_set_rhs_block, and caches the choice in a JSON
+file keyed by (extents, w_prec, s_prec, n_offsets, nrhs, device name).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import api
+
+CACHE = os.environ.get("BRI_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "bri_autotune.json"))
+TILES = {2: "tile32x8", 3: "tile16x16", 4: "tile64x4", 5: "tile16x8"}
+RBLKS = (1, 2, 3, 4, 6, 12)
+
+
+def _key(dims, w_prec, s_prec, n_offsets, nrhs):
+    dev = torch.cuda.get_device_name()
+    return f"{'x'.join(map(str, dims))}|w{w_prec}|s{s_prec}|o{n_offsets}|r{nrhs}|{dev}"
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(c):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        with open(CACHE, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+    except OSError:
+        pass
+
+
+def candidates(dims, nrhs, s_prec=api.F32):
+    out = []
+    for code, name in TILES.items():
+        tx = {2: 32, 3: 16, 4: 64, 5: 16}[code]
+        if tx > 2 * dims[0]:
+            continue
+        for r in (1, 2, 3, 4):
+            if r > 1 and (code in (3, 4) or r > nrhs):
+                continue
+            if r > 2 and code == 2 and s_prec == api.F64:
+                continue  # the LDS of a 32x8 tile holds at most 2 FP64 spinors
+            out.append((f"{name}_r{r}", code, r))
+    for r in RBLKS:
+        if r <= nrhs:
+            out.append((f"gather_r{r}", 0, r))
+    return out
+
+
+def _install(w_prec, s_prec, kernel, rblk):
+    api.bri_set_apply_kernel(w_prec, s_prec, kernel)
+    api.bri_set_rhs_block(w_prec, s_prec, rblk)
+
+
+def tune(dims, W, psi, mass=0.1, reps=5, use_cache=True):
+    """Pick and install the fastest configuration for apply(W, psi).
+    Returns (name, ms, table of all timings)."""
+    w_prec, s_prec = api.prec_of(W), api.prec_of(psi)
+    n_off, nrhs = W.shape[0], psi.shape[0]
+    key = _key(dims, w_prec, s_prec, n_off, nrhs)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        e = cache[key]
+        _install(w_prec, s_prec, e["kernel"], e["rblk"])
+        return e["name"], e["ms"], e.get("table", {})
+    out = torch.empty_like(psi)
+    table = {}
+    best = None
+    for name, kernel, rblk in candidates(dims, nrhs, s_prec):
+        _install(w_prec, s_prec, kernel, rblk)
+        api.bri_apply(dims, W, psi, mass, out=out)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            api.bri_apply(dims, W, psi, mass, out=out)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        table[name] = ms
+        if best is None or ms < best[3]:
+            best = (name, kernel, rblk, ms)
+    name, kernel, rblk, ms = best
+    _install(w_prec, s_prec, kernel, rblk)
+    cache[key] = {"name": name, "kernel": kernel, "rblk": rblk, "ms": ms, "table": table}
+    if use_cache:
+        _store(cache)
+    return name, ms, table

@@ -52,12 +52,13 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 namespace {
 // rhs-per-thread setting of the fused multi-RHS apply, per (w_prec, s_prec)
-int g_rhs_block[3][3] = {{2, 2, 2}, {4, 4, 4}, {4, 4, 4}};
+int g_rhs_block[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};
 // apply kernel per (w_prec, s_prec): 0 = register-blocked gather, 1 = LDS tiles
+// with the tile shape chosen from Lx, 2..5 = LDS tiles 32x8, 16x16, 64x4, 16x8
 int g_apply_kernel[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};
 
 int snap_rblk(int want, int nrhs) {
-    static const int allowed[] = {12, 6, 4, 3, 2, 1};
+    static const int allowed[] = {12, 6, 4, 3, 2, 1};  // snapped down to one of these
     if (want > nrhs) want = nrhs;
     for (int a : allowed)
         if (a <= want) return a;
@@ -83,9 +84,16 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
         const bool combo = (wp == BRI_F64 && sp == BRI_F64) || (wp == BRI_F32 && sp == BRI_F32) ||
                            (wp == BRI_F16 && (sp == BRI_F32 || sp == BRI_F16));
         if (!combo) return fail(BRI_E_UNSUPPORTED, "unsupported (w_prec, s_prec) combination");
+        const int kernel = g_apply_kernel[wp][sp];
         int rblk = nrhs == 1 ? 1 : snap_rblk(g_rhs_block[wp][sp], nrhs);
-        if (rblk == 1 && g_apply_kernel[wp][sp] == 1) rblk = 0;  // 0 selects the LDS-tiled kernel
-        return hip_check(apply_stored(g, noff, (int)wp, (int)sp, W, in, out, diag, nrhs, rblk, dag, st),
+        if (kernel >= 1) {
+            // LDS tiles hold 1..4 right-hand sides per thread (shapes 16x16, 64x4: 1)
+            if (kernel == 3 || kernel == 4) rblk = 1;
+            if (rblk > 4) rblk = 4;
+            if (wp == BRI_F64 && rblk > 2 && kernel != 5) rblk = 2;  // LDS of a 32x8 tile
+        }
+        return hip_check(apply_stored(g, noff, (int)wp, (int)sp, kernel, rblk, W, in, out, diag, nrhs,
+                                      dag, st),
                          "apply (stored)");
     }
     if (v == BRI_RECOMPUTE) {
@@ -213,8 +221,7 @@ bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W, bri_prec wp, 
 bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
     g_last_error.clear();
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    static const int defaults[3] = {2, 4, 4};
-    if (r == 0) r = defaults[wp];
+    if (r == 0) r = 1;
     if (r != 1 && r != 2 && r != 3 && r != 4 && r != 6 && r != 12)
         return fail(BRI_E_ARG, "rhs_per_thread must be 1, 2, 3, 4, 6 or 12");
     g_rhs_block[wp][sp] = r;
@@ -224,7 +231,7 @@ bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
 bri_status bri_set_apply_kernel(bri_prec wp, bri_prec sp, int32_t kernel) {
     g_last_error.clear();
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    if (kernel != 0 && kernel != 1) return fail(BRI_E_ARG, "kernel must be 0 (gather) or 1 (LDS tiles)");
+    if (kernel < 0 || kernel > 5) return fail(BRI_E_ARG, "kernel must be in 0..5");
     g_apply_kernel[wp][sp] = kernel;
     return BRI_OK;
 }

@@ -1,0 +1,149 @@
+// Stored-transporter apply with LDS-staged spinor layers (one right-hand
+// side per thread).
+#pragma once
+#include "stencil.h"
+
+namespace bri {
+// ---------------------------------------------------------------- stored W, LDS tiles
+// One workgroup = a TX x TY tile of the (x, y) plane at fixed (z, t); one
+// thread per site.  The 81-point neighbourhood is visited as 9 layers
+// (n_z, n_t); for each layer the workgroup stages psi on the tile plus a
+// one-site halo in x and y into LDS (every neighbour read of the layer then
+// comes from LDS), and the 9 (n_x, n_y) offsets of the layer are applied.
+// Transporters are streamed from HBM with non-temporal loads (80-offset
+// store: every element is read exactly once).  With R > 1 each thread holds R
+// right-hand sides (rhs R*blockIdx.y .. +R-1): the LDS holds R layers and
+// every transporter load serves all R.
+template <int TX, int TY>
+struct TileShape {
+    static constexpr int HX = TX + 2, HY = TY + 2, NH = HX * HY, NT = TX * TY;
+    static constexpr int LOADS = (NH + NT - 1) / NT;  // halo sites per thread
+};
+
+template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R>
+__global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty,
+                                                        const WS *__restrict__ W,
+                                                        const SS *__restrict__ in,
+                                                        SS *__restrict__ out, A diag, int nrhs) {
+    using TS = TileShape<TX, TY>;
+    __shared__ SS lds[R][12][TS::NH];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const size_t V = (size_t)g.V;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const int bx = blk % ntx;
+    int r = blk / ntx;
+    const int by = r % nty;
+    r /= nty;
+    const int z = r % Lz, t = r / Lz;
+    const int r0 = blockIdx.y * R;
+    const int nr = nrhs - r0 < R ? nrhs - r0 : R;  // right-hand sides of this block
+    in += (size_t)r0 * 12 * V;
+    out += (size_t)r0 * 12 * V;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = bx * TX + tx, y = by * TY + ty;
+    const bool valid = x < Lx && y < Ly;
+    const int site = valid ? x + Lx * (y + Ly * (z + Lz * t)) : 0;
+
+    // (x, y) part of the global index of the halo sites this thread stages
+    int hxy[TS::LOADS];
+#pragma unroll
+    for (int k = 0; k < TS::LOADS; ++k) {
+        const int q = threadIdx.x + k * TS::NT;
+        const int hx = q % TS::HX - 1, hy = q / TS::HX - 1;
+        const int gx = (bx * TX + hx + Lx) % Lx, gy = (by * TY + hy + Ly) % Ly;
+        hxy[k] = q < TS::NH ? gx + Lx * gy : -1;
+    }
+    const int plane = Lx * Ly;
+
+    cx<A> acc[R][4][3];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[r][s][a] = cmake<A>(0, 0);
+
+#pragma unroll 1
+    for (int layer = 0; layer < 9; ++layer) {
+        const int nz = layer % 3 - 1, nt = layer / 3 - 1;
+        const int zz = (z + nz + Lz) % Lz, tt = (t + nt + Lt) % Lt;
+        const int zt = plane * (zz + Lz * tt);
+        __syncthreads();  // previous layer fully consumed
+#pragma unroll
+        for (int k = 0; k < TS::LOADS; ++k) {
+            if (hxy[k] >= 0) {
+                const int q = threadIdx.x + k * TS::NT;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (R > 1 && r >= nr) break;
+                    const SS *src = in + (size_t)r * 12 * V + zt + hxy[k];
+#pragma unroll
+                    for (int p = 0; p < 12; ++p) lds[r][p][q] = src[p * V];
+                }
+            }
+        }
+        __syncthreads();
+        if (valid) {
+#pragma unroll 1
+            for (int o = 0; o < 9; ++o) {
+                const int nx = o % 3 - 1, ny = o / 3 - 1;
+                const int qn = (ty + 1 + ny) * TS::HX + tx + 1 + nx;
+                if ((nx | ny | nz | nt) == 0) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (R > 1 && r >= nr) break;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+#pragma unroll
+                            for (int a = 0; a < 3; ++a)
+                                acc[r][s][a] = caxpy(diag, ldc<A>(&lds[r][3 * s + a][qn]), acc[r][s][a]);
+                    }
+                    continue;
+                }
+                const int i = (nx + 1) + 3 * (ny + 1) + 9 * (nz + 1) + 27 * (nt + 1);
+                const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
+                const A lam = lam_rt<A>(k);
+                const A rho = DAG ? -rho_rt<A>(k) : rho_rt<A>(k);
+                cx<A> w[3][3];
+                if (NOFF == 80) {
+                    const WS *p = W + (size_t)(i < 40 ? i : i - 1) * 9 * V + site;
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ldnt<A>(p + e * V);
+                } else if (i > 40) {
+                    const WS *p = W + (size_t)(i - 41) * 9 * V + site;
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + e * V);
+                } else {
+                    // W(x, x+n) = W(x+n, x)^dag, stored at x+n under offset -n
+                    const int yn = ((x + nx + Lx) % Lx) + Lx * (((y + ny + Ly) % Ly) + Ly * (zz + Lz * tt));
+                    const WS *p = W + (size_t)(39 - i) * 9 * V + yn;
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) w[e % 3][e / 3] = cconj(ld<A>(p + e * V));
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (R > 1 && r >= nr) break;
+                    cx<A> psi[4][3];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) psi[s][b] = ldc<A>(&lds[r][3 * s + b][qn]);
+                    colour_spin_accum(acc[r], w, psi, lam, rho, nx, ny, nz, nt);
+                }
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (R > 1 && r >= nr) break;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) st(out + (size_t)r * 12 * V + (3 * s + a) * V + site, acc[r][s][a]);
+        }
+    }
+}
+
+
+}  // namespace bri

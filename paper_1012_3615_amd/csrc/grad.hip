@@ -16,7 +16,7 @@
 //      s_mu = -1: U_mu(y), y = x+n:     += (1/k) G_n(x)^dag W(x, n+mu)
 //    with W(x, 0) = 1.
 #include "abi_internal.h"
-#include "apply_kernels.h"
+#include "stencil.h"
 #include "kernels.h"
 
 namespace bri {

@@ -9,8 +9,17 @@
 namespace bri {
 
 // apply.hip
-hipError_t apply_stored(const Geom &g, int noff, int wp, int sp, const void *W, const void *in,
-                        void *out, double diag, int nrhs, int rblk, bool dag, hipStream_t st);
+hipError_t apply_stored(const Geom &g, int noff, int wp, int sp, int kernel, int rblk, const void *W,
+                        const void *in, void *out, double diag, int nrhs, bool dag, hipStream_t st);
+#define BRI_DECL_APPLY(tag)                                                                        \
+    hipError_t apply_stored_##tag(const Geom &g, int noff, int kernel, int rblk, const void *W,    \
+                                  const void *in, void *out, double diag, int nrhs, bool dag,     \
+                                  hipStream_t st);
+BRI_DECL_APPLY(f64)
+BRI_DECL_APPLY(f32)
+BRI_DECL_APPLY(f16)
+BRI_DECL_APPLY(f16h)
+#undef BRI_DECL_APPLY
 hipError_t apply_recompute(const Geom &g, int up, int sp, const void *U, const void *in, void *out,
                            double diag, int nrhs, bool dag, hipStream_t st);
 

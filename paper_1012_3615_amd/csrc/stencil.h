@@ -1,0 +1,95 @@
+// Device helpers of the Brillouin stencil (Eq. def_pref, c_SW = 0):
+//   (D psi)(x) = (lambda_0 + m) psi(x)
+//              + sum_{n != 0} [lambda_k + rho_k sum_mu n_mu gamma_mu] W(x,x+n) psi(x+n)
+// The loops over the offsets run at run time; an offset is the same for every
+// lane of a wavefront, so the tests on its components are uniform (scalar)
+// branches and the spin structure costs exactly the non-zero gamma terms.
+#pragma once
+#include "common.h"
+
+namespace bri {
+
+
+// Contribution of one offset, one colour:
+//   out += lam * chi + sum_{mu: n_mu != 0} (rho n_mu) gamma_mu chi
+// in the chiral basis
+//   gamma_x chi = (-i chi3, -i chi2,  i chi1,  i chi0)
+//   gamma_y chi = (  -chi3,    chi2,    chi1,  -chi0)
+//   gamma_z chi = (-i chi2,  i chi3,  i chi0, -i chi1)
+//   gamma_t chi = (   chi2,    chi3,    chi0,   chi1)
+template <typename T>
+__device__ __forceinline__ void spin_accum_rt(cx<T> o[4], const cx<T> c[4], T lam, T rho, int nx,
+                                              int ny, int nz, int nt) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) o[s] = caxpy(lam, c[s], o[s]);
+    if (nx != 0) {
+        const T r = nx > 0 ? rho : -rho;  // (-i) z = (z.im, -z.re)
+        o[0].re = fma(r, c[3].im, o[0].re); o[0].im = fma(-r, c[3].re, o[0].im);
+        o[1].re = fma(r, c[2].im, o[1].re); o[1].im = fma(-r, c[2].re, o[1].im);
+        o[2].re = fma(-r, c[1].im, o[2].re); o[2].im = fma(r, c[1].re, o[2].im);
+        o[3].re = fma(-r, c[0].im, o[3].re); o[3].im = fma(r, c[0].re, o[3].im);
+    }
+    if (ny != 0) {
+        const T r = ny > 0 ? rho : -rho;
+        o[0].re = fma(-r, c[3].re, o[0].re); o[0].im = fma(-r, c[3].im, o[0].im);
+        o[1].re = fma(r, c[2].re, o[1].re); o[1].im = fma(r, c[2].im, o[1].im);
+        o[2].re = fma(r, c[1].re, o[2].re); o[2].im = fma(r, c[1].im, o[2].im);
+        o[3].re = fma(-r, c[0].re, o[3].re); o[3].im = fma(-r, c[0].im, o[3].im);
+    }
+    if (nz != 0) {
+        const T r = nz > 0 ? rho : -rho;
+        o[0].re = fma(r, c[2].im, o[0].re); o[0].im = fma(-r, c[2].re, o[0].im);
+        o[1].re = fma(-r, c[3].im, o[1].re); o[1].im = fma(r, c[3].re, o[1].im);
+        o[2].re = fma(-r, c[0].im, o[2].re); o[2].im = fma(r, c[0].re, o[2].im);
+        o[3].re = fma(r, c[1].im, o[3].re); o[3].im = fma(-r, c[1].re, o[3].im);
+    }
+    if (nt != 0) {
+        const T r = nt > 0 ? rho : -rho;
+        o[0] = caxpy(r, c[2], o[0]);
+        o[1] = caxpy(r, c[3], o[1]);
+        o[2] = caxpy(r, c[0], o[2]);
+        o[3] = caxpy(r, c[1], o[3]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T lam_rt(int k) {
+    return k == 1 ? (T)(-8.0 / 128.0) : k == 2 ? (T)(-4.0 / 128.0) : k == 3 ? (T)(-2.0 / 128.0) : (T)(-1.0 / 128.0);
+}
+template <typename T>
+__device__ __forceinline__ T rho_rt(int k) {
+    return k == 1 ? (T)(64.0 / 432.0) : k == 2 ? (T)(16.0 / 432.0) : k == 3 ? (T)(4.0 / 432.0) : (T)(1.0 / 432.0);
+}
+
+// neighbour site for a run-time offset (each n_mu in {-1,0,1})
+__device__ __forceinline__ int nbr_rt(const Nbr &nb, int nx, int ny, int nz, int nt) {
+    const int a = nx < 0 ? nb.part[0][0] : nx > 0 ? nb.part[0][2] : nb.part[0][1];
+    const int b = ny < 0 ? nb.part[1][0] : ny > 0 ? nb.part[1][2] : nb.part[1][1];
+    const int c = nz < 0 ? nb.part[2][0] : nz > 0 ? nb.part[2][2] : nb.part[2][1];
+    const int d = nt < 0 ? nb.part[3][0] : nt > 0 ? nb.part[3][2] : nb.part[3][1];
+    return a + b + c + d;
+}
+
+// chi[s] = w[a][.] psi[s][.] for colour row a, all spins, and accumulate
+template <typename A>
+__device__ __forceinline__ void colour_spin_accum(cx<A> acc[4][3], const cx<A> w[3][3],
+                                                  const cx<A> psi[4][3], A lam, A rho, int nx,
+                                                  int ny, int nz, int nt) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<A> chi[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            cx<A> t = cmul(w[a][0], psi[s][0]);
+            t = cmac(t, w[a][1], psi[s][1]);
+            chi[s] = cmac(t, w[a][2], psi[s][2]);
+        }
+        cx<A> o[4] = {acc[0][a], acc[1][a], acc[2][a], acc[3][a]};
+        spin_accum_rt(o, chi, lam, rho, nx, ny, nz, nt);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s][a] = o[s];
+    }
+}
+
+
+}  // namespace bri
