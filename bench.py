@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 FLOPS_PER_SITE = 35376           # nominal flops per site and right-hand side
 KERNEL_SOURCES = ["paper_1012_3615_amd/csrc/common.h", "paper_1012_3615_amd/csrc/stencil.h",
                   "paper_1012_3615_amd/csrc/apply_tiled.h"]
-PMC_FILE = os.path.join(ROOT, "profiles", "apply_stored_f32_w80_32x32x32x64.pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "apply_tiled_f32_w80_32x32x32x64.pmc.json")
 
 
 def bytes_per_site(n_off, wbytes, sbytes, nrhs=1):
@@ -213,7 +213,7 @@ def main():
                    "spinor": f"gaussian, seed {SEED_PSI}"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(launch_bytes),
-                     "kernel": "k_apply_tiled<80,float2,float2,float,false,32,8>",
+                     "kernel": "k_apply_tiled<80,float2,float2,float,false,32,8,1>",
                      "alg_bytes_per_site": bps, "alg_bytes_per_launch": launch_bytes,
                      "kernel_ms": per_ms},
         "gflops": FLOPS_PER_SITE * V / (per_ms * 1e-3) / 1e9,
@@ -255,13 +255,21 @@ def main():
         bench_variant("recompute_f32", U32, x32, 0, 0, 0, variant=bri.RECOMPUTE, steps=5)
         bench_variant("recompute_f64", U64, x64, 0, 0, 0, variant=bri.RECOMPUTE, steps=5)
         del U32, x64
-        # 12 spin-colour point sources in one fused launch
+        # 12 spin-colour point sources in one fused launch, configuration from the autotuner
+        from paper_1012_3615_amd import autotune
         src = synth.point_sources(DIMS)
         x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F32)
-        del src
+        name, _, table = autotune.tune(DIMS, W, x12, MASS, reps=3)
         bench_variant("stored_w80_f32_12rhs", W, x12, 80, 8, 8, steps=5)
-        extras["stored_w80_f32_12rhs"]["rhs_per_thread"] = bri.bri_get_rhs_block(bri.F32, bri.F32)
+        extras["stored_w80_f32_12rhs"]["autotuned"] = name
+        extras["stored_w80_f32_12rhs"]["autotune_ms"] = table
         del x12
+        x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F64)
+        W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
+        name, _, _ = autotune.tune(DIMS, W64, x12, MASS, reps=2)
+        bench_variant("stored_w80_f64_12rhs", W64, x12, 80, 16, 16, steps=3)
+        extras["stored_w80_f64_12rhs"]["autotuned"] = name
+        del x12, W64, src
         torch.cuda.empty_cache()
         res["extras"] = extras
 
