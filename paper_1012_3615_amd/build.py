@@ -5,7 +5,9 @@
 
 Each .hip source is compiled to an object with hipcc, then linked into
 paper_1012_3615_amd/libbri.so.  Packed FP32 instructions are disabled for
-device code (-packed-fp32-ops).
+device code (-packed-fp32-ops).  Floating-point contraction is off: the
+kernels write every fused multiply-add explicitly, so all launch
+configurations of an operation round identically.
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ SOURCES = ["abi.hip", "apply.hip", "apply_f64.hip", "apply_f32.hip", "apply_f16.
            "build.hip", "pack.hip", "blas.hip", "solve.hip", "grad.hip"]
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(HERE, "..", "include"),

@@ -20,7 +20,7 @@ struct TileShape {
     static constexpr int LOADS = (NH + NT - 1) / NT;  // halo sites per thread
 };
 
-template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R>
+template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R, bool PF = false>
 __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty,
                                                         const WS *__restrict__ W,
                                                         const SS *__restrict__ in,
@@ -63,6 +63,33 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[r][s][a] = cmake<A>(0, 0);
 
+    // transporter of offset (nx, ny) of layer (lz, lt) = (layer % 3, layer / 3)
+    auto load_w = [&](int layer, int nx, int ny, cx<A> (&w)[3][3]) {
+        const int lnz = layer % 3 - 1, lnt = layer / 3 - 1;
+        const int i = (nx + 1) + 3 * (ny + 1) + 9 * (lnz + 1) + 27 * (lnt + 1);
+        if (NOFF == 80) {
+            const WS *p = W + (size_t)(i < 40 ? i : i - 1) * 9 * V + site;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ldnt<A>(p + e * V);
+        } else if (i > 40) {
+            const WS *p = W + (size_t)(i - 41) * 9 * V + site;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + e * V);
+        } else {
+            // W(x, x+n) = W(x+n, x)^dag, stored at x+n under offset -n
+            const int zn = (z + lnz + Lz) % Lz, tn = (t + lnt + Lt) % Lt;
+            const int yn = ((x + nx + Lx) % Lx) + Lx * (((y + ny + Ly) % Ly) + Ly * (zn + Lz * tn));
+            const WS *p = W + (size_t)(39 - i) * 9 * V + yn;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) w[e % 3][e / 3] = cconj(ld<A>(p + e * V));
+        }
+    };
+    // with PF the next transporter of the layer is in flight during the
+    // arithmetic of the current one (not across layers: vector-memory loads
+    // return in order, and an HBM load issued before the layer's LDS fill
+    // would delay the fill's L2 hits)
+    cx<A> wn[3][3];
+
 #pragma unroll 1
     for (int layer = 0; layer < 9; ++layer) {
         const int nz = layer % 3 - 1, nt = layer / 3 - 1;
@@ -83,12 +110,14 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
             }
         }
         __syncthreads();
+        const bool centre = (nz | nt) == 0;  // this layer holds n = 0 at o = 4
         if (valid) {
+            if (PF) load_w(layer, -1, -1, wn);
 #pragma unroll 1
             for (int o = 0; o < 9; ++o) {
                 const int nx = o % 3 - 1, ny = o / 3 - 1;
                 const int qn = (ty + 1 + ny) * TS::HX + tx + 1 + nx;
-                if ((nx | ny | nz | nt) == 0) {
+                if (centre && o == 4) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         if (R > 1 && r >= nr) break;
@@ -100,25 +129,21 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                     }
                     continue;
                 }
-                const int i = (nx + 1) + 3 * (ny + 1) + 9 * (nz + 1) + 27 * (nt + 1);
                 const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
                 const A lam = lam_rt<A>(k);
                 const A rho = DAG ? -rho_rt<A>(k) : rho_rt<A>(k);
                 cx<A> w[3][3];
-                if (NOFF == 80) {
-                    const WS *p = W + (size_t)(i < 40 ? i : i - 1) * 9 * V + site;
+                if (PF) {
 #pragma unroll
-                    for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ldnt<A>(p + e * V);
-                } else if (i > 40) {
-                    const WS *p = W + (size_t)(i - 41) * 9 * V + site;
+                    for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + e * V);
+                        for (int b = 0; b < 3; ++b) w[a][b] = wn[a][b];
+                    // issue the next transporter before this one's arithmetic
+                    int o2 = o + 1;
+                    if (centre && o2 == 4) ++o2;
+                    if (o2 < 9) load_w(layer, o2 % 3 - 1, o2 / 3 - 1, wn);
                 } else {
-                    // W(x, x+n) = W(x+n, x)^dag, stored at x+n under offset -n
-                    const int yn = ((x + nx + Lx) % Lx) + Lx * (((y + ny + Ly) % Ly) + Ly * (zz + Lz * tt));
-                    const WS *p = W + (size_t)(39 - i) * 9 * V + yn;
-#pragma unroll
-                    for (int e = 0; e < 9; ++e) w[e % 3][e / 3] = cconj(ld<A>(p + e * V));
+                    load_w(layer, nx, ny, w);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {

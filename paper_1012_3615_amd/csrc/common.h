@@ -25,10 +25,11 @@ template <typename T>
 __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
-// a*b
+// a*b (explicit fused multiply-adds: the library is built with
+// -ffp-contract=off so every kernel configuration rounds identically)
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
 }
 // acc + a*b
 template <typename T>

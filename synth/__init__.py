@@ -24,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "lattice_shape", "volume", "gauge_links", "unit_links", "gaussian_spinor",
+    "lattice_shape", "volume", "gauge_links", "gauge_links_device", "unit_links", "gaussian_spinor",
     "point_sources", "random_su3_field", "gauge_transform_links",
     "gauge_transform_spinor", "plane_wave", "mean_plaquette_trace",
 ]
@@ -68,6 +68,31 @@ def gauge_links(dims, eps, seed):
     shp = lattice_shape(dims)
     n = 4 * volume(dims)
     return _expi_traceless_hermitian(rng, n, float(eps)).reshape((4,) + shp + (3, 3))
+
+
+def gauge_links_device(dims, eps, seed, device="cuda"):
+    """Same distribution as ``gauge_links`` drawn with torch's seeded generator
+    on ``device`` (for lattices where the host eigendecompositions would take
+    minutes).  U = exp(i eps H) by ``torch.linalg.matrix_exp``.  Returns a
+    complex128 tensor [4, Lt, Lz, Ly, Lx, 3, 3]; not bit-identical to
+    ``gauge_links`` for the same seed."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    shp = (4,) + lattice_shape(dims) + (3, 3)
+    out = torch.empty(shp, dtype=torch.complex128, device=device)
+    flat = out.view(-1, 3, 3)
+    eye = torch.eye(3, dtype=torch.complex128, device=device)
+    for lo in range(0, flat.shape[0], _CHUNK):
+        hi = min(flat.shape[0], lo + _CHUNK)
+        re = torch.randn((hi - lo, 3, 3), generator=gen, dtype=torch.float64, device=device)
+        im = torch.randn((hi - lo, 3, 3), generator=gen, dtype=torch.float64, device=device)
+        g = torch.complex(re, im)
+        h = 0.5 * (g + g.conj().transpose(-1, -2))
+        tr = torch.diagonal(h, dim1=-2, dim2=-1).sum(-1).real / 3.0
+        h = h - tr[:, None, None] * eye
+        flat[lo:hi] = torch.linalg.matrix_exp(1j * eps * h)
+    return out
 
 
 def unit_links(dims):
