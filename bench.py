@@ -136,6 +136,34 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
             "plain_iterations_total": iters, "plain_max_true_residual": worst}
 
 
+def gradient_timing(torch, bri, dev):
+    """FP64 link gradient of S = Re<chi, D psi> at 16^3 x 32 (the gradient
+    lattice): forward = transporter build + apply, backward = transporter
+    build + apply_dag (psi gradient) + bri_grad_links (which rebuilds the
+    transporters itself)."""
+    import synth
+    import numpy as np
+    dims = (16, 16, 16, 32)
+    u = synth.gauge_links(dims, EPS, 5101)
+    U = bri.bri_pack_links(dims, torch.from_numpy(u).to(dev), bri.F64)
+    chi = bri.bri_pack_spinor(dims, torch.from_numpy(synth.gaussian_spinor(dims, 5103, 1)).to(dev), bri.F64)
+    psi = bri.bri_pack_spinor(dims, torch.from_numpy(synth.gaussian_spinor(dims, 5104, 1)).to(dev), bri.F64)
+
+    def fwd():
+        W = bri.bri_build_transporters(dims, U, bri.F64, 80)
+        return bri.bri_apply(dims, W, psi, MASS)
+
+    def bwd():
+        W = bri.bri_build_transporters(dims, U, bri.F64, 80)
+        bri.bri_apply_dag(dims, W, chi, MASS)
+        return bri.bri_grad_links(dims, U, chi, psi)
+
+    _, pf = timed_launches(torch, fwd, 5, 2)
+    _, pb = timed_launches(torch, bwd, 5, 2)
+    tf, tb = float(np.mean(pf)), float(np.mean(pb))
+    return {"forward_ms": tf, "backward_ms": tb, "backward_over_forward": tb / tf}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +303,8 @@ def main():
 
     if not a.no_extras and not a.no_solve:
         res["solve_12rhs"] = solve_comparison(torch, bri, U64, dev)
+    if not a.no_extras:
+        res["gradient_16x16x16x32"] = gradient_timing(torch, bri, dev)
 
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(u, psi[0])

@@ -19,7 +19,8 @@ hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double
         return hipErrorInvalidValue;
     } else {
         const int ntx = (g.L[0] + TX - 1) / TX, nty = (g.L[1] + TY - 1) / TY;
-        dim3 grid(ntx * nty * g.L[2] * g.L[3], (nrhs + R - 1) / R);
+        // one-dimensional grid, right-hand-side group fastest (see k_apply_tiled)
+        dim3 grid(ntx * nty * g.L[2] * g.L[3] * ((nrhs + R - 1) / R));
         if (dag)
             hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF>), grid, dim3(TX * TY),
                                0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out, (A)diag,

@@ -11,9 +11,9 @@ namespace bri {
 // one-site halo in x and y into LDS (every neighbour read of the layer then
 // comes from LDS), and the 9 (n_x, n_y) offsets of the layer are applied.
 // Transporters are streamed from HBM with non-temporal loads (80-offset
-// store: every element is read exactly once).  With R > 1 each thread holds R
-// right-hand sides (rhs R*blockIdx.y .. +R-1): the LDS holds R layers and
-// every transporter load serves all R.
+// store: every element is read exactly once per right-hand-side group).  With
+// R > 1 each thread holds R right-hand sides: the LDS holds R layers and every
+// transporter load serves all R.
 template <int TX, int TY>
 struct TileShape {
     static constexpr int HX = TX + 2, HY = TY + 2, NH = HX * HY, NT = TX * TY;
@@ -27,7 +27,13 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                                                         SS *__restrict__ out, A diag, int nrhs) {
     using TS = TileShape<TX, TY>;
     __shared__ SS lds[R][12][TS::NH];
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    // one-dimensional grid: tile-major, right-hand-side group fastest, so the
+    // groups of a tile run back to back on one XCD and share its transporters
+    // through that XCD's L2
+    const int ngrp = (nrhs + R - 1) / R;
+    const int lin = xcd_block(blockIdx.x, gridDim.x);
+    const int grp = lin % ngrp;
+    const int blk = lin / ngrp;
     const size_t V = (size_t)g.V;
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
     const int bx = blk % ntx;
@@ -35,7 +41,7 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
     const int by = r % nty;
     r /= nty;
     const int z = r % Lz, t = r / Lz;
-    const int r0 = blockIdx.y * R;
+    const int r0 = grp * R;
     const int nr = nrhs - r0 < R ? nrhs - r0 : R;  // right-hand sides of this block
     in += (size_t)r0 * 12 * V;
     out += (size_t)r0 * 12 * V;

@@ -35,9 +35,4 @@ hipError_t unpack_spinor(const Geom &g, int nrhs, const void *soa, int p, double
                          hipStream_t st);
 hipError_t unpack_links(const Geom &g, const void *soa, int p, double2 *canon, hipStream_t st);
 
-// grad.hip
-hipError_t grad_links_f64(const Geom &g, const double2 *U, const double2 *W40, const double2 *chi,
-                          const double2 *psi, int nrhs, double2 *GW, double2 *gradU,
-                          hipStream_t st);
-
 }  // namespace bri

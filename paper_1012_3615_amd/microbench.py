@@ -1,0 +1,116 @@
+"""Microbenchmark of the operator variants (for timing and for rocprofv3).
+
+    python -m paper_1012_3615_amd.microbench --dims 32 32 32 64 --reps 3 \\
+        --variants tile_w80_f32 gather_w80_f32 tile_w40_f32 tile_w80_f16 \\
+                   tile12_w80_f32 recompute_f32 stream
+
+Each variant builds its inputs (links exp(i 0.3 H), seed 4001; Gaussian
+spinors; the 12 point sources for the 12-RHS variant), runs one untimed
+launch, then `reps` launches timed with HIP events on the current stream,
+and prints one line per variant.  `stream` times a plain device read of a
+8 GiB buffer (torch sum) and a 2 GiB copy, as a reference for the
+achievable HBM bandwidth.  Inputs come from the seeded generator that runs
+on the device, so large lattices start quickly.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+import torch
+
+import synth
+from . import api as bri
+
+CB = {bri.F64: 16, bri.F32: 8, bri.F16: 4}
+
+# name -> (variant, w_prec, s_prec, n_offsets, nrhs, kernel, rhs_per_thread)
+VARIANTS = {
+    "tile_w80_f32": (bri.STORED, bri.F32, bri.F32, 80, 1, 1, 1),
+    "tile_w80_f32_dag": (bri.STORED, bri.F32, bri.F32, 80, 1, 1, 1),
+    "gather_w80_f32": (bri.STORED, bri.F32, bri.F32, 80, 1, 0, 1),
+    "tile_w40_f32": (bri.STORED, bri.F32, bri.F32, 40, 1, 1, 1),
+    "tile_w80_f16": (bri.STORED, bri.F16, bri.F32, 80, 1, 1, 1),
+    "tile_w80_f16h": (bri.STORED, bri.F16, bri.F16, 80, 1, 1, 1),
+    "tile_w80_f64": (bri.STORED, bri.F64, bri.F64, 80, 1, 1, 1),
+    "tile12_w80_f32": (bri.STORED, bri.F32, bri.F32, 80, 12, 6, 2),
+    "tile12_w80_f64": (bri.STORED, bri.F64, bri.F64, 80, 12, 6, 2),
+    "recompute_f32": (bri.RECOMPUTE, bri.F32, bri.F32, 80, 1, 1, 1),
+    "recompute_f64": (bri.RECOMPUTE, bri.F64, bri.F64, 80, 1, 1, 1),
+}
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def run(dims, names, reps=3, mass=0.1):
+    V = bri.volume(dims)
+    Ud = synth.gauge_links_device(dims, 0.3, 4001)
+    U64 = bri.bri_pack_links(dims, Ud, bri.F64)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4002)
+    shp = (1,) + synth.lattice_shape(dims) + (4, 3)
+    psi = torch.complex(torch.randn(shp, generator=gen, dtype=torch.float64, device="cuda"),
+                        torch.randn(shp, generator=gen, dtype=torch.float64, device="cuda"))
+    out = []
+    for name in names:
+        if name == "stream":
+            big = torch.ones(1 << 30, dtype=torch.float64, device="cuda")       # 8 GiB
+            ms = _time(lambda: big.sum(), reps)
+            out.append({"variant": "stream_read_8GiB", "ms": ms, "GBs": big.numel() * 8 / ms / 1e6})
+            del big
+            a = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+            b = torch.empty_like(a)
+            ms = _time(lambda: b.copy_(a), reps)
+            out.append({"variant": "copy_2GiB", "ms": ms, "GBs": 2 * a.numel() / ms / 1e6})
+            del a, b
+            continue
+        variant, wp, sp, noff, nrhs, kernel, rblk = VARIANTS[name]
+        if nrhs == 12:
+            src = torch.from_numpy(synth.point_sources(dims)).to("cuda")
+            x = bri.bri_pack_spinor(dims, src, sp)
+            del src
+        else:
+            x = bri.bri_pack_spinor(dims, psi, sp)
+        if variant == bri.STORED:
+            Wv = bri.bri_build_transporters(dims, U64, wp, noff)
+            byts = V * (noff * 9 * CB[wp] + nrhs * 2 * 12 * CB[sp])
+        else:
+            Wv = bri.bri_pack_links(dims, Ud, wp)
+            byts = V * (36 * CB[wp] + nrhs * 2 * 12 * CB[sp])
+        old = (bri.bri_get_apply_kernel(wp, sp), bri.bri_get_rhs_block(wp, sp))
+        bri.bri_set_apply_kernel(wp, sp, kernel)
+        bri.bri_set_rhs_block(wp, sp, rblk)
+        y = torch.empty_like(x)
+        fn = bri.bri_apply_dag if name.endswith("_dag") else bri.bri_apply
+        ms = _time(lambda: fn(dims, Wv, x, mass, variant=variant, out=y), reps)
+        bri.bri_set_apply_kernel(wp, sp, old[0])
+        bri.bri_set_rhs_block(wp, sp, old[1])
+        out.append({"variant": name, "ms": ms, "alg_GBs": byts / ms / 1e6,
+                    "nominal_TFs": 35376 * V * nrhs / ms / 1e9})
+        del Wv, x, y
+        torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dims", type=int, nargs=4, default=[32, 32, 32, 64])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--variants", nargs="+", default=["tile_w80_f32"])
+    a = ap.parse_args()
+    for r in run(tuple(a.dims), a.variants, a.reps):
+        print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()
