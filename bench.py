@@ -120,6 +120,15 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
     _, im = bri.bri_solve_cgne(DIMS, W64, b, MASS, p, W_lo=W32)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
+    del W32
+    W16 = bri.bri_build_transporters(DIMS, U64, bri.F16, 80)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = bri.solve_params(tol=tol, inner_prec=bri.F16, inner_tol=1e-2, check_every=4)
+    _, ih = bri.bri_solve_cgne(DIMS, W64, b, MASS, p, W_lo=W16)
+    torch.cuda.synchronize()
+    t_half = time.perf_counter() - t0
+    del W16
     t0 = time.perf_counter()
     iters, worst = 0, 0.0
     p = bri.solve_params(tol=tol, inner_prec=bri.F64, check_every=4)
@@ -133,7 +142,43 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
             "ratio_mixed_over_plain": t_mixed / t_plain,
             "mixed_iterations": im["iterations"], "mixed_outer": im["outer"],
             "mixed_max_true_residual": max(im["true_residual"][:12]),
+            "mixed_f16w_s": t_half, "ratio_mixed_f16w_over_plain": t_half / t_plain,
+            "mixed_f16w_iterations": ih["iterations"], "mixed_f16w_outer": ih["outer"],
+            "mixed_f16w_max_true_residual": max(ih["true_residual"][:12]),
             "plain_iterations_total": iters, "plain_max_true_residual": worst}
+
+
+def solve_cfg3(torch, bri, dev, tol=1e-10):
+    """24^3 x 48, links eps 0.4 (seed 3001), Gaussian right-hand side (seed
+    3002), m in {0.05, 0.2, 0.5}: mixed precision (FP32 transporters, inner
+    1e-3; FP16 transporters, inner 1e-2) against plain FP64 CGNE, all to a true
+    FP64 residual of 1e-10."""
+    import synth
+    dims = (24, 24, 24, 48)
+    u = synth.gauge_links(dims, 0.4, 3001)
+    U = bri.bri_pack_links(dims, torch.from_numpy(u).to(dev), bri.F64)
+    del u
+    b = bri.bri_pack_spinor(dims, torch.from_numpy(synth.gaussian_spinor(dims, 3002, 1)).to(dev), bri.F64)
+    W64 = bri.bri_build_transporters(dims, U, bri.F64, 80)
+    Wlo = {bri.F32: bri.bri_build_transporters(dims, U, bri.F32, 80),
+           bri.F16: bri.bri_build_transporters(dims, U, bri.F16, 80)}
+    out = {}
+    for m in (0.05, 0.2, 0.5):
+        row = {}
+        for name, prec, itol in (("plain_fp64", bri.F64, 0.5), ("mixed_f32", bri.F32, 1e-3),
+                                 ("mixed_f16w", bri.F16, 1e-2)):
+            p = bri.solve_params(tol=tol, inner_prec=prec, inner_tol=itol, check_every=4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = bri.bri_solve_cgne(dims, W64, b, m, p, W_lo=Wlo.get(prec))
+            torch.cuda.synchronize()
+            row[name] = {"s": time.perf_counter() - t0, "iterations": info["iterations"],
+                         "outer": info["outer"], "applies": info["applies"],
+                         "true_residual": info["true_residual"][0]}
+        for name in ("mixed_f32", "mixed_f16w"):
+            row[name]["speedup_vs_plain"] = row["plain_fp64"]["s"] / row[name]["s"]
+        out[f"m={m}"] = row
+    return out
 
 
 def gradient_timing(torch, bri, dev):
@@ -305,6 +350,8 @@ def main():
         res["solve_12rhs"] = solve_comparison(torch, bri, U64, dev)
     if not a.no_extras:
         res["gradient_16x16x16x32"] = gradient_timing(torch, bri, dev)
+    if not a.no_extras and not a.no_solve:
+        res["solve_24x24x24x48"] = solve_cfg3(torch, bri, dev)
 
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(u, psi[0])
