@@ -286,7 +286,7 @@ def main():
                    "spinor": f"gaussian, seed {SEED_PSI}"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(launch_bytes),
-                     "kernel": "k_apply_tiled<80,float2,float2,float,false,32,8,1,true>",
+                     "kernel": "k_apply_tiled<80,float2,float2,float,false,32,8,1,true,true>",
                      "alg_bytes_per_site": bps, "alg_bytes_per_launch": launch_bytes,
                      "kernel_ms": per_ms},
         "gflops": FLOPS_PER_SITE * V / (per_ms * 1e-3) / 1e9,

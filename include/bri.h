@@ -140,9 +140,12 @@ int32_t bri_get_rhs_block(bri_prec w_prec, bri_prec s_prec);
 /* Choose the stored-variant kernel used when one right-hand side is held per
  * thread: 1 = LDS tiles (default; each workgroup stages the spinor of its
  * x-y tile plus halo layer by layer in LDS; tile 16x16 if Lx <= 16, else
- * 32x8, with the next transporter prefetched), 2..5 = LDS tiles of 32x8,
+ * 32x8, with the next transporter prefetched and, for one right-hand side
+ * per thread on the 32x8 tile, each layer's offsets unrolled), 2..5 = LDS tiles of 32x8,
  * 16x16, 64x4 or 16x8 sites, 6, 7 = tiles of 32x8, 16x16 with transporter
- * prefetch, 0 = direct neighbour gathers through the caches.  All add the 81 terms of a site in
+ * prefetch, 8 = tile 32x8 with prefetch and each layer's offsets unrolled
+ * (one right-hand side per thread),
+ * 0 = direct neighbour gathers through the caches.  All add the 81 terms of a site in
  * the same order (offset index 0..80), so their results agree bit for bit.  Host-side state, not thread-safe against concurrent
  * applies. */
 bri_status bri_set_apply_kernel(bri_prec w_prec, bri_prec s_prec, int32_t kernel);

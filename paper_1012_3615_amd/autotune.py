@@ -20,7 +20,8 @@ from . import api
 
 CACHE = os.environ.get("BRI_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "bri_autotune.json"))
-TILES = {2: "tile32x8", 3: "tile16x16", 4: "tile64x4", 5: "tile16x8", 6: "tile32x8pf", 7: "tile16x16pf"}
+TILES = {2: "tile32x8", 3: "tile16x16", 4: "tile64x4", 5: "tile16x8", 6: "tile32x8pf", 7: "tile16x16pf",
+         8: "tile32x8pfu"}
 RBLKS = (1, 2, 3, 4, 6, 12)
 
 
@@ -49,11 +50,11 @@ def _store(c):
 def candidates(dims, nrhs, s_prec=api.F32):
     out = []
     for code, name in TILES.items():
-        tx = {2: 32, 3: 16, 4: 64, 5: 16, 6: 32, 7: 16}[code]
+        tx = {2: 32, 3: 16, 4: 64, 5: 16, 6: 32, 7: 16, 8: 32}[code]
         if tx > 2 * dims[0]:
             continue
         for r in (1, 2, 3, 4):
-            if r > 1 and (code in (3, 4, 7) or r > nrhs or (code == 6 and r > 2)):
+            if r > 1 and (code in (3, 4, 7, 8) or r > nrhs or (code == 6 and r > 2)):
                 continue
             if r > 2 and code == 2 and s_prec == api.F64:
                 continue  # the LDS of a 32x8 tile holds at most 2 FP64 spinors

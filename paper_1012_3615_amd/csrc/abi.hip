@@ -89,7 +89,7 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
         int rblk = nrhs == 1 ? 1 : snap_rblk(g_rhs_block[wp][sp], nrhs);
         if (kernel >= 1) {
             // LDS tiles hold 1..4 right-hand sides per thread (shapes 16x16, 64x4: 1)
-            if (kernel == 3 || kernel == 4 || kernel == 7) rblk = 1;
+            if (kernel == 3 || kernel == 4 || kernel == 7 || kernel == 8) rblk = 1;
             if (kernel == 6 && rblk > 2) rblk = 2;
             if (rblk > 4) rblk = 4;
             if (wp == BRI_F64 && rblk > 2 && kernel != 5 && !(kernel == 1 && g.L[0] <= 16))
@@ -234,7 +234,7 @@ bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
 bri_status bri_set_apply_kernel(bri_prec wp, bri_prec sp, int32_t kernel) {
     g_last_error.clear();
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    if (kernel < 0 || kernel > 7) return fail(BRI_E_ARG, "kernel must be in 0..7");
+    if (kernel < 0 || kernel > 8) return fail(BRI_E_ARG, "kernel must be in 0..8");
     g_apply_kernel[wp][sp] = kernel;
     return BRI_OK;
 }

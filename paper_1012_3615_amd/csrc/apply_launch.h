@@ -10,7 +10,8 @@ namespace launch {
 
 constexpr int kGatherBlock = 256;
 
-template <int NOFF, typename WS, typename SS, typename A, int TX, int TY, int R, bool PF = false>
+template <int NOFF, typename WS, typename SS, typename A, int TX, int TY, int R, bool PF = false,
+          bool UN = false>
 hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double diag, int nrhs,
                  bool dag, hipStream_t st) {
     // the LDS of a workgroup is at most 160 KiB on gfx950
@@ -22,11 +23,11 @@ hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double
         // one-dimensional grid, right-hand-side group fastest (see k_apply_tiled)
         dim3 grid(ntx * nty * g.L[2] * g.L[3] * ((nrhs + R - 1) / R));
         if (dag)
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF>), grid, dim3(TX * TY),
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF, UN>), grid, dim3(TX * TY),
                                0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out, (A)diag,
                                nrhs);
         else
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF>), grid, dim3(TX * TY),
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF, UN>), grid, dim3(TX * TY),
                                0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out, (A)diag,
                                nrhs);
         return hipGetLastError();
@@ -48,7 +49,8 @@ hipError_t gather(const Geom &g, const void *W, const void *in, void *out, doubl
 
 // kernel: 0 gather (rblk in 1,2,3,4,6,12); 1 tiles with the shape chosen from
 // Lx; 2..5 tiles 32x8, 16x16, 64x4, 16x8; 6, 7 tiles 32x8 and 16x16 with the
-// next transporter prefetched.  Tiles hold rblk in 1..4 right-hand sides per
+// next transporter prefetched; 8 tile 32x8 with prefetch and the offsets of a
+// layer unrolled at compile time (rblk 1 only: with 2 the unrolled form spills).  Tiles hold rblk in 1..4 right-hand sides per
 // thread (16x16 and 64x4: 1; 32x8 with prefetch: 1, 2).
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void *in, void *out,
@@ -69,7 +71,7 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         if (g.L[0] <= 16)
             kernel = rblk == 1 ? 7 : 5;
         else
-            kernel = rblk <= 2 ? 6 : 2;
+            kernel = rblk == 1 ? 8 : rblk == 2 ? 6 : 2;
     }
     switch (kernel * 16 + rblk) {
         case 2 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1>(g, W, in, out, diag, nrhs, dag, st);
@@ -85,6 +87,7 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         case 6 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, true>(g, W, in, out, diag, nrhs, dag, st);
         case 6 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, true>(g, W, in, out, diag, nrhs, dag, st);
         case 7 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 16, 1, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 8 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, true, true>(g, W, in, out, diag, nrhs, dag, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -20,7 +20,8 @@ struct TileShape {
     static constexpr int LOADS = (NH + NT - 1) / NT;  // halo sites per thread
 };
 
-template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R, bool PF = false>
+template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R, bool PF = false,
+          bool UN = false>
 __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty,
                                                         const WS *__restrict__ W,
                                                         const SS *__restrict__ in,
@@ -119,8 +120,8 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
         const bool centre = (nz | nt) == 0;  // this layer holds n = 0 at o = 4
         if (valid) {
             if (PF) load_w(layer, -1, -1, wn);
-#pragma unroll 1
-            for (int o = 0; o < 9; ++o) {
+            // one offset (nx, ny) = (o % 3 - 1, o / 3 - 1) of this layer
+            auto offset = [&](const int o) {
                 const int nx = o % 3 - 1, ny = o / 3 - 1;
                 const int qn = (ty + 1 + ny) * TS::HX + tx + 1 + nx;
                 if (centre && o == 4) {
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                             for (int a = 0; a < 3; ++a)
                                 acc[r][s][a] = caxpy(diag, ldc<A>(&lds[r][3 * s + a][qn]), acc[r][s][a]);
                     }
-                    continue;
+                    return;
                 }
                 const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
                 const A lam = lam_rt<A>(k);
@@ -161,6 +162,14 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                         for (int b = 0; b < 3; ++b) psi[s][b] = ldc<A>(&lds[r][3 * s + b][qn]);
                     colour_spin_accum(acc[r], w, psi, lam, rho, nx, ny, nz, nt);
                 }
+            };
+            if constexpr (UN) {
+                // compile-time offsets: the spin structure and the prefetch
+                // registers resolve statically
+                static_for<0, 9>([&](auto O) { offset(decltype(O)::value); });
+            } else {
+#pragma unroll 1
+                for (int o = 0; o < 9; ++o) offset(o);
             }
         }
     }
