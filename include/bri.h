@@ -131,23 +131,27 @@ bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W_or_U, bri_prec
                          void *out, int32_t nrhs, void *stream);
 
 /* Choose the number of right-hand sides held per thread in the fused
- * multi-RHS apply (1, 2, 3, 4, 6 or 12; 0 restores the built-in default) for
- * the given precisions.  Used by the autotuner; host-side state, not
+ * multi-RHS apply (1, 2, 3, 4, 6 or 12; 0 restores the built-in default of 2)
+ * for the given precisions.  Used by the autotuner; host-side state, not
  * thread-safe against concurrent applies. */
 bri_status bri_set_rhs_block(bri_prec w_prec, bri_prec s_prec, int32_t rhs_per_thread);
 int32_t bri_get_rhs_block(bri_prec w_prec, bri_prec s_prec);
 
-/* Choose the stored-variant kernel used when one right-hand side is held per
- * thread: 1 = LDS tiles (default; each workgroup stages the spinor of its
- * x-y tile plus halo layer by layer in LDS; tile 16x16 if Lx <= 16, else
- * 32x8, with the next transporter prefetched and, for one right-hand side
- * per thread on the 32x8 tile, each layer's offsets unrolled), 2..5 = LDS tiles of 32x8,
- * 16x16, 64x4 or 16x8 sites, 6, 7 = tiles of 32x8, 16x16 with transporter
- * prefetch, 8 = tile 32x8 with prefetch and each layer's offsets unrolled
- * (one right-hand side per thread),
- * 0 = direct neighbour gathers through the caches.  All add the 81 terms of a site in
- * the same order (offset index 0..80), so their results agree bit for bit.  Host-side state, not thread-safe against concurrent
- * applies. */
+/* Choose the stored-variant kernel for the given precisions.  Codes:
+ *   1  LDS tiles, shape chosen from Lx (default): each workgroup stages the
+ *      spinor of its x-y tile plus a one-site halo layer by layer in LDS;
+ *      for Lx > 16 a 32x8 tile with the next transporter prefetched and each
+ *      layer's offsets unrolled; for Lx <= 16 a 16x16 tile (one right-hand
+ *      side per thread) or 16x8 (several);
+ *   2..5   LDS tiles of 32x8, 16x16, 64x4 or 16x8 sites;
+ *   6, 7   tiles 32x8, 16x16 with transporter prefetch;
+ *   8      tile 32x8 with prefetch and each layer's offsets unrolled;
+ *   9, 10  tiles 32x8, 16x8 with the offsets unrolled, no prefetch;
+ *   0      direct neighbour gathers through the caches.
+ * A tile kernel holds 1-4 right-hand sides per thread (bri_set_rhs_block,
+ * clamped to what the shape supports).  All add the 81 terms of a site in
+ * the same order (offset index 0..80), so their results agree bit for bit.
+ * Host-side state, not thread-safe against concurrent applies. */
 bri_status bri_set_apply_kernel(bri_prec w_prec, bri_prec s_prec, int32_t kernel);
 int32_t bri_get_apply_kernel(bri_prec w_prec, bri_prec s_prec);
 

@@ -21,7 +21,10 @@ from . import api
 CACHE = os.environ.get("BRI_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "bri_autotune.json"))
 TILES = {2: "tile32x8", 3: "tile16x16", 4: "tile64x4", 5: "tile16x8", 6: "tile32x8pf", 7: "tile16x16pf",
-         8: "tile32x8pfu"}
+         8: "tile32x8pfu", 9: "tile32x8u", 10: "tile16x8u"}
+# right-hand sides per thread instantiated for each tile code
+TILE_RBLK = {2: (1, 2, 3, 4), 3: (1,), 4: (1,), 5: (1, 2, 3, 4), 6: (1, 2), 7: (1,), 8: (1, 2),
+             9: (1, 2, 3), 10: (2, 3, 4)}
 RBLKS = (1, 2, 3, 4, 6, 12)
 
 
@@ -50,13 +53,13 @@ def _store(c):
 def candidates(dims, nrhs, s_prec=api.F32):
     out = []
     for code, name in TILES.items():
-        tx = {2: 32, 3: 16, 4: 64, 5: 16, 6: 32, 7: 16, 8: 32}[code]
+        tx = {2: 32, 3: 16, 4: 64, 5: 16, 6: 32, 7: 16, 8: 32, 9: 32, 10: 16}[code]
         if tx > 2 * dims[0]:
             continue
-        for r in (1, 2, 3, 4):
-            if r > 1 and (code in (3, 4, 7, 8) or r > nrhs or (code == 6 and r > 2)):
+        for r in TILE_RBLK[code]:
+            if r > nrhs:
                 continue
-            if r > 2 and code == 2 and s_prec == api.F64:
+            if r > 2 and tx == 32 and s_prec == api.F64:
                 continue  # the LDS of a 32x8 tile holds at most 2 FP64 spinors
             out.append((f"{name}_r{r}", code, r))
     for r in RBLKS:

@@ -52,7 +52,7 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 namespace {
 // rhs-per-thread setting of the fused multi-RHS apply, per (w_prec, s_prec)
-int g_rhs_block[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};
+int g_rhs_block[3][3] = {{2, 2, 2}, {2, 2, 2}, {2, 2, 2}};
 // apply kernel per (w_prec, s_prec): 0 = register-blocked gather, 1 = LDS tiles
 // with the tile shape chosen from Lx, 2..5 = LDS tiles 32x8, 16x16, 64x4, 16x8,
 // 6, 7 = tiles 32x8, 16x16 with transporter prefetch
@@ -89,10 +89,12 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
         int rblk = nrhs == 1 ? 1 : snap_rblk(g_rhs_block[wp][sp], nrhs);
         if (kernel >= 1) {
             // LDS tiles hold 1..4 right-hand sides per thread (shapes 16x16, 64x4: 1)
-            if (kernel == 3 || kernel == 4 || kernel == 7 || kernel == 8) rblk = 1;
-            if (kernel == 6 && rblk > 2) rblk = 2;
+            if (kernel == 3 || kernel == 4 || kernel == 7) rblk = 1;
+            if ((kernel == 6 || kernel == 8) && rblk > 2) rblk = 2;
+            if (kernel == 9 && rblk > 3) rblk = 3;
+            if (kernel == 10 && rblk < 2) rblk = 2;
             if (rblk > 4) rblk = 4;
-            if (wp == BRI_F64 && rblk > 2 && kernel != 5 && !(kernel == 1 && g.L[0] <= 16))
+            if (wp == BRI_F64 && rblk > 2 && kernel != 5 && kernel != 10 && !(kernel == 1 && g.L[0] <= 16))
                 rblk = 2;  // LDS of a 32x8 tile
         }
         return hip_check(apply_stored(g, noff, (int)wp, (int)sp, kernel, rblk, W, in, out, diag, nrhs,
@@ -224,7 +226,7 @@ bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W, bri_prec wp, 
 bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
     g_last_error.clear();
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    if (r == 0) r = 1;
+    if (r == 0) r = 2;
     if (r != 1 && r != 2 && r != 3 && r != 4 && r != 6 && r != 12)
         return fail(BRI_E_ARG, "rhs_per_thread must be 1, 2, 3, 4, 6 or 12");
     g_rhs_block[wp][sp] = r;
@@ -234,7 +236,7 @@ bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
 bri_status bri_set_apply_kernel(bri_prec wp, bri_prec sp, int32_t kernel) {
     g_last_error.clear();
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    if (kernel < 0 || kernel > 8) return fail(BRI_E_ARG, "kernel must be in 0..8");
+    if (kernel < 0 || kernel > 10) return fail(BRI_E_ARG, "kernel must be in 0..10");
     g_apply_kernel[wp][sp] = kernel;
     return BRI_OK;
 }

@@ -50,7 +50,8 @@ hipError_t gather(const Geom &g, const void *W, const void *in, void *out, doubl
 // kernel: 0 gather (rblk in 1,2,3,4,6,12); 1 tiles with the shape chosen from
 // Lx; 2..5 tiles 32x8, 16x16, 64x4, 16x8; 6, 7 tiles 32x8 and 16x16 with the
 // next transporter prefetched; 8 tile 32x8 with prefetch and the offsets of a
-// layer unrolled at compile time (rblk 1 only: with 2 the unrolled form spills).  Tiles hold rblk in 1..4 right-hand sides per
+// layer unrolled at compile time (rblk 1, 2); 9, 10 tiles 32x8 (rblk 1-3) and
+// 16x8 (rblk 2-4) with the offsets unrolled, no prefetch.  Tiles hold rblk in 1..4 right-hand sides per
 // thread (16x16 and 64x4: 1; 32x8 with prefetch: 1, 2).
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void *in, void *out,
@@ -69,9 +70,9 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
     if (kernel == 1) {
         // default shapes: transporter prefetch where it is instantiated
         if (g.L[0] <= 16)
-            kernel = rblk == 1 ? 7 : 5;
+            kernel = rblk == 1 ? 7 : 10;
         else
-            kernel = rblk == 1 ? 8 : rblk == 2 ? 6 : 2;
+            kernel = rblk <= 2 ? 8 : rblk == 3 ? 9 : 2;
     }
     switch (kernel * 16 + rblk) {
         case 2 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1>(g, W, in, out, diag, nrhs, dag, st);
@@ -88,6 +89,13 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         case 6 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, true>(g, W, in, out, diag, nrhs, dag, st);
         case 7 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 16, 1, true>(g, W, in, out, diag, nrhs, dag, st);
         case 8 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, true, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 8 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, true, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 9 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, false, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 9 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, false, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 9 * 16 + 3: return tiled<NOFF, WS, SS, A, 32, 8, 3, false, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 10 * 16 + 2: return tiled<NOFF, WS, SS, A, 16, 8, 2, false, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 10 * 16 + 3: return tiled<NOFF, WS, SS, A, 16, 8, 3, false, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 10 * 16 + 4: return tiled<NOFF, WS, SS, A, 16, 8, 4, false, true>(g, W, in, out, diag, nrhs, dag, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
         if (valid) {
             if (PF) load_w(layer, -1, -1, wn);
             // one offset (nx, ny) = (o % 3 - 1, o / 3 - 1) of this layer
-            auto offset = [&](const int o) {
+            auto offset = [&](const int o) __attribute__((always_inline)) {
                 const int nx = o % 3 - 1, ny = o / 3 - 1;
                 const int qn = (ty + 1 + ny) * TS::HX + tx + 1 + nx;
                 if (centre && o == 4) {

@@ -33,8 +33,9 @@ VARIANTS = {
     "tile_w80_f16": (bri.STORED, bri.F16, bri.F32, 80, 1, 1, 1),
     "tile_w80_f16h": (bri.STORED, bri.F16, bri.F16, 80, 1, 1, 1),
     "tile_w80_f64": (bri.STORED, bri.F64, bri.F64, 80, 1, 1, 1),
-    "tile12_w80_f32": (bri.STORED, bri.F32, bri.F32, 80, 12, 6, 2),
-    "tile12_w80_f64": (bri.STORED, bri.F64, bri.F64, 80, 12, 6, 2),
+    "tile12_w80_f32": (bri.STORED, bri.F32, bri.F32, 80, 12, 1, 2),
+    "tile12_w80_f16": (bri.STORED, bri.F16, bri.F32, 80, 12, 1, 1),
+    "tile12_w80_f64": (bri.STORED, bri.F64, bri.F64, 80, 12, 1, 2),
     "recompute_f32": (bri.RECOMPUTE, bri.F32, bri.F32, 80, 1, 1, 1),
     "recompute_f64": (bri.RECOMPUTE, bri.F64, bri.F64, 80, 1, 1, 1),
 }
