@@ -26,8 +26,15 @@ without blocking or fusion:
   (the factorisation of App. D applied to the product forms), used as a pin;
 * ``free``        - the free-field momentum-space symbol and propagator;
 * ``solver``      - CG on the normal equations;
-* ``grad``        - gradients of Re<chi, D psi> with respect to links and psi.
+* ``grad``        - gradients of Re<chi, D psi> with respect to links and psi;
+* ``projection``  - the projections to U(3) and SU(3) of Sec. 5.2 (SVD, then
+  the constrained phase maximisation);
+* ``smearing``    - one APE smearing step (Eq. def_ape);
+* ``clover``      - the clover term of Eq. def_pref (clover-leaf field strength);
+* ``production``  - the operator of Sec. 5: back-projected transporters plus
+  the clover term.
 
 Parity status of each function is listed in the module docstrings.
 """
-from . import constants, gamma, lattice, transporters, dirac, factorized, free, solver, grad  # noqa: F401
+from . import (constants, gamma, lattice, transporters, dirac, factorized, free, solver, grad,  # noqa: F401
+               projection, smearing, clover, production)
