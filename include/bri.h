@@ -2,7 +2,10 @@
  * bri.h - C ABI of the MI355X (gfx950) Brillouin Dirac operator library.
  *
  * The operator is the "Brillouin operator" of Durr & Koutsou,
- * arXiv:1012.3615, Eq. def_pref with c_SW = 0 and lattice spacing a = 1:
+ * arXiv:1012.3615, Eq. def_pref with lattice spacing a = 1; the core entry
+ * points apply it with c_SW = 0 and path-averaged transporters, the
+ * production-operator section at the end adds the SU(3) back-projection, the
+ * APE smearing and the clover term of the paper's Sec. 5:
  *
  *   D = sum_mu gamma_mu nabla^iso_mu - (1/2) Lap^bri + m,
  *
@@ -206,6 +209,87 @@ size_t bri_grad_workspace_bytes(bri_dims d);
 bri_status bri_grad_links(bri_dims d, const double *U_soa, const double *chi, const double *psi,
                           int32_t nrhs, double scale, double *gradU, void *work,
                           size_t work_bytes, void *stream);
+
+/* ---- production operator (Sec. 5) -----------------------------------------
+ * The operator of the paper's quenched tests uses (i) links after one APE
+ * smearing step (Eq. def_ape), (ii) transporters back-projected to SU(3)
+ * after the path averaging (Sec. 5.1) with the projection of Sec. 5.2, and
+ * (iii) the clover term of Eq. def_pref,
+ *     -(c_SW/2) sum_{mu<nu} sigma_{mu nu} F_{mu nu},  c_SW = 1 at tree level (Sec. 5.3),
+ * with sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu] and F_{mu nu} the Hermitian
+ * clover-leaf field strength (Q - Q^dag)/(8i), Q the sum of the four
+ * plaquettes at x in the (mu, nu) plane, made traceless.  D^dag is again D
+ * with rho_k -> -rho_k (the clover term is Hermitian and commutes with
+ * gamma5).  All construction steps compute in FP64. */
+
+/* Nearest SU(3) matrix in the Frobenius norm (Sec. 5.2, Eq. proj_SU) for n
+ * FP64 matrices in the SoA layout [9][n] (element e = 3a + b, one complex
+ * double each): A = U S V^dag from the eigen-decomposition of A^dag A, then
+ * the phases D that maximise Re tr(A^dag U D V^dag) under det = 1, found by a
+ * scan of spacing pi/3 over two free phases and Newton refinement; the result
+ * is U D V^dag.  Y may equal A (in place); other overlap is BRI_E_ARG.  The
+ * matrices must be non-singular.  n = 0 is a no-op. */
+bri_status bri_project_su3(int64_t n, const double *A, double *Y, void *stream);
+
+/* One APE step (Eq. def_ape) on FP64 SoA links [mu][9][V]:
+ *   V_mu(x) = P_SU(3){ (1-alpha) 1 + (alpha/6) sum_{+-nu != mu}
+ *             U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag U_mu(x)^dag } U_mu(x),
+ * where the link of a -nu step from y is U_nu(y-nu)^dag.  The paper uses
+ * alpha = 0.72.  U_soa and V_soa must not overlap. */
+bri_status bri_ape_smear(bri_dims d, const double *U_soa, double *V_soa, double alpha, void *stream);
+
+/* Storage form of the transporters. */
+typedef enum {
+    BRI_W_AVERAGE = 0,  /* path average (as bri_build_transporters), 9 complex each          */
+    BRI_W_SU3 = 1,      /* back-projected to SU(3), 9 complex each                             */
+    BRI_W_SU3_2ROW = 2  /* back-projected, rows 0 and 1 only (6 complex each, layout
+                           [n_offsets][6][V]); the apply rebuilds row 2 = conj(row0 x row1) */
+} bri_wform;
+
+/* Transporters in the given form.  For the SU(3) forms the 2-, 3- and 4-hop
+ * path averages are built in FP64 exactly as by bri_build_transporters, then
+ * each is projected (the 1-hop transporters are the links, already in SU(3)),
+ * then converted to w_prec.  work: bri_build_workspace_bytes_ex bytes. */
+size_t bri_transporter_bytes_ex(bri_dims d, bri_prec p, int32_t n_offsets, bri_wform form);
+size_t bri_build_workspace_bytes_ex(bri_dims d, bri_prec p, int32_t n_offsets, bri_wform form);
+bri_status bri_build_transporters_ex(bri_dims d, const double *U_soa, void *W, bri_prec w_prec,
+                                     int32_t n_offsets, bri_wform form, void *work, size_t work_bytes,
+                                     void *stream);
+
+/* Clover term per site from FP64 SoA links, stored in c_prec.  In the chiral
+ * basis it is block diagonal: one Hermitian 6x6 block on spins (0,1) and one
+ * on spins (2,3), local index 3*spin' + colour.  Layout [2][18][V] complex:
+ * planes 0..2 hold the real diagonal in pairs (M00, M11), (M22, M33),
+ * (M44, M55) as (re, im); planes 3..17 hold M_ij for i < j, row by row. */
+size_t bri_clover_bytes(bri_dims d, bri_prec p);
+bri_status bri_build_clover(bri_dims d, const double *U_soa, double csw, void *C, bri_prec c_prec,
+                            void *stream);
+
+/* An operator: transporters, their form and, optionally, the clover term. */
+typedef struct {
+    const void *W;       /* transporters (bri_build_transporters or _ex)                     */
+    bri_prec w_prec;
+    int32_t n_offsets;   /* 40 or 80; 80 for BRI_W_SU3_2ROW or with a clover term           */
+    bri_wform w_form;
+    const void *clover;  /* bri_build_clover output in the spinor precision; NULL: c_SW = 0  */
+} bri_operator;
+
+/* out = D in (dagger = 0) or D^dag in (dagger = 1) for the stored variant,
+ * with the spinor and precision rules of bri_apply.  The two-row form and the
+ * clover term use the default LDS-tile kernel (one or two right-hand sides
+ * per thread); otherwise this is bri_apply / bri_apply_dag. */
+bri_status bri_apply_op(bri_dims d, const bri_operator *op, bri_prec s_prec, double mass,
+                        const void *in, void *out, int32_t nrhs, int32_t dagger, void *stream);
+
+/* bri_solve_cgne for a general operator: op_hi in FP64 (w_prec F64, clover
+ * F64) for the outer residual and the plain solver; op_lo for the inner
+ * solve of defect correction (w_prec = p->inner_prec, clover F32), the same
+ * operator at lower precision.  p->n_offsets is ignored (each operator
+ * carries its own).  Workspace: bri_solve_workspace_bytes. */
+bri_status bri_solve_cgne_op(bri_dims d, const bri_solve_params *p, const bri_operator *op_hi,
+                             const bri_operator *op_lo, double mass, const double *b, double *x,
+                             int32_t nrhs, void *work, size_t work_bytes, bri_solve_stats *stats,
+                             void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,4 +11,6 @@ from .api import (  # noqa: F401
     bri_build_transporters, bri_apply, bri_apply_dag,
     bri_set_rhs_block, bri_get_rhs_block, bri_set_apply_kernel, bri_get_apply_kernel,
     solve_params, bri_solve_cgne, bri_grad_links,
+    W_AVERAGE, W_SU3, W_SU3_2ROW, Operator, bri_project_su3, bri_ape_smear, bri_build_transporters_ex,
+    bri_build_clover, bri_apply_op, bri_solve_cgne_op,
 )

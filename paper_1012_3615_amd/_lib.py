@@ -39,6 +39,16 @@ class bri_solve_stats(ctypes.Structure):
     ]
 
 
+class bri_operator(ctypes.Structure):
+    _fields_ = [
+        ("W", ctypes.c_void_p),
+        ("w_prec", ctypes.c_int32),
+        ("n_offsets", ctypes.c_int32),
+        ("w_form", ctypes.c_int32),
+        ("clover", ctypes.c_void_p),
+    ]
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _sz = ctypes.c_size_t
@@ -69,6 +79,17 @@ PROTOTYPES = {
                               _i32, _vp, _sz, ctypes.POINTER(bri_solve_stats), _vp]),
     "bri_grad_workspace_bytes": (_sz, [_D]),
     "bri_grad_links": (_i32, [_D, _vp, _vp, _vp, _i32, _dbl, _vp, _vp, _sz, _vp]),
+    "bri_project_su3": (_i32, [ctypes.c_int64, _vp, _vp, _vp]),
+    "bri_ape_smear": (_i32, [_D, _vp, _vp, _dbl, _vp]),
+    "bri_transporter_bytes_ex": (_sz, [_D, _i32, _i32, _i32]),
+    "bri_build_workspace_bytes_ex": (_sz, [_D, _i32, _i32, _i32]),
+    "bri_build_transporters_ex": (_i32, [_D, _vp, _vp, _i32, _i32, _i32, _vp, _sz, _vp]),
+    "bri_clover_bytes": (_sz, [_D, _i32]),
+    "bri_build_clover": (_i32, [_D, _vp, _dbl, _vp, _i32, _vp]),
+    "bri_apply_op": (_i32, [_D, ctypes.POINTER(bri_operator), _i32, _dbl, _vp, _vp, _i32, _i32, _vp]),
+    "bri_solve_cgne_op": (_i32, [_D, ctypes.POINTER(bri_solve_params), ctypes.POINTER(bri_operator),
+                                 ctypes.POINTER(bri_operator), _dbl, _vp, _vp, _i32, _vp, _sz,
+                                 ctypes.POINTER(bri_solve_stats), _vp]),
 }
 
 

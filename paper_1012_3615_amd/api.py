@@ -6,7 +6,8 @@ real tensors whose last axis holds (re, im):
 
     spinors       [nrhs, 12, V, 2]     component = 3*spin + colour
     links         [4, 9, V, 2]         element   = 3*a + b
-    transporters  [n_offsets, 9, V, 2]
+    transporters  [n_offsets, 9, V, 2]   (two-row SU(3) form: [n_offsets, 6, V, 2])
+    clover term   [2, 18, V, 2]
 
 with dtype float64 (F64), float32 (F32) or float16 (F16).  Canonical fields
 are complex128 tensors [4, Lt, Lz, Ly, Lx, 3, 3] (links) and
@@ -22,6 +23,7 @@ from . import _lib
 
 F64, F32, F16 = 0, 1, 2
 STORED, RECOMPUTE = 0, 1
+W_AVERAGE, W_SU3, W_SU3_2ROW = 0, 1, 2
 
 _lib_handle = _lib.load()
 
@@ -244,6 +246,140 @@ def bri_solve_cgne(dims, W_hi, b, mass, params, W_lo=None, x=None, raise_on_noco
     }
     if st != 0 and (raise_on_noconv or st != -4):
         raise BriError(st, "bri_solve_cgne")
+    return x, info
+
+
+# ------------------------------------------------------------------ production operator (Sec. 5)
+def bri_project_su3(A, out=None):
+    """Closest SU(3) matrices for FP64 SoA matrices A [9, n, 2]; out may be A."""
+    _need_cuda(A, out)
+    if prec_of(A) != F64 or A.dim() != 3 or A.shape[0] != 9 or A.shape[2] != 2:
+        raise ValueError("A must be an FP64 tensor [9, n, 2]")
+    Y = out if out is not None else torch.empty_like(A)
+    _shape(Y, A.shape, "out")
+    _check(_lib_handle.bri_project_su3(A.shape[1], _ptr(A), _ptr(Y), _stream()), "bri_project_su3")
+    return Y
+
+
+def bri_ape_smear(dims, U_soa, alpha=0.72, out=None):
+    """One APE smearing step of FP64 SoA links."""
+    _need_cuda(U_soa, out)
+    _shape(U_soa, (4, 9, volume(dims), 2), "links")
+    if prec_of(U_soa) != F64:
+        raise ValueError("APE smearing takes FP64 links")
+    V = out if out is not None else torch.empty_like(U_soa)
+    _shape(V, U_soa.shape, "out")
+    _check(_lib_handle.bri_ape_smear(_dims(dims), _ptr(U_soa), _ptr(V), float(alpha), _stream()),
+           "bri_ape_smear")
+    return V
+
+
+def _rows(form):
+    return 6 if form == W_SU3_2ROW else 9
+
+
+def bri_build_transporters_ex(dims, U_soa, prec=F64, n_offsets=80, form=W_SU3, out=None):
+    _need_cuda(U_soa, out)
+    if prec_of(U_soa) != F64:
+        raise ValueError("transporters are built from FP64 links")
+    _shape(U_soa, (4, 9, volume(dims), 2), "links")
+    shape = (n_offsets, _rows(form), volume(dims), 2)
+    W = out if out is not None else torch.empty(shape, dtype=_TORCH[prec], device=U_soa.device)
+    _shape(W, shape, "transporters")
+    nbytes = _lib_handle.bri_build_workspace_bytes_ex(_dims(dims), prec, n_offsets, form)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=U_soa.device) if nbytes else None
+    _check(_lib_handle.bri_build_transporters_ex(_dims(dims), _ptr(U_soa), _ptr(W), prec, n_offsets, form,
+                                                 _ptr(work), nbytes, _stream()),
+           "bri_build_transporters_ex")
+    return W
+
+
+def bri_build_clover(dims, U_soa, csw=1.0, prec=F64):
+    """Clover term [2, 18, V, 2] in prec from FP64 SoA links."""
+    _need_cuda(U_soa)
+    _shape(U_soa, (4, 9, volume(dims), 2), "links")
+    if prec_of(U_soa) != F64:
+        raise ValueError("the clover term is built from FP64 links")
+    C = torch.empty((2, 18, volume(dims), 2), dtype=_TORCH[prec], device=U_soa.device)
+    _check(_lib_handle.bri_build_clover(_dims(dims), _ptr(U_soa), float(csw), _ptr(C), prec, _stream()),
+           "bri_build_clover")
+    return C
+
+
+class Operator:
+    """Transporters (and form) plus an optional clover term; keeps the tensors alive."""
+
+    def __init__(self, W, form=W_AVERAGE, clover=None):
+        self.W, self.form, self.clover = W, form, clover
+
+    def struct(self, dims):
+        _need_cuda(self.W, self.clover)
+        V = volume(dims)
+        _shape(self.W, (self.W.shape[0], _rows(self.form), V, 2), "transporters")
+        if self.clover is not None:
+            _shape(self.clover, (2, 18, V, 2), "clover")
+        o = _lib.bri_operator()
+        o.W = self.W.data_ptr()
+        o.w_prec = prec_of(self.W)
+        o.n_offsets = self.W.shape[0]
+        o.w_form = self.form
+        o.clover = self.clover.data_ptr() if self.clover is not None else None
+        return o
+
+
+def bri_apply_op(dims, op, psi, mass, dagger=False, out=None):
+    """out = D psi (or D^dag psi) for an Operator."""
+    _need_cuda(psi, out)
+    _shape(psi, (psi.shape[0], 12, volume(dims), 2), "spinor")
+    if op.clover is not None and op.clover.dtype != psi.dtype:
+        raise ValueError("the clover term must be stored in the spinor precision")
+    if out is None:
+        out = torch.empty_like(psi)
+    elif out.shape != psi.shape or out.dtype != psi.dtype:
+        raise ValueError("out must match the input spinor's shape and dtype")
+    o = op.struct(dims)
+    _check(_lib_handle.bri_apply_op(_dims(dims), ctypes.byref(o), prec_of(psi), float(mass), _ptr(psi),
+                                    _ptr(out), psi.shape[0], int(bool(dagger)), _stream()),
+           "bri_apply_op")
+    return out
+
+
+def bri_solve_cgne_op(dims, op_hi, b, mass, params, op_lo=None, x=None, raise_on_noconv=True):
+    """bri_solve_cgne for Operators (op_hi FP64; op_lo in the inner precision,
+    clover FP32).  Returns (x, stats dict)."""
+    _need_cuda(b, x)
+    V = volume(dims)
+    _shape(b, (b.shape[0], 12, V, 2), "b")
+    if x is not None:
+        _shape(x, b.shape, "x")
+    if prec_of(b) != F64 or prec_of(op_hi.W) != F64:
+        raise ValueError("b and the outer operator must be FP64")
+    if op_hi.clover is not None and op_hi.clover.dtype != torch.float64:
+        raise ValueError("the outer clover term must be FP64")
+    if params.inner_prec != F64:
+        if op_lo is None or prec_of(op_lo.W) != params.inner_prec:
+            raise ValueError("op_lo must be given in the inner precision")
+        if op_lo.clover is not None and op_lo.clover.dtype != torch.float32:
+            raise ValueError("the inner clover term must be FP32")
+    nrhs = b.shape[0]
+    if x is None:
+        x = torch.zeros_like(b)
+    nbytes = _lib_handle.bri_solve_workspace_bytes(_dims(dims), ctypes.byref(params), nrhs)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=b.device)
+    stats = _lib.bri_solve_stats()
+    hi = op_hi.struct(dims)
+    lo = op_lo.struct(dims) if op_lo is not None else None
+    st = _lib_handle.bri_solve_cgne_op(_dims(dims), ctypes.byref(params), ctypes.byref(hi),
+                                       ctypes.byref(lo) if lo is not None else None, float(mass), _ptr(b),
+                                       _ptr(x), nrhs, _ptr(work), nbytes, ctypes.byref(stats), _stream())
+    info = {
+        "iterations": stats.iterations, "outer": stats.outer, "applies": stats.applies,
+        "converged": bool(stats.converged),
+        "true_residual": [stats.true_residual[i] for i in range(min(nrhs, _lib.BRI_MAX_RHS))],
+        "status": st,
+    }
+    if st != 0 and (raise_on_noconv or st != -4):
+        raise BriError(st, "bri_solve_cgne_op")
     return x, info
 
 

@@ -23,8 +23,9 @@ OUT = os.path.join(HERE, "libbri.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("BRI_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.hip", "apply.hip", "apply_f64.hip", "apply_f32.hip", "apply_f16.hip", "apply_f16h.hip",
-           "build.hip", "pack.hip", "blas.hip", "solve.hip", "grad.hip"]
+SOURCES = ["abi.hip", "abi_prod.hip", "apply.hip", "apply_f64.hip", "apply_f32.hip", "apply_f16.hip", "apply_f16h.hip",
+           "apply_prod_f64.hip", "apply_prod_f32.hip", "apply_prod_f16.hip", "apply_prod_f16h.hip",
+           "build.hip", "production.hip", "pack.hip", "blas.hip", "solve.hip", "grad.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -22,4 +22,18 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
                       bri_prec sp, double mass, const void *in, void *out, int32_t nrhs,
                       void *stream, bool dag);
 
+// A stored-transporter operator: W, its precision and offset count, the number
+// of stored rows per transporter (3, or 2 for the two-row SU(3) store) and
+// the clover term (nullptr for c_SW = 0).
+struct OpDesc {
+    const void *W;
+    bri_prec wp;
+    int32_t noff;
+    int rows;
+    const void *clover;
+};
+bri_status op_from_public(const bri_operator *op, OpDesc *out);
+bri_status apply_op(bri_dims d, const OpDesc &op, bri_prec sp, double mass, const void *in, void *out,
+                    int32_t nrhs, void *stream, bool dag);
+
 }  // namespace bri

@@ -11,9 +11,9 @@ namespace launch {
 constexpr int kGatherBlock = 256;
 
 template <int NOFF, typename WS, typename SS, typename A, int TX, int TY, int R, bool PF = false,
-          bool UN = false>
+          bool UN = false, int ROWS = 3, bool CLV = false>
 hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double diag, int nrhs,
-                 bool dag, hipStream_t st) {
+                 bool dag, hipStream_t st, const void *clover = nullptr) {
     // the LDS of a workgroup is at most 160 KiB on gfx950
     constexpr size_t lds = sizeof(SS) * 12 * R * (TX + 2) * (TY + 2);
     if constexpr (lds > 160 * 1024) {
@@ -23,13 +23,13 @@ hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double
         // one-dimensional grid, right-hand-side group fastest (see k_apply_tiled)
         dim3 grid(ntx * nty * g.L[2] * g.L[3] * ((nrhs + R - 1) / R));
         if (dag)
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF, UN>), grid, dim3(TX * TY),
-                               0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out, (A)diag,
-                               nrhs);
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF, UN, ROWS, CLV>), grid,
+                               dim3(TX * TY), 0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out,
+                               (A)diag, nrhs, (const SS *)clover);
         else
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF, UN>), grid, dim3(TX * TY),
-                               0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out, (A)diag,
-                               nrhs);
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF, UN, ROWS, CLV>), grid,
+                               dim3(TX * TY), 0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out,
+                               (A)diag, nrhs, (const SS *)clover);
         return hipGetLastError();
     }
 }
@@ -98,6 +98,41 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         case 10 * 16 + 4: return tiled<NOFF, WS, SS, A, 16, 8, 4, false, true>(g, W, in, out, diag, nrhs, dag, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Production-operator forms (80-offset store only): ROWS = 2 for the two-row
+// store of back-projected transporters, CLV for the clover term.  The tile
+// is the default one for the extent Lx (32x8 with prefetch and unrolled
+// offsets, or 16x16 / 16x8 for Lx <= 16); rblk 1 or 2 right-hand sides per
+// thread.
+template <typename WS, typename SS, typename A, int ROWS, bool CLV>
+hipError_t stored_ext(const Geom &g, int rblk, const void *W, const void *in, void *out, double diag,
+                      int nrhs, bool dag, hipStream_t st, const void *clover) {
+    const bool small = g.L[0] <= 16;
+    if (rblk == 1)
+        return small ? tiled<80, WS, SS, A, 16, 16, 1, true, false, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
+                                                                             clover)
+                     : tiled<80, WS, SS, A, 32, 8, 1, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
+                                                                           clover);
+    if (rblk == 2)
+        return small ? tiled<80, WS, SS, A, 16, 8, 2, false, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
+                                                                            clover)
+                     : tiled<80, WS, SS, A, 32, 8, 2, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
+                                                                           clover);
+    return hipErrorInvalidValue;
+}
+
+// rows: 3 or 2; clover: nullptr for c_SW = 0
+template <typename WS, typename SS, typename A>
+hipError_t stored_prod(const Geom &g, int rows, int rblk, const void *W, const void *in, void *out, double diag,
+                       int nrhs, bool dag, hipStream_t st, const void *clover) {
+    if (rows == 3 && clover)
+        return stored_ext<WS, SS, A, 3, true>(g, rblk, W, in, out, diag, nrhs, dag, st, clover);
+    if (rows == 2 && clover)
+        return stored_ext<WS, SS, A, 2, true>(g, rblk, W, in, out, diag, nrhs, dag, st, clover);
+    if (rows == 2)
+        return stored_ext<WS, SS, A, 2, false>(g, rblk, W, in, out, diag, nrhs, dag, st, nullptr);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace launch

@@ -2,6 +2,7 @@
 // side per thread).
 #pragma once
 #include "stencil.h"
+#include "su3.h"
 
 namespace bri {
 // ---------------------------------------------------------------- stored W, LDS tiles
@@ -14,6 +15,10 @@ namespace bri {
 // store: every element is read exactly once per right-hand-side group).  With
 // R > 1 each thread holds R right-hand sides: the LDS holds R layers and every
 // transporter load serves all R.
+//
+// Options for the production operator: ROWS = 2 reads the two-row store of
+// back-projected (SU(3)) transporters and rebuilds the third row; CLV adds
+// the clover term, a Hermitian 6x6 block per chirality and site, at n = 0.
 template <int TX, int TY>
 struct TileShape {
     static constexpr int HX = TX + 2, HY = TY + 2, NH = HX * HY, NT = TX * TY;
@@ -21,11 +26,12 @@ struct TileShape {
 };
 
 template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R, bool PF = false,
-          bool UN = false>
+          bool UN = false, int ROWS = 3, bool CLV = false>
 __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty,
                                                         const WS *__restrict__ W,
                                                         const SS *__restrict__ in,
-                                                        SS *__restrict__ out, A diag, int nrhs) {
+                                                        SS *__restrict__ out, A diag, int nrhs,
+                                                        const SS *__restrict__ clover) {
     using TS = TileShape<TX, TY>;
     __shared__ SS lds[R][12][TS::NH];
     // one-dimensional grid: tile-major, right-hand-side group fastest, so the
@@ -70,25 +76,59 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[r][s][a] = cmake<A>(0, 0);
 
+    // clover term first, while few registers are live: one chirality block
+    // (six spin-colour components) at a time, psi(x) read from global memory
+    if constexpr (CLV) {
+        if (valid) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cx<A> cl[18];
+                clover_load_block(clover, V, site, b, cl);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (R > 1 && r >= nr) break;
+                    cx<A> xb[6];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) xb[i] = ldc<A>(in + (size_t)r * 12 * V + (6 * b + i) * V + site);
+                    clover_accum_block(cl, xb, b, acc[r]);
+                }
+            }
+        }
+    }
+
     // transporter of offset (nx, ny) of layer (lz, lt) = (layer % 3, layer / 3)
     auto load_w = [&](int layer, int nx, int ny, cx<A> (&w)[3][3]) {
         const int lnz = layer % 3 - 1, lnt = layer / 3 - 1;
         const int i = (nx + 1) + 3 * (ny + 1) + 9 * (lnz + 1) + 27 * (lnt + 1);
+        constexpr int NE = 3 * ROWS;  // stored elements per transporter
         if (NOFF == 80) {
-            const WS *p = W + (size_t)(i < 40 ? i : i - 1) * 9 * V + site;
+            const WS *p = W + (size_t)(i < 40 ? i : i - 1) * NE * V + site;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ldnt<A>(p + e * V);
+            for (int e = 0; e < NE; ++e) w[e / 3][e % 3] = ldnt<A>(p + e * V);
+            if constexpr (ROWS == 2) su3_third_row(w);
         } else if (i > 40) {
-            const WS *p = W + (size_t)(i - 41) * 9 * V + site;
+            const WS *p = W + (size_t)(i - 41) * NE * V + site;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + e * V);
+            for (int e = 0; e < NE; ++e) w[e / 3][e % 3] = ld<A>(p + e * V);
+            if constexpr (ROWS == 2) su3_third_row(w);
         } else {
             // W(x, x+n) = W(x+n, x)^dag, stored at x+n under offset -n
             const int zn = (z + lnz + Lz) % Lz, tn = (t + lnt + Lt) % Lt;
             const int yn = ((x + nx + Lx) % Lx) + Lx * (((y + ny + Ly) % Ly) + Ly * (zn + Lz * tn));
-            const WS *p = W + (size_t)(39 - i) * 9 * V + yn;
+            const WS *p = W + (size_t)(39 - i) * NE * V + yn;
+            if constexpr (ROWS == 2) {
+                cx<A> m[3][3];
 #pragma unroll
-            for (int e = 0; e < 9; ++e) w[e % 3][e / 3] = cconj(ld<A>(p + e * V));
+                for (int e = 0; e < NE; ++e) m[e / 3][e % 3] = ld<A>(p + e * V);
+                su3_third_row(m);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) w[a][b] = cconj(m[b][a]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) w[e % 3][e / 3] = cconj(ld<A>(p + e * V));
+            }
         }
     };
     // with PF the next transporter of the layer is in flight during the

@@ -20,12 +20,30 @@ BRI_DECL_APPLY(f32)
 BRI_DECL_APPLY(f16)
 BRI_DECL_APPLY(f16h)
 #undef BRI_DECL_APPLY
+// apply_prod_*.hip: production-operator forms of the stored apply (80
+// offsets; rows 3 or 2; clover in the spinor precision or nullptr)
+#define BRI_DECL_PROD(tag)                                                                         \
+    hipError_t apply_prod_##tag(const Geom &g, int rows, int rblk, const void *W, const void *in,  \
+                                void *out, double diag, int nrhs, bool dag, hipStream_t st,        \
+                                const void *clover);
+BRI_DECL_PROD(f64)
+BRI_DECL_PROD(f32)
+BRI_DECL_PROD(f16)
+BRI_DECL_PROD(f16h)
+#undef BRI_DECL_PROD
 hipError_t apply_recompute(const Geom &g, int up, int sp, const void *U, const void *in, void *out,
                            double diag, int nrhs, bool dag, hipStream_t st);
 
 // build.hip: FP64 40-offset store, then conversion
 hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st);
 hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st);
+
+// production.hip
+hipError_t project_su3_soa(const double2 *A, double2 *Y, int64_t n, hipStream_t st);
+hipError_t project_w40(const Geom &g, double2 *W40, hipStream_t st);
+hipError_t ape_smear(const Geom &g, const double2 *U, double2 *Vout, double alpha, hipStream_t st);
+hipError_t build_clover(const Geom &g, const double2 *U, void *C, int cp, double csw, hipStream_t st);
+hipError_t convert_w40_rows2(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st);
 
 // pack.hip
 hipError_t pack_links(const Geom &g, const double2 *canon, void *soa, int p, hipStream_t st);

@@ -76,7 +76,6 @@ struct Ctx {
     Geom g;
     size_t n;  // reals per rhs
     int nrhs;
-    int noff;
     double mass;
     bool dag;  // solve D^dag x = b
     hipStream_t st;
@@ -108,8 +107,8 @@ bri_status fetch(const Ctx &c, const double *dev, double *host, size_t count) {
 
 // inner CGNE on D e = r with e = 0 initially; r holds the right-hand side.
 template <typename T>
-bri_status inner_cgne(const Ctx &c, const void *W, bri_prec wp, bri_prec sp, double rel, int max_it,
-                      int check_every, int *iters, int *applies) {
+bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, int max_it, int check_every,
+                      int *iters, int *applies) {
     T *e = (T *)(c.w + c.L.e), *r = (T *)(c.w + c.L.r), *p = (T *)(c.w + c.L.p);
     T *q = (T *)(c.w + c.L.q), *z = (T *)(c.w + c.L.z);
     double *part = (double *)(c.w + c.L.part);
@@ -119,7 +118,7 @@ bri_status inner_cgne(const Ctx &c, const void *W, bri_prec wp, bri_prec sp, dou
     const size_t bytes = c.n * c.nrhs * sizeof(T);
 
     BRI_HIP(zero(c.n * c.nrhs, e, c.st), "zero");
-    BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
+    BRI_TRY(apply_op(c.d, op, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
     ++*applies;
     BRI_TRY(norm2<T>(c, r, rr2));
     BRI_TRY(norm2<T>(c, z, zz2));
@@ -127,12 +126,12 @@ bri_status inner_cgne(const Ctx &c, const void *W, bri_prec wp, bri_prec sp, dou
     BRI_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, c.st), "copy");
     std::vector<double> hs(7 * c.nrhs);
     for (int it = 1; it <= max_it; ++it) {
-        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, p, q, c.nrhs, c.st, c.dag));
+        BRI_TRY(apply_op(c.d, op, sp, c.mass, p, q, c.nrhs, c.st, c.dag));
         BRI_TRY(norm2<T>(c, q, qq2));
         BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
         BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
         BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
-        BRI_TRY(apply_impl(c.d, BRI_STORED, W, wp, c.noff, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
+        BRI_TRY(apply_op(c.d, op, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
         BRI_TRY(norm2<T>(c, z, zz2));
         BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
         BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
@@ -154,28 +153,15 @@ bri_status inner_cgne(const Ctx &c, const void *W, bri_prec wp, bri_prec sp, dou
 }
 
 }  // namespace
-}  // namespace bri
 
-using namespace bri;
-
-extern "C" {
-
-size_t bri_solve_workspace_bytes(bri_dims d, const bri_solve_params *p, int32_t nrhs) {
-    Geom g;
-    if (!p || !dims_ok(d, &g) || nrhs < 1 || nrhs > BRI_MAX_RHS) return 0;
-    const size_t tb = p->inner_prec == BRI_F64 ? sizeof(double) : sizeof(float);
-    return layout((size_t)24 * g.V, nrhs, tb).total;
-}
-
-bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_hi, const void *W_lo,
-                          double mass, const double *b, double *x, int32_t nrhs, void *work,
-                          size_t work_bytes, bri_solve_stats *stats, void *stream) {
-    g_last_error.clear();
+// the solver for operators hi (FP64) and lo (inner precision, used when mixed)
+static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc &hi, const OpDesc &lo, double mass,
+                      const double *b, double *x, int32_t nrhs, void *work, size_t work_bytes,
+                      bri_solve_stats *stats, void *stream) {
     Geom g;
     if (!p || !stats) return fail(BRI_E_ARG, "null params or stats");
     if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
     if (nrhs < 1 || nrhs > BRI_MAX_RHS) return fail(BRI_E_ARG, "nrhs must be in [1, %d]", BRI_MAX_RHS);
-    if (p->n_offsets != 40 && p->n_offsets != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
     if (!(p->tol > 0.0) || p->max_iter < 1 || p->max_outer < 1 || p->check_every < 1)
         return fail(BRI_E_ARG, "invalid solver parameters");
     const bool mixed = p->inner_prec != BRI_F64;
@@ -183,7 +169,9 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
         return fail(BRI_E_ARG, "invalid inner precision");
     if (mixed && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
         return fail(BRI_E_ARG, "inner_tol must be in (0, 1)");
-    if (!aligned(W_hi) || !aligned(b) || !aligned(x) || (mixed && !aligned(W_lo)))
+    if (hi.wp != BRI_F64) return fail(BRI_E_ARG, "the outer operator must have FP64 transporters");
+    if (mixed && lo.wp != p->inner_prec) return fail(BRI_E_ARG, "inner operator precision differs from inner_prec");
+    if (!aligned(hi.W) || !aligned(b) || !aligned(x) || (mixed && !aligned(lo.W)))
         return fail(BRI_E_ARG, "null or misaligned pointer");
     const size_t n = (size_t)24 * g.V;
     const Layout L = layout(n, nrhs, mixed ? sizeof(float) : sizeof(double));
@@ -193,7 +181,7 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     if (overlap(b, vb, x, vb) || overlap(work, L.total, x, vb) || overlap(work, L.total, b, vb))
         return fail(BRI_E_ARG, "b, x and the workspace must not overlap");
 
-    Ctx c{d, g, n, nrhs, p->n_offsets, mass, p->dagger != 0, (hipStream_t)stream, (char *)work, L};
+    Ctx c{d, g, n, nrhs, mass, p->dagger != 0, (hipStream_t)stream, (char *)work, L};
     *stats = bri_solve_stats{};
     double *r_hi = (double *)(c.w + L.r_hi), *dx = (double *)(c.w + L.dx_hi);
     double *part = (double *)(c.w + L.part), *red = (double *)(c.w + L.red);
@@ -208,7 +196,7 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     int iters = 0, applies = 0;
     bool converged = false;
     for (int outer = 0;; ++outer) {
-        BRI_TRY(apply_impl(d, BRI_STORED, W_hi, BRI_F64, c.noff, BRI_F64, mass, x, dx, nrhs, c.st, c.dag));
+        BRI_TRY(apply_op(d, hi, BRI_F64, mass, x, dx, nrhs, c.st, c.dag));
         ++applies;
         BRI_HIP(residual(n, nrhs, b, dx, r_hi, part, nb, c.st), "residual");
         BRI_HIP(dot_finish(nrhs, part, nb, red, c.st), "residual finish");
@@ -236,8 +224,8 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
         if (mixed) {
             float *r_lo = (float *)(c.w + L.r);
             BRI_HIP((convert<double, float>(n, nrhs, r_hi, r_lo, scale, c.st)), "convert");
-            BRI_TRY(inner_cgne<float>(c, W_lo, p->inner_prec, BRI_F32, p->inner_tol,
-                                      p->max_iter - iters, p->check_every, &it, &applies));
+            BRI_TRY(inner_cgne<float>(c, lo, BRI_F32, p->inner_tol, p->max_iter - iters, p->check_every, &it,
+                                      &applies));
             BRI_HIP(accum<float>(n, nrhs, (const float *)(c.w + L.e), x, unscale, c.st), "accumulate");
         } else {
             // plain FP64: aim the inner solve at the final tolerance of the worst column
@@ -246,8 +234,8 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
                 if (sc[i] > 0.0) worst = std::fmax(worst, std::sqrt(rr[2 * i] / std::fmax(bb[2 * i], 1e-300)));
             const double rel = worst > 0.0 ? std::fmin(0.5, 0.5 * p->tol / worst) : 0.5;
             BRI_HIP((convert<double, double>(n, nrhs, r_hi, (double *)(c.w + L.r), scale, c.st)), "convert");
-            BRI_TRY(inner_cgne<double>(c, W_hi, BRI_F64, BRI_F64, rel, p->max_iter - iters,
-                                       p->check_every, &it, &applies));
+            BRI_TRY(inner_cgne<double>(c, hi, BRI_F64, rel, p->max_iter - iters, p->check_every, &it,
+                                       &applies));
             BRI_HIP(accum<double>(n, nrhs, (const double *)(c.w + L.e), x, unscale, c.st), "accumulate");
         }
         iters += it;
@@ -258,6 +246,45 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     stats->converged = converged ? 1 : 0;
     if (!converged) return fail(BRI_E_NOCONV, "not converged after %d iterations, %d outer cycles", iters, stats->outer);
     return BRI_OK;
+}
+
+}  // namespace bri
+
+using namespace bri;
+
+extern "C" {
+
+size_t bri_solve_workspace_bytes(bri_dims d, const bri_solve_params *p, int32_t nrhs) {
+    Geom g;
+    if (!p || !dims_ok(d, &g) || nrhs < 1 || nrhs > BRI_MAX_RHS) return 0;
+    const size_t tb = p->inner_prec == BRI_F64 ? sizeof(double) : sizeof(float);
+    return layout((size_t)24 * g.V, nrhs, tb).total;
+}
+
+bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_hi, const void *W_lo,
+                          double mass, const double *b, double *x, int32_t nrhs, void *work,
+                          size_t work_bytes, bri_solve_stats *stats, void *stream) {
+    g_last_error.clear();
+    if (!p) return fail(BRI_E_ARG, "null params or stats");
+    if (p->n_offsets != 40 && p->n_offsets != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
+    const OpDesc hi{W_hi, BRI_F64, p->n_offsets, 3, nullptr};
+    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr};
+    return solve_core(d, p, hi, lo, mass, b, x, nrhs, work, work_bytes, stats, stream);
+}
+
+bri_status bri_solve_cgne_op(bri_dims d, const bri_solve_params *p, const bri_operator *op_hi,
+                             const bri_operator *op_lo, double mass, const double *b, double *x, int32_t nrhs,
+                             void *work, size_t work_bytes, bri_solve_stats *stats, void *stream) {
+    g_last_error.clear();
+    if (!p) return fail(BRI_E_ARG, "null params or stats");
+    OpDesc hi{}, lo{};
+    bri_status s = op_from_public(op_hi, &hi);
+    if (s != BRI_OK) return s;
+    if (p->inner_prec != BRI_F64) {
+        s = op_from_public(op_lo, &lo);
+        if (s != BRI_OK) return s;
+    }
+    return solve_core(d, p, hi, lo, mass, b, x, nrhs, work, work_bytes, stats, stream);
 }
 
 }  // extern "C"

@@ -92,4 +92,39 @@ __device__ __forceinline__ void colour_spin_accum(cx<A> acc[4][3], const cx<A> w
 }
 
 
+// ------------------------------------------------------------------ clover term
+// Per site two Hermitian 6x6 blocks (spins 0,1 and spins 2,3; local index
+// 3*s + colour), stored as [2][18][V] complex: planes 0..2 hold the real
+// diagonal in pairs (M_00, M_11), (M_22, M_33), (M_44, M_55), planes 3..17 the
+// entries M_ij, i < j, row by row.
+__host__ __device__ constexpr int clover_plane(int i, int j) {
+    // number of strictly-upper entries in rows 0..i-1 of a 6x6 matrix, plus column offset
+    return 3 + (i * (11 - i)) / 2 + (j - i - 1);
+}
+
+template <typename A, typename CS>
+__device__ __forceinline__ void clover_load_block(const CS *C, size_t V, int site, int b, cx<A> (&cl)[18]) {
+#pragma unroll
+    for (int p = 0; p < 18; ++p) cl[p] = ldnt<A>(C + (size_t)(b * 18 + p) * V + site);
+}
+
+// acc[s][a] += (M_b x)_(3s+a - 6b) for block b, x its six spin-colour components
+template <typename A>
+__device__ __forceinline__ void clover_accum_block(const cx<A> (&cl)[18], const cx<A> (&x)[6], int b,
+                                                   cx<A> (&acc)[4][3]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const int c = 6 * b + i;
+        cx<A> y = acc[c / 3][c % 3];
+        const A d = (i % 2 == 0) ? cl[i / 2].re : cl[i / 2].im;
+        y = caxpy(d, x[i], y);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            if (j > i) y = cmac(y, cl[clover_plane(i, j)], x[j]);
+            if (j < i) y = cmacc(y, cl[clover_plane(j, i)], x[j]);
+        }
+        acc[c / 3][c % 3] = y;
+    }
+}
+
 }  // namespace bri

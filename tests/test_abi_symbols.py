@@ -60,7 +60,16 @@ def test_size_queries(lib):
     assert lib.bri_transporter_bytes(d, 1, 39) == 0
     assert lib.bri_build_workspace_bytes(d, 0, 40) == 0
     assert lib.bri_build_workspace_bytes(d, 1, 80) == V * 40 * 9 * 16
-    assert lib.bri_abi_version() == 1
+    assert lib.bri_abi_version() == 2
+    # production-operator forms: two-row SU(3) store and the clover term
+    assert lib.bri_transporter_bytes_ex(d, 1, 80, 0) == V * 80 * 9 * 8
+    assert lib.bri_transporter_bytes_ex(d, 1, 80, 1) == V * 80 * 9 * 8
+    assert lib.bri_transporter_bytes_ex(d, 1, 80, 2) == V * 80 * 6 * 8
+    assert lib.bri_transporter_bytes_ex(d, 1, 80, 3) == 0
+    assert lib.bri_build_workspace_bytes_ex(d, 0, 40, 1) == 0
+    assert lib.bri_build_workspace_bytes_ex(d, 0, 40, 2) == V * 40 * 9 * 16
+    assert lib.bri_clover_bytes(d, 1) == V * 36 * 8
+    assert lib.bri_clover_bytes(d, 0) == V * 36 * 16
     d.L[3] = 1
     assert lib.bri_spinor_bytes(d, 1, 1) == 0
 
@@ -78,6 +87,17 @@ def test_argument_errors_without_device(lib):
     st = lib.bri_apply(d, 0, None, 1, 80, 1, 0.1, None, None, 1, None)
     assert st == -1
     assert b"pointer" in lib.bri_last_error()
+    assert lib.bri_project_su3(-1, None, None, None) == -1
+    assert lib.bri_project_su3(0, None, None, None) == 0
+    assert lib.bri_apply_op(d, None, 1, 0.1, None, None, 1, 0, None) == -1
+    assert b"operator" in lib.bri_last_error()
+    op = plib.bri_operator()
+    op.w_form = 7
+    assert lib.bri_apply_op(d, ctypes.byref(op), 1, 0.1, None, None, 1, 0, None) == -1
+    assert b"form" in lib.bri_last_error()
+    assert lib.bri_build_transporters_ex(d, None, None, 1, 80, 2, None, 0, None) == -1
+    assert lib.bri_ape_smear(d, None, None, 0.72, None) == -1
+    assert lib.bri_build_clover(d, None, 1.0, None, 1, None) == -1
     d.L[0] = 1
     st = lib.bri_build_transporters(d, None, None, 0, 80, None, 0, None)
     assert st == -1
