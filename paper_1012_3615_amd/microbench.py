@@ -5,7 +5,9 @@
                    tile12_w80_f32 recompute_f32 stream
 
 Each variant builds its inputs (links exp(i 0.3 H), seed 4001; Gaussian
-spinors; the 12 point sources for the 12-RHS variant), runs one untimed
+spinors; the 12 point sources for the 12-RHS variant; for the production
+operator forms prod*: one APE step, back-projected transporters whole or as
+two rows, and the clover term), runs one untimed
 launch, then `reps` launches timed with HIP events on the current stream,
 and prints one line per variant.  `stream` times a plain device read of a
 8 GiB buffer (torch sum) and a 2 GiB copy, as a reference for the
@@ -38,6 +40,16 @@ VARIANTS = {
     "tile12_w80_f64": (bri.STORED, bri.F64, bri.F64, 80, 12, 1, 2),
     "recompute_f32": (bri.RECOMPUTE, bri.F32, bri.F32, 80, 1, 1, 1),
     "recompute_f64": (bri.RECOMPUTE, bri.F64, bri.F64, 80, 1, 1, 1),
+}
+
+# production operator (Sec. 5): name -> (w_prec, s_prec, transporter form, clover, nrhs)
+PROD = {
+    "prod2c_f32": (bri.F32, bri.F32, bri.W_SU3_2ROW, True, 1),
+    "prod3c_f32": (bri.F32, bri.F32, bri.W_SU3, True, 1),
+    "prod2_f32": (bri.F32, bri.F32, bri.W_SU3_2ROW, False, 1),
+    "prod2c_f16": (bri.F16, bri.F32, bri.W_SU3_2ROW, True, 1),
+    "prod2c_f64": (bri.F64, bri.F64, bri.W_SU3_2ROW, True, 1),
+    "prod2c12_f32": (bri.F32, bri.F32, bri.W_SU3_2ROW, True, 12),
 }
 
 
@@ -75,6 +87,10 @@ def run(dims, names, reps=3, mass=0.1):
             out.append({"variant": "copy_2GiB", "ms": ms, "GBs": 2 * a.numel() / ms / 1e6})
             del a, b
             continue
+        if name in PROD:
+            out.append(_run_prod(dims, name, Ud, U64, psi, reps, mass))
+            torch.cuda.empty_cache()
+            continue
         variant, wp, sp, noff, nrhs, kernel, rblk = VARIANTS[name]
         if nrhs == 12:
             src = torch.from_numpy(synth.point_sources(dims)).to("cuda")
@@ -101,6 +117,26 @@ def run(dims, names, reps=3, mass=0.1):
         del Wv, x, y
         torch.cuda.empty_cache()
     return out
+
+
+def _run_prod(dims, name, Ud, U64, psi, reps, mass):
+    wp, sp, form, clover, nrhs = PROD[name]
+    V = bri.volume(dims)
+    Us = bri.bri_ape_smear(dims, U64, 0.72)
+    W = bri.bri_build_transporters_ex(dims, Us, wp, 80, form)
+    C = bri.bri_build_clover(dims, Us, 1.0, sp) if clover else None
+    op = bri.Operator(W, form, C)
+    if nrhs == 12:
+        src = torch.from_numpy(synth.point_sources(dims)).to("cuda")
+        x = bri.bri_pack_spinor(dims, src, sp)
+        del src
+    else:
+        x = bri.bri_pack_spinor(dims, psi, sp)
+    y = torch.empty_like(x)
+    ms = _time(lambda: bri.bri_apply_op(dims, op, x, mass, out=y), reps)
+    rows = 6 if form == bri.W_SU3_2ROW else 9
+    byts = V * (80 * rows * CB[wp] + nrhs * 2 * 12 * CB[sp] + (36 * CB[sp] if clover else 0))
+    return {"variant": name, "ms": ms, "alg_GBs": byts / ms / 1e6, "alg_bytes_per_site": byts // V}
 
 
 def main():
