@@ -32,9 +32,11 @@ without blocking or fusion:
 * ``smearing``    - one APE smearing step (Eq. def_ape);
 * ``clover``      - the clover term of Eq. def_pref (clover-leaf field strength);
 * ``production``  - the operator of Sec. 5: back-projected transporters plus
-  the clover term.
+  the clover term;
+* ``overlap``     - the overlap operator with the Brillouin kernel (Sec. 7),
+  dense and exact for tiny lattices.
 
 Parity status of each function is listed in the module docstrings.
 """
 from . import (constants, gamma, lattice, transporters, dirac, factorized, free, solver, grad,  # noqa: F401
-               projection, smearing, clover, production)
+               projection, smearing, clover, production, overlap)
