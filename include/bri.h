@@ -291,6 +291,60 @@ bri_status bri_solve_cgne_op(bri_dims d, const bri_solve_params *p, const bri_op
                              int32_t nrhs, void *work, size_t work_bytes, bri_solve_stats *stats,
                              void *stream);
 
+/* ---- overlap operator with the Brillouin kernel (Sec. 7) ------------------
+ *   D_ov,m = (1 - m/(2 rho)) rho [1 + gamma5 sign(H)] + m,   H = gamma5 D(-rho),
+ * (Eqs. def_over and def_mass, a = 1, 0 < rho < 2), D(-rho) the kernel operator
+ * `op` at mass -rho.  H is Hermitian and H^2 = D^dag D.  All fields are FP64
+ * SoA spinors and `op` must have FP64 transporters (and an FP64 clover term if
+ * any).  The spectrum of A = D^dag D is estimated by Lanczos (the Ritz values
+ * of Sec. 7.3); sign(H) = H (H^2)^{-1/2} is evaluated as gamma5 D p(A) with p
+ * the Chebyshev interpolant of x^{-1/2} on [lo, hi], which must contain the
+ * spectrum of A (outside the optional low modes). */
+
+/* k Lanczos steps on A = D^dag D (op at `mass`) from the FP64 field v0 (one
+ * field, need not be normalised).  Host outputs: alpha[0..k-1] (diagonal of
+ * the tridiagonal T), beta[0..k-1] with beta[0] = |v0| and beta[j] the
+ * off-diagonal (j, j-1) element; *k_done = steps performed (fewer than k only
+ * if an invariant subspace was found).  basis: NULL, or caller memory for k
+ * fields ([k][12][V]) in which the Lanczos vectors are kept; each new vector
+ * is then re-orthogonalised against all kept ones (two classical Gram-Schmidt
+ * passes, each one batched dot launch and one fused update), otherwise only
+ * the three-term recurrence is used.  Synchronises the stream twice per step
+ * (alpha and beta go to the host).  Workspace: bri_lanczos_workspace_bytes(d, k). */
+size_t bri_lanczos_workspace_bytes(bri_dims d, int32_t k);
+bri_status bri_lanczos(bri_dims d, const bri_operator *op, double mass, int32_t k, const double *v0,
+                       double *alpha, double *beta, double *basis, int32_t *k_done, void *work,
+                       size_t work_bytes, void *stream);
+
+/* Ritz values: the eigenvalues of the k x k symmetric tridiagonal matrix
+ * (alpha, beta[1..k-1]) in ascending order, by bisection on Sturm counts
+ * (host only, no device work).  With filter = 1, numerically equal values
+ * (relative 1e-10) are kept once and a simple value that is also an eigenvalue
+ * of the matrix without its first row and column is dropped as spurious
+ * (the Cullum-Willoughby test for Lanczos without re-orthogonalisation).
+ * out: host array of k doubles; *n_out: number written. */
+bri_status bri_ritz_values(int32_t k, const double *alpha, const double *beta, int32_t filter, double *out,
+                           int32_t *n_out);
+
+/* out = sign(H) psi for nrhs FP64 fields, H = gamma5 D (op at `mass`):
+ *   sign(H) psi = sum_i s_i v_i <v_i, psi> + gamma5 D p(A) (psi - sum_i v_i <v_i, psi>),
+ * with n_low >= 0 orthonormal eigenvectors v_i of H (low_vecs, FP64
+ * [n_low][12][V]) and their eigenvalues (low_evals, host; s_i = their sign),
+ * and p of the given degree on [lo, hi].  Cost: 2*degree + 3 applications of D.
+ * *approx_err (host, may be NULL): max over [lo, hi] of |1 - sqrt(x) p(x)|.
+ * psi and out must not overlap.  Workspace: bri_sign_workspace_bytes(d, nrhs). */
+size_t bri_sign_workspace_bytes(bri_dims d, int32_t nrhs);
+bri_status bri_sign_h(bri_dims d, const bri_operator *op, double mass, double lo, double hi, int32_t degree,
+                      int32_t n_low, const double *low_vecs, const double *low_evals, const double *psi,
+                      double *out, int32_t nrhs, double *approx_err, void *work, size_t work_bytes,
+                      void *stream);
+
+/* out = D_ov,m psi with sign(H) from bri_sign_h at mass -rho (same arguments). */
+bri_status bri_overlap_apply(bri_dims d, const bri_operator *op, double rho, double m, double lo, double hi,
+                             int32_t degree, int32_t n_low, const double *low_vecs, const double *low_evals,
+                             const double *psi, double *out, int32_t nrhs, double *approx_err, void *work,
+                             size_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

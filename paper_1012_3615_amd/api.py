@@ -383,6 +383,93 @@ def bri_solve_cgne_op(dims, op_hi, b, mass, params, op_lo=None, x=None, raise_on
     return x, info
 
 
+# ------------------------------------------------------------------ overlap operator (Sec. 7)
+def bri_lanczos(dims, op, mass, k, v0, keep_basis=False):
+    """k Lanczos steps on D^dag D (op at `mass`) from the FP64 field v0 [1,12,V,2].
+    Returns (alpha, beta, basis or None) with numpy alpha, beta truncated to
+    the steps performed."""
+    import numpy as np
+    _need_cuda(v0)
+    _shape(v0, (1, 12, volume(dims), 2), "v0")
+    if prec_of(v0) != F64:
+        raise ValueError("the Lanczos process works on FP64 fields")
+    alpha = np.zeros(k)
+    beta = np.zeros(k)
+    basis = torch.empty((k, 12, volume(dims), 2), dtype=torch.float64, device=v0.device) if keep_basis else None
+    nbytes = _lib_handle.bri_lanczos_workspace_bytes(_dims(dims), int(k))
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=v0.device)
+    done = ctypes.c_int32(0)
+    o = op.struct(dims)
+    _check(_lib_handle.bri_lanczos(_dims(dims), ctypes.byref(o), float(mass), int(k), _ptr(v0),
+                                   alpha.ctypes.data_as(ctypes.c_void_p), beta.ctypes.data_as(ctypes.c_void_p),
+                                   _ptr(basis), ctypes.byref(done), _ptr(work), nbytes, _stream()), "bri_lanczos")
+    n = done.value
+    return alpha[:n], beta[:n], (basis[:n] if basis is not None else None)
+
+
+def bri_ritz_values(alpha, beta, filter=True):
+    """Eigenvalues of the Lanczos tridiagonal (ascending), optionally with
+    spurious copies removed."""
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    out = np.zeros(len(a))
+    n = ctypes.c_int32(0)
+    _check(_lib_handle.bri_ritz_values(len(a), a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+                                       int(bool(filter)), out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)),
+           "bri_ritz_values")
+    return out[:n.value]
+
+
+def _lowmodes(dims, low_vecs, low_evals):
+    import numpy as np
+    if low_vecs is None or len(low_evals) == 0:
+        return 0, None, None
+    _need_cuda(low_vecs)
+    _shape(low_vecs, (len(low_evals), 12, volume(dims), 2), "low_vecs")
+    ev = np.ascontiguousarray(low_evals, dtype=np.float64)
+    return len(ev), low_vecs, ev
+
+
+def bri_sign_h(dims, op, mass, psi, lo, hi, degree, low_vecs=None, low_evals=(), out=None):
+    """sign(gamma5 D) psi for FP64 fields; returns (out, approx_err)."""
+    _need_cuda(psi, out)
+    _shape(psi, (psi.shape[0], 12, volume(dims), 2), "psi")
+    if prec_of(psi) != F64:
+        raise ValueError("sign(H) works on FP64 fields")
+    n_low, lv, ev = _lowmodes(dims, low_vecs, low_evals)
+    out = out if out is not None else torch.empty_like(psi)
+    nbytes = _lib_handle.bri_sign_workspace_bytes(_dims(dims), psi.shape[0])
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=psi.device)
+    err = ctypes.c_double(0.0)
+    o = op.struct(dims)
+    _check(_lib_handle.bri_sign_h(_dims(dims), ctypes.byref(o), float(mass), float(lo), float(hi), int(degree),
+                                  n_low, _ptr(lv), ev.ctypes.data_as(ctypes.c_void_p) if ev is not None else None,
+                                  _ptr(psi), _ptr(out), psi.shape[0], ctypes.byref(err), _ptr(work), nbytes,
+                                  _stream()), "bri_sign_h")
+    return out, err.value
+
+
+def bri_overlap_apply(dims, op, psi, rho, m, lo, hi, degree, low_vecs=None, low_evals=(), out=None):
+    """D_ov,m psi (Eqs. def_over, def_mass) for FP64 fields; returns (out, approx_err)."""
+    _need_cuda(psi, out)
+    _shape(psi, (psi.shape[0], 12, volume(dims), 2), "psi")
+    if prec_of(psi) != F64:
+        raise ValueError("the overlap operator works on FP64 fields")
+    n_low, lv, ev = _lowmodes(dims, low_vecs, low_evals)
+    out = out if out is not None else torch.empty_like(psi)
+    nbytes = _lib_handle.bri_sign_workspace_bytes(_dims(dims), psi.shape[0])
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=psi.device)
+    err = ctypes.c_double(0.0)
+    o = op.struct(dims)
+    _check(_lib_handle.bri_overlap_apply(_dims(dims), ctypes.byref(o), float(rho), float(m), float(lo), float(hi),
+                                         int(degree), n_low, _ptr(lv),
+                                         ev.ctypes.data_as(ctypes.c_void_p) if ev is not None else None,
+                                         _ptr(psi), _ptr(out), psi.shape[0], ctypes.byref(err), _ptr(work),
+                                         nbytes, _stream()), "bri_overlap_apply")
+    return out, err.value
+
+
 # ------------------------------------------------------------------ gradient
 def bri_grad_links(dims, U_soa, chi, psi, scale=1.0):
     """scale * dS/dU (FP64 SoA links) for S = Re sum_rhs <chi, D psi>."""
