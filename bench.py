@@ -69,13 +69,20 @@ def timed_launches(torch, fn, steps, warmup):
     return total, [s.elapsed_time(e) for s, e in ev]
 
 
-def cpu_baseline(u, psi, target_s=15.0):
+def cpu_baseline(u, psi, got, target_s=15.0):
     """The CPU oracle as it stands (plain numpy, FP64), on sampled sites of the
-    same 32^3 x 64 workload, scaled to applications/s of the whole lattice."""
+    same 32^3 x 64 workload, scaled to applications/s of the whole lattice;
+    also the relative error of the timed GPU output `got` (canonical layout)
+    at 64 random sites.  Returns (baseline dict, spot error)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import dirac
     V = int(np.prod(DIMS))
+    rs = np.random.default_rng(5)
+    spot = np.stack([rs.integers(0, L, 64) for L in DIMS], axis=1)
+    ref = dirac.apply_at(u, psi, MASS, spot)
+    gs = np.stack([got[t, z, y, x] for x, y, z, t in spot])
+    spot_err = float(np.linalg.norm(gs - ref) / np.linalg.norm(ref))
     rng = np.random.default_rng(99)
     with threadpool_limits(limits=1):
         probe = np.stack([rng.integers(0, L, 256) for L in DIMS], axis=1)
@@ -89,7 +96,7 @@ def cpu_baseline(u, psi, target_s=15.0):
         dt = time.perf_counter() - t0
     return {"value": (n / dt) / V, "unit": "applies/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} random sites of the 32^3x64 lattice via the pointwise oracle "
-                      f"(FP64 numpy, single thread), {dt:.1f} s, scaled by sites/V"}
+                      f"(FP64 numpy, single thread), {dt:.1f} s, scaled by sites/V"}, spot_err
 
 
 def traffic_from_profile(launch_bytes_alg):
@@ -282,6 +289,44 @@ def production_operator(torch, bri, U64, dev, psi, tol=1e-10):
     return out
 
 
+def overlap_kernel(torch, bri, dev):
+    """The overlap kernel of Sec. 7 at 24^3 x 48 (links eps 0.4, seed 3001):
+    the Brillouin operator with one APE step and SU(3) back-projected (two-row)
+    transporters, c_SW = 0, at mass -rho, rho = 1.  300 Lanczos steps on
+    D^dag D (three-term recurrence, spurious copies filtered) give the Ritz
+    values of Sec. 7.3 (1st, 10th, largest); sign(H) is then applied to 1e-10
+    on [0.9 r_1, 1.05 r_max] and timed."""
+    import numpy as np
+    import synth
+    dims, rho = (24, 24, 24, 48), 1.0
+    u = synth.gauge_links(dims, 0.4, 3001)
+    U = bri.bri_pack_links(dims, torch.from_numpy(u).to(dev), bri.F64)
+    del u
+    Us = bri.bri_ape_smear(dims, U, 0.72)
+    op = bri.Operator(bri.bri_build_transporters_ex(dims, Us, bri.F64, 80, bri.W_SU3_2ROW), bri.W_SU3_2ROW)
+    del U, Us
+    v0 = bri.bri_pack_spinor(dims, torch.from_numpy(synth.gaussian_spinor(dims, 3003, 1)).to(dev), bri.F64)
+    k = 300
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, b, _ = bri.bri_lanczos(dims, op, -rho, k, v0)
+    t_lanczos = time.perf_counter() - t0
+    r = bri.bri_ritz_values(a, b)
+    lo, hi = 0.9 * r[0], 1.05 * r[-1]
+    deg = bri.sign_degree(lo, hi, 1e-10)
+    out = torch.empty_like(v0)
+    _, p = timed_launches(torch, lambda: bri.bri_sign_h(dims, op, -rho, v0, lo, hi, deg, out=out,
+                                                        with_error=False), 3, 1)
+    ms = float(np.mean(p))
+    return {"lattice": list(dims), "kernel": "Brillouin, 1 APE step (0.72), SU(3) two-row W, c_SW = 0",
+            "rho": rho, "lanczos_steps": k, "lanczos_s": t_lanczos, "ritz_kept": int(len(r)),
+            "ritz_1st": float(r[0]), "ritz_10th": float(r[9]), "ritz_largest": float(r[-1]),
+            "condition": float(r[-1] / r[0]), "condition_without_9_lowest": float(r[-1] / r[9]),
+            "sign_interval": [lo, hi], "sign_degree_1e-10": deg,
+            "sign_error_bound": bri.bri_sign_approx_error(lo, hi, deg),
+            "sign_ms": ms, "ms_per_D_apply_in_sign": ms / (2 * deg + 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,14 +376,8 @@ def main():
     launch_bytes = bps * V
     achieved = launch_bytes / (per_ms * 1e-3) / 1e9
 
-    # spot parity of the timed configuration against the pointwise oracle
-    from oracle import dirac
-    rng = np.random.default_rng(5)
-    sites = np.stack([rng.integers(0, L, 64) for L in DIMS], axis=1)
+    # the timed output, kept for the spot parity check of the CPU-baseline leg
     got = bri.bri_unpack_spinor(DIMS, out).cpu().numpy()[0]
-    ref = dirac.apply_at(u, psi[0], MASS, sites)
-    gs = np.stack([got[t, z, y, x] for x, y, z, t in sites])
-    spot_err = float(np.linalg.norm(gs - ref) / np.linalg.norm(ref))
 
     res = {
         "metric": "D_B applies/sec at 32^3x64 (FP32, stored 80 transporters)",
@@ -363,7 +402,6 @@ def main():
                      "alg_bytes_per_site": bps, "alg_bytes_per_launch": launch_bytes,
                      "kernel_ms": per_ms},
         "gflops": FLOPS_PER_SITE * V / (per_ms * 1e-3) / 1e9,
-        "spot_parity_rel_err": spot_err,
         "build_transporters_ms": build_ms,
         "input_generation_s": gen_s,
     }
@@ -430,11 +468,13 @@ def main():
         del W, out
         torch.cuda.empty_cache()
         res["production_operator"] = production_operator(torch, bri, U64, dev, psi)
+        torch.cuda.empty_cache()
+        res["overlap_kernel_24x24x24x48"] = overlap_kernel(torch, bri, dev)
 
     if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(u, psi[0])
+        res["cpu_baseline"], res["spot_parity_rel_err"] = cpu_baseline(u, psi[0], got)
     else:
-        res["cpu_baseline"] = None
+        res["cpu_baseline"], res["spot_parity_rel_err"] = None, None
     print(json.dumps(res), flush=True)
 
 

@@ -334,6 +334,9 @@ bri_status bri_ritz_values(int32_t k, const double *alpha, const double *beta, i
  * *approx_err (host, may be NULL): max over [lo, hi] of |1 - sqrt(x) p(x)|.
  * psi and out must not overlap.  Workspace: bri_sign_workspace_bytes(d, nrhs). */
 size_t bri_sign_workspace_bytes(bri_dims d, int32_t nrhs);
+/* The error bound *err of the interpolant of the given degree on [lo, hi]
+ * (host only), to choose the degree before applying. */
+bri_status bri_sign_approx_error(double lo, double hi, int32_t degree, double *err);
 bri_status bri_sign_h(bri_dims d, const bri_operator *op, double mass, double lo, double hi, int32_t degree,
                       int32_t n_low, const double *low_vecs, const double *low_evals, const double *psi,
                       double *out, int32_t nrhs, double *approx_err, void *work, size_t work_bytes,

@@ -421,6 +421,30 @@ def bri_ritz_values(alpha, beta, filter=True):
     return out[:n.value]
 
 
+def bri_sign_approx_error(lo, hi, degree):
+    """max over [lo, hi] of |1 - sqrt(x) p(x)| for the degree-`degree` interpolant."""
+    e = ctypes.c_double(0.0)
+    _check(_lib_handle.bri_sign_approx_error(float(lo), float(hi), int(degree), ctypes.byref(e)),
+           "bri_sign_approx_error")
+    return e.value
+
+
+def sign_degree(lo, hi, target, max_degree=100000):
+    """Smallest degree (doubling from 16, then bisection) whose error bound is below target."""
+    lo_d, d = 0, 16
+    while bri_sign_approx_error(lo, hi, d) >= target:
+        lo_d, d = d, 2 * d
+        if d > max_degree:
+            raise ValueError("the interval needs a degree above max_degree")
+    while d - lo_d > 1:
+        m = (lo_d + d) // 2
+        if bri_sign_approx_error(lo, hi, m) < target:
+            d = m
+        else:
+            lo_d = m
+    return d
+
+
 def _lowmodes(dims, low_vecs, low_evals):
     import numpy as np
     if low_vecs is None or len(low_evals) == 0:
@@ -431,8 +455,9 @@ def _lowmodes(dims, low_vecs, low_evals):
     return len(ev), low_vecs, ev
 
 
-def bri_sign_h(dims, op, mass, psi, lo, hi, degree, low_vecs=None, low_evals=(), out=None):
-    """sign(gamma5 D) psi for FP64 fields; returns (out, approx_err)."""
+def bri_sign_h(dims, op, mass, psi, lo, hi, degree, low_vecs=None, low_evals=(), out=None, with_error=True):
+    """sign(gamma5 D) psi for FP64 fields; returns (out, approx_err) (approx_err
+    None when with_error is False, which skips its host-side evaluation)."""
     _need_cuda(psi, out)
     _shape(psi, (psi.shape[0], 12, volume(dims), 2), "psi")
     if prec_of(psi) != F64:
@@ -445,9 +470,9 @@ def bri_sign_h(dims, op, mass, psi, lo, hi, degree, low_vecs=None, low_evals=(),
     o = op.struct(dims)
     _check(_lib_handle.bri_sign_h(_dims(dims), ctypes.byref(o), float(mass), float(lo), float(hi), int(degree),
                                   n_low, _ptr(lv), ev.ctypes.data_as(ctypes.c_void_p) if ev is not None else None,
-                                  _ptr(psi), _ptr(out), psi.shape[0], ctypes.byref(err), _ptr(work), nbytes,
-                                  _stream()), "bri_sign_h")
-    return out, err.value
+                                  _ptr(psi), _ptr(out), psi.shape[0], ctypes.byref(err) if with_error else None,
+                                  _ptr(work), nbytes, _stream()), "bri_sign_h")
+    return out, (err.value if with_error else None)
 
 
 def bri_overlap_apply(dims, op, psi, rho, m, lo, hi, degree, low_vecs=None, low_evals=(), out=None):

@@ -212,6 +212,40 @@ std::vector<double> tridiag_eigenvalues(int k, const double *a, const double *b)
     return ev;
 }
 
+// Chebyshev interpolant of x^{-1/2} on [lo, hi] at the degree+1 Chebyshev-Gauss
+// nodes: coefficients of T_k((x - mid)/hw)
+std::vector<double> inv_sqrt_coeffs(double lo, double hi, int degree) {
+    const int M = degree + 1;
+    const double hw = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+    std::vector<double> f(M), cf(M);
+    for (int j = 0; j < M; ++j) f[j] = 1.0 / std::sqrt(hw * std::cos(M_PI * (j + 0.5) / M) + mid);
+    for (int kk = 0; kk < M; ++kk) {
+        double s = 0.0;
+        for (int j = 0; j < M; ++j) s += f[j] * std::cos(M_PI * kk * (j + 0.5) / M);
+        cf[kk] = 2.0 * s / M;
+    }
+    cf[0] *= 0.5;
+    return cf;
+}
+
+// max over 20001 equidistant points of [lo, hi] of |1 - sqrt(x) p(x)|
+double inv_sqrt_error(double lo, double hi, const std::vector<double> &cf) {
+    const int N = (int)cf.size() - 1;
+    const double hw = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+    double e = 0.0;
+    for (int i = 0; i <= 20000; ++i) {
+        const double x = lo + (hi - lo) * i / 20000.0, tt = (x - mid) / hw;
+        double u1 = 0.0, u2 = 0.0;
+        for (int kk = N; kk >= 1; --kk) {
+            const double u = cf[kk] + 2.0 * tt * u1 - u2;
+            u2 = u1;
+            u1 = u;
+        }
+        e = std::max(e, std::fabs(1.0 - std::sqrt(x) * (cf[0] + tt * u1 - u2)));
+    }
+    return e;
+}
+
 }  // namespace
 }  // namespace bri
 
@@ -325,6 +359,14 @@ bri_status bri_ritz_values(int32_t k, const double *alpha, const double *beta, i
     return BRI_OK;
 }
 
+bri_status bri_sign_approx_error(double lo, double hi, int32_t degree, double *err) {
+    g_last_error.clear();
+    if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi)) return fail(BRI_E_ARG, "need 0 < lo < hi");
+    if (degree < 0 || degree > 100000 || !err) return fail(BRI_E_ARG, "invalid degree or output");
+    *err = inv_sqrt_error(lo, hi, inv_sqrt_coeffs(lo, hi, degree));
+    return BRI_OK;
+}
+
 size_t bri_sign_workspace_bytes(bri_dims d, int32_t nrhs) {
     Geom g;
     if (!dims_ok(d, &g) || nrhs < 1 || nrhs > BRI_MAX_RHS) return 0;
@@ -360,31 +402,10 @@ bri_status bri_sign_h(bri_dims d, const bri_operator *op, double mass, double lo
     c.part = (double *)(w8 + 5 * fb);
     c.red = (double *)(w8 + 5 * fb + align256(1024 * 2 * sizeof(double)));
 
-    // Chebyshev interpolant of x^{-1/2} on [lo, hi] at the degree+1 Chebyshev-Gauss nodes
-    const int N = degree, M = degree + 1;
+    const int N = degree;
     const double hw = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
-    std::vector<double> f(M), cf(M);
-    for (int j = 0; j < M; ++j) f[j] = 1.0 / std::sqrt(hw * std::cos(M_PI * (j + 0.5) / M) + mid);
-    for (int kk = 0; kk < M; ++kk) {
-        double s = 0.0;
-        for (int j = 0; j < M; ++j) s += f[j] * std::cos(M_PI * kk * (j + 0.5) / M);
-        cf[kk] = 2.0 * s / M;
-    }
-    cf[0] *= 0.5;
-    if (approx_err) {
-        double e = 0.0;
-        for (int i = 0; i <= 20000; ++i) {
-            const double x = lo + (hi - lo) * i / 20000.0, tt = (x - mid) / hw;
-            double u1 = 0.0, u2 = 0.0;
-            for (int kk = N; kk >= 1; --kk) {
-                const double u = cf[kk] + 2.0 * tt * u1 - u2;
-                u2 = u1;
-                u1 = u;
-            }
-            e = std::max(e, std::fabs(1.0 - std::sqrt(x) * (cf[0] + tt * u1 - u2)));
-        }
-        *approx_err = e;
-    }
+    const std::vector<double> cf = inv_sqrt_coeffs(lo, hi, degree);
+    if (approx_err) *approx_err = inv_sqrt_error(lo, hi, cf);
 
     // deflation: P = psi - sum_i v_i <v_i, psi> per right-hand side
     std::vector<double> cr((size_t)nrhs * n_low), ci((size_t)nrhs * n_low);

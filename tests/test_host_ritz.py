@@ -52,3 +52,20 @@ def test_spurious_filter_on_lanczos_without_reorthogonalisation(api):
         assert np.abs(good - x).min() < 1e-8
     for g in good:
         assert np.abs(lam - g).min() < 1e-6
+
+
+def test_sign_error_bound_and_degree(api):
+    """The library's error bound of the x^-1/2 interpolant equals a direct
+    evaluation with numpy's Chebyshev interpolation at the same nodes, and
+    sign_degree returns the smallest degree meeting a target."""
+    lo, hi = 0.02, 2.5
+    for deg in (5, 40, 120):
+        c = np.polynomial.chebyshev.chebinterpolate(
+            lambda t: 1.0 / np.sqrt(0.5 * (hi - lo) * t + 0.5 * (hi + lo)), deg)
+        xs = np.linspace(lo, hi, 20001)
+        p = np.polynomial.chebyshev.chebval((2 * xs - hi - lo) / (hi - lo), c)
+        want = np.max(np.abs(1 - np.sqrt(xs) * p))
+        # agreement up to the rounding of evaluating a degree-120 polynomial (~1e-13)
+        assert abs(api.bri_sign_approx_error(lo, hi, deg) - want) <= 1e-6 * want + 1e-12
+    d = api.sign_degree(lo, hi, 1e-10)
+    assert api.bri_sign_approx_error(lo, hi, d) < 1e-10 <= api.bri_sign_approx_error(lo, hi, d - 1)
