@@ -326,6 +326,21 @@ bri_status bri_lanczos(bri_dims d, const bri_operator *op, double mass, int32_t 
 bri_status bri_ritz_values(int32_t k, const double *alpha, const double *beta, int32_t filter, double *out,
                            int32_t *n_out);
 
+/* The n_low eigenmodes of H = gamma5 D (op at `mass`) of smallest |eigenvalue|:
+ * k re-orthogonalised Lanczos steps on A = H^2 from v0 (basis: caller memory
+ * for k fields), the eigenvectors of the tridiagonal for its n_low smallest
+ * eigenvalues (bisection, inverse iteration), the Ritz vectors X_i, then
+ * Rayleigh-Ritz for H on span{X}.  Outputs: vecs [n_low][12][V] orthonormal
+ * (FP64), evals (host, signed eigenvalues of H by increasing |.|), resid
+ * (host, |H v_i - evals_i v_i|).  The modes are exact only as far as the
+ * residuals say; the cost is O(k^2) field reads for the re-orthogonalisation,
+ * so this is meant for small lattices.  Workspace:
+ * bri_lowmodes_workspace_bytes(d, k, n_low). */
+size_t bri_lowmodes_workspace_bytes(bri_dims d, int32_t k, int32_t n_low);
+bri_status bri_overlap_lowmodes(bri_dims d, const bri_operator *op, double mass, int32_t k, const double *v0,
+                                int32_t n_low, double *basis, double *vecs, double *evals, double *resid,
+                                void *work, size_t work_bytes, void *stream);
+
 /* out = sign(H) psi for nrhs FP64 fields, H = gamma5 D (op at `mass`):
  *   sign(H) psi = sum_i s_i v_i <v_i, psi> + gamma5 D p(A) (psi - sum_i v_i <v_i, psi>),
  * with n_low >= 0 orthonormal eigenvectors v_i of H (low_vecs, FP64

@@ -94,6 +94,9 @@ PROTOTYPES = {
     "bri_lanczos": (_i32, [_D, ctypes.POINTER(bri_operator), _dbl, _i32, _vp, _vp, _vp, _vp,
                            ctypes.POINTER(_i32), _vp, _sz, _vp]),
     "bri_ritz_values": (_i32, [_i32, _vp, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
+    "bri_lowmodes_workspace_bytes": (_sz, [_D, _i32, _i32]),
+    "bri_overlap_lowmodes": (_i32, [_D, ctypes.POINTER(bri_operator), _dbl, _i32, _vp, _i32, _vp, _vp, _vp, _vp,
+                                    _vp, _sz, _vp]),
     "bri_sign_workspace_bytes": (_sz, [_D, _i32]),
     "bri_sign_approx_error": (_i32, [_dbl, _dbl, _i32, ctypes.POINTER(_dbl)]),
     "bri_sign_h": (_i32, [_D, ctypes.POINTER(bri_operator), _dbl, _dbl, _dbl, _i32, _i32, _vp, _vp, _vp, _vp,

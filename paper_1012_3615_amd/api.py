@@ -421,6 +421,28 @@ def bri_ritz_values(alpha, beta, filter=True):
     return out[:n.value]
 
 
+def bri_overlap_lowmodes(dims, op, mass, k, v0, n_low):
+    """The n_low eigenmodes of gamma5 D (op at `mass`) of smallest |eigenvalue|.
+    Returns (vecs [n_low,12,V,2] FP64, evals numpy, residuals numpy)."""
+    import numpy as np
+    _need_cuda(v0)
+    V = volume(dims)
+    _shape(v0, (1, 12, V, 2), "v0")
+    basis = torch.empty((k, 12, V, 2), dtype=torch.float64, device=v0.device)
+    vecs = torch.empty((n_low, 12, V, 2), dtype=torch.float64, device=v0.device)
+    ev = np.zeros(n_low)
+    rs = np.zeros(n_low)
+    nbytes = _lib_handle.bri_lowmodes_workspace_bytes(_dims(dims), int(k), int(n_low))
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=v0.device)
+    o = op.struct(dims)
+    _check(_lib_handle.bri_overlap_lowmodes(_dims(dims), ctypes.byref(o), float(mass), int(k), _ptr(v0), int(n_low),
+                                            _ptr(basis), _ptr(vecs), ev.ctypes.data_as(ctypes.c_void_p),
+                                            rs.ctypes.data_as(ctypes.c_void_p), _ptr(work), nbytes, _stream()),
+           "bri_overlap_lowmodes")
+    del basis
+    return vecs, ev, rs
+
+
 def bri_sign_approx_error(lo, hi, degree):
     """max over [lo, hi] of |1 - sqrt(x) p(x)| for the degree-`degree` interpolant."""
     e = ctypes.c_double(0.0)

@@ -10,6 +10,7 @@
 // All fields are FP64 SoA spinors; A and H use the stored-transporter apply.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <vector>
 
 #include "abi_internal.h"
@@ -108,6 +109,43 @@ __global__ __launch_bounds__(kB) void k_multi_caxpy(size_t ncx, int nv, const do
         }
         w[2 * q] = re;
         w[2 * q + 1] = im;
+    }
+}
+
+// Y_i = sum_{j < nv} C_ij V_j for 8 outputs i0..i0+7 per block row (blockIdx.y),
+// C real [nout][nv] (cplx = 0) or complex [nout][nv][2] (cplx = 1), in device memory
+__global__ __launch_bounds__(kB) void k_combine(size_t ncx, int nv, int nout, const double *__restrict__ Vb,
+                                                const double *__restrict__ C, int cplx, double *Y) {
+    constexpr int G = 8;
+    const int i0 = blockIdx.y * G;
+    for (size_t q = (size_t)blockIdx.x * kB + threadIdx.x; q < ncx; q += (size_t)gridDim.x * kB) {
+        double re[G], im[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) re[g] = im[g] = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            const double vr = Vb[(size_t)j * 2 * ncx + 2 * q], vi = Vb[(size_t)j * 2 * ncx + 2 * q + 1];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int i = i0 + g;
+                if (i >= nout) break;
+                if (cplx) {
+                    const double cr = C[((size_t)i * nv + j) * 2], ci = C[((size_t)i * nv + j) * 2 + 1];
+                    re[g] = fma(cr, vr, fma(-ci, vi, re[g]));
+                    im[g] = fma(cr, vi, fma(ci, vr, im[g]));
+                } else {
+                    const double cr = C[(size_t)i * nv + j];
+                    re[g] = fma(cr, vr, re[g]);
+                    im[g] = fma(cr, vi, im[g]);
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = i0 + g;
+            if (i >= nout) break;
+            Y[(size_t)i * 2 * ncx + 2 * q] = re[g];
+            Y[(size_t)i * 2 * ncx + 2 * q + 1] = im[g];
+        }
     }
 }
 
@@ -210,6 +248,118 @@ std::vector<double> tridiag_eigenvalues(int k, const double *a, const double *b)
         ev[m] = 0.5 * (l + h);
     }
     return ev;
+}
+
+// eigenvector of the symmetric tridiagonal (a, b[1..k-1]) for the eigenvalue
+// theta by inverse iteration: Gaussian elimination with partial pivoting of
+// T - theta 1 (rows swapped where the sub-diagonal entry is larger, which
+// fills a second super-diagonal), three solves from a constant start, each
+// made orthogonal to the vectors in `prev` (earlier members of a cluster)
+std::vector<double> tridiag_eigvec(int k, const double *a, const double *b, double theta,
+                                   const std::vector<std::vector<double>> &prev) {
+    double tn = 0.0;
+    for (int i = 0; i < k; ++i) tn = std::max(tn, std::fabs(a[i]) + (i ? std::fabs(b[i]) : 0.0));
+    const double tiny = std::max(tn, 1e-300) * 1e-15;
+    std::vector<double> d(k), du(k, 0.0), du2(k, 0.0), l(k, 0.0);
+    std::vector<int> swp(k, 0);
+    for (int i = 0; i < k; ++i) {
+        d[i] = a[i] - theta;
+        if (i + 1 < k) du[i] = b[i + 1];
+    }
+    std::vector<double> dl(k, 0.0);
+    for (int i = 0; i + 1 < k; ++i) dl[i] = b[i + 1];
+    for (int i = 0; i + 1 < k; ++i) {
+        if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+            if (d[i] == 0.0) d[i] = tiny;
+            l[i] = dl[i] / d[i];
+            d[i + 1] -= l[i] * du[i];
+        } else {
+            // swap rows i and i+1
+            const double r0 = d[i], r1 = du[i];           // old row i: (d_i, du_i, 0)
+            const double s0 = dl[i], s1 = d[i + 1], s2 = i + 2 < k ? du[i + 1] : 0.0;  // old row i+1
+            d[i] = s0;
+            du[i] = s1;
+            du2[i] = s2;
+            l[i] = r0 / s0;
+            d[i + 1] = r1 - l[i] * s1;
+            if (i + 2 < k) du[i + 1] = -l[i] * s2;
+            swp[i] = 1;
+        }
+    }
+    if (d[k - 1] == 0.0) d[k - 1] = tiny;
+    std::vector<double> y(k, 1.0);
+    for (int it = 0; it < 3; ++it) {
+        // forward: apply the row operations to the right-hand side
+        for (int i = 0; i + 1 < k; ++i) {
+            if (swp[i]) std::swap(y[i], y[i + 1]);
+            y[i + 1] -= l[i] * y[i];
+        }
+        // back substitution with U (diagonal d, super-diagonals du, du2)
+        for (int i = k - 1; i >= 0; --i) {
+            double v = y[i];
+            if (i + 1 < k) v -= du[i] * y[i + 1];
+            if (i + 2 < k) v -= du2[i] * y[i + 2];
+            y[i] = v / (d[i] != 0.0 ? d[i] : tiny);
+        }
+        for (const auto &p : prev) {
+            double dp = 0.0;
+            for (int i = 0; i < k; ++i) dp += p[i] * y[i];
+            for (int i = 0; i < k; ++i) y[i] -= dp * p[i];
+        }
+        double nrm = 0.0;
+        for (double v : y) nrm += v * v;
+        nrm = std::sqrt(nrm);
+        for (double &v : y) v /= nrm;
+    }
+    return y;
+}
+
+// Hermitian n x n eigen-decomposition by cyclic complex Jacobi rotations
+// (each rotation first removes the phase of the off-diagonal element, then
+// applies the real symmetric rotation that zeroes it).  h row-major, z the
+// eigenvectors in its columns, w the eigenvalues.
+void jacobi_herm(int n, std::vector<std::complex<double>> h, std::vector<std::complex<double>> &z,
+                 std::vector<double> &w) {
+    using C = std::complex<double>;
+    z.assign((size_t)n * n, C(0.0, 0.0));
+    for (int i = 0; i < n; ++i) z[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int p = 0; p < n; ++p) {
+            dia += std::abs(h[(size_t)p * n + p]);
+            for (int q = p + 1; q < n; ++q) off += std::norm(h[(size_t)p * n + q]);
+        }
+        if (off <= 1e-34 * dia * dia) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const C hpq = h[(size_t)p * n + q];
+                const double r = std::abs(hpq);
+                if (r == 0.0) continue;
+                const C ph = std::conj(hpq) / r;  // e^{-i beta}
+                const double tau = (h[(size_t)q * n + q].real() - h[(size_t)p * n + p].real()) / (2.0 * r);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                // G acts on columns p, q: G_pp = c, G_pq = s, G_qp = -s ph, G_qq = c ph
+                const C gpp = c, gpq = s, gqp = -s * ph, gqq = c * ph;
+                for (int i = 0; i < n; ++i) {  // h <- h G
+                    const C hp = h[(size_t)i * n + p], hq = h[(size_t)i * n + q];
+                    h[(size_t)i * n + p] = hp * gpp + hq * gqp;
+                    h[(size_t)i * n + q] = hp * gpq + hq * gqq;
+                }
+                for (int j = 0; j < n; ++j) {  // h <- G^dag h
+                    const C hp = h[(size_t)p * n + j], hq = h[(size_t)q * n + j];
+                    h[(size_t)p * n + j] = std::conj(gpp) * hp + std::conj(gqp) * hq;
+                    h[(size_t)q * n + j] = std::conj(gpq) * hp + std::conj(gqq) * hq;
+                }
+                for (int i = 0; i < n; ++i) {  // z <- z G
+                    const C zp = z[(size_t)i * n + p], zq = z[(size_t)i * n + q];
+                    z[(size_t)i * n + p] = zp * gpp + zq * gqp;
+                    z[(size_t)i * n + q] = zp * gpq + zq * gqq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = h[(size_t)i * n + i].real();
 }
 
 // Chebyshev interpolant of x^{-1/2} on [lo, hi] at the degree+1 Chebyshev-Gauss
@@ -324,6 +474,124 @@ bri_status bri_lanczos(bri_dims d, const bri_operator *op, double mass, int32_t 
         vprev = vcur;
         vcur = vnext;
     }
+    return BRI_OK;
+}
+
+size_t bri_lowmodes_workspace_bytes(bri_dims d, int32_t k, int32_t n_low) {
+    Geom g;
+    if (!dims_ok(d, &g) || k < 1 || n_low < 1 || n_low > k) return 0;
+    const size_t fb = align256((size_t)24 * g.V * n_low * sizeof(double));
+    return bri_lanczos_workspace_bytes(d, k) + 3 * fb + align256((size_t)n_low * k * sizeof(double)) +
+           align256((size_t)n_low * n_low * 2 * sizeof(double)) + align256((size_t)n_low * 1024 * 2 * sizeof(double)) +
+           align256((size_t)n_low * n_low * 2 * sizeof(double));
+}
+
+bri_status bri_overlap_lowmodes(bri_dims d, const bri_operator *op, double mass, int32_t k, const double *v0,
+                                int32_t n_low, double *basis, double *vecs, double *evals, double *resid, void *work,
+                                size_t work_bytes, void *stream) {
+    g_last_error.clear();
+    Ctx c{};
+    if (!dims_ok(d, &c.g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    OV_TRY(check_op(op, &c.op));
+    if (k < 1 || k > 65535 || n_low < 1 || n_low > k) return fail(BRI_E_ARG, "need 1 <= n_low <= k <= 65535");
+    if (!aligned(basis) || !aligned(vecs) || !evals || !resid) return fail(BRI_E_ARG, "null or misaligned pointer");
+    const size_t need = bri_lowmodes_workspace_bytes(d, k, n_low);
+    if (!aligned(work) || work_bytes < need) return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", need);
+    c.d = d;
+    c.mass = mass;
+    c.n = (size_t)24 * c.g.V;
+    c.st = (hipStream_t)stream;
+    const size_t ncx = c.n / 2, nf = c.n * n_low;
+    const size_t lw = bri_lanczos_workspace_bytes(d, k), fb = align256(nf * sizeof(double));
+    char *w8 = (char *)work;
+    double *X = (double *)(w8 + lw), *HX = (double *)(w8 + lw + fb), *T = (double *)(w8 + lw + 2 * fb);
+    char *q8 = w8 + lw + 3 * fb;
+    double *Cr = (double *)q8;
+    q8 += align256((size_t)n_low * k * sizeof(double));
+    double *Cz = (double *)q8;
+    q8 += align256((size_t)n_low * n_low * 2 * sizeof(double));
+    c.part = (double *)q8;
+    q8 += align256((size_t)n_low * 1024 * 2 * sizeof(double));
+    c.red = (double *)q8;
+    if (overlap(basis, (size_t)k * c.n * sizeof(double), work, need) ||
+        overlap(vecs, nf * sizeof(double), work, need) || overlap(vecs, nf * sizeof(double), basis, (size_t)k * c.n * sizeof(double)))
+        return fail(BRI_E_ARG, "basis, vecs and the workspace must not overlap");
+
+    // 1. re-orthogonalised Lanczos with the basis kept
+    std::vector<double> al(k), be(k);
+    int32_t kd = 0;
+    OV_TRY(bri_lanczos(d, op, mass, k, v0, al.data(), be.data(), basis, &kd, work, lw, stream));
+    if (kd < n_low) return fail(BRI_E_NOCONV, "Lanczos stopped after %d steps (< n_low)", kd);
+    // 2. the n_low smallest eigenpairs of T by bisection and inverse iteration
+    const std::vector<double> th = tridiag_eigenvalues(kd, al.data(), be.data());
+    std::vector<std::vector<double>> ys;
+    const double scale = std::max(std::fabs(th.front()), std::fabs(th.back()));
+    for (int i = 0; i < n_low; ++i) {
+        std::vector<std::vector<double>> cl;  // earlier members of this cluster
+        for (int j = 0; j < i; ++j)
+            if (std::fabs(th[i] - th[j]) <= 1e-8 * scale) cl.push_back(ys[j]);
+        ys.push_back(tridiag_eigvec(kd, al.data(), be.data(), th[i], cl));
+    }
+    std::vector<double> ch((size_t)n_low * kd);
+    for (int i = 0; i < n_low; ++i)
+        for (int j = 0; j < kd; ++j) ch[(size_t)i * kd + j] = ys[i][j];
+    OV_HIP(hipMemcpyAsync(Cr, ch.data(), ch.size() * sizeof(double), hipMemcpyHostToDevice, c.st), "copy");
+    // 3. Ritz vectors X_i = sum_j y_ij V_j
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(ncx), (n_low + 7) / 8), dim3(kB), 0, c.st, ncx, kd, n_low, basis, Cr,
+                       0, X);
+    OV_HIP(hipGetLastError(), "combine");
+    // 4. Rayleigh-Ritz for H = gamma5 D on span{X}: G_ij = <X_i, H X_j>
+    OV_TRY(apply_op(c.d, c.op, BRI_F64, c.mass, X, T, n_low, c.st, false));
+    OV_TRY(gamma5_comb(c, n_low, 0.0, nullptr, 1.0, T, HX));
+    const int nb = dot_blocks(c.n);
+    for (int j = 0; j < n_low; ++j) {
+        hipLaunchKernelGGL(k_multidot_partial, dim3(nb, n_low), dim3(kB), 0, c.st, ncx, X, HX + (size_t)j * c.n, c.part);
+        OV_HIP(hipGetLastError(), "gram");
+        OV_HIP(dot_finish(n_low, c.part, nb, c.red + (size_t)j * n_low * 2, c.st), "gram finish");
+    }
+    std::vector<double> gh((size_t)n_low * n_low * 2);
+    OV_HIP(hipMemcpyAsync(gh.data(), c.red, gh.size() * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy");
+    OV_HIP(hipStreamSynchronize(c.st), "synchronize");
+    std::vector<std::complex<double>> G((size_t)n_low * n_low), Z;
+    for (int j = 0; j < n_low; ++j)
+        for (int i = 0; i < n_low; ++i)  // red[j][i] = <X_i, H X_j> = G_ij
+            G[(size_t)i * n_low + j] = {gh[((size_t)j * n_low + i) * 2], gh[((size_t)j * n_low + i) * 2 + 1]};
+    for (int i = 0; i < n_low; ++i)  // symmetrise (rounding)
+        for (int j = i + 1; j < n_low; ++j) {
+            const auto a = 0.5 * (G[(size_t)i * n_low + j] + std::conj(G[(size_t)j * n_low + i]));
+            G[(size_t)i * n_low + j] = a;
+            G[(size_t)j * n_low + i] = std::conj(a);
+        }
+    std::vector<double> mu;
+    jacobi_herm(n_low, G, Z, mu);
+    std::vector<int> ord(n_low);
+    for (int i = 0; i < n_low; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return std::fabs(mu[x]) < std::fabs(mu[y]); });
+    // 5. v_i = sum_j Z_{j, ord_i} X_j
+    std::vector<double> zc((size_t)n_low * n_low * 2);
+    for (int i = 0; i < n_low; ++i) {
+        evals[i] = mu[ord[i]];
+        for (int j = 0; j < n_low; ++j) {
+            zc[((size_t)i * n_low + j) * 2] = Z[(size_t)j * n_low + ord[i]].real();
+            zc[((size_t)i * n_low + j) * 2 + 1] = Z[(size_t)j * n_low + ord[i]].imag();
+        }
+    }
+    OV_HIP(hipMemcpyAsync(Cz, zc.data(), zc.size() * sizeof(double), hipMemcpyHostToDevice, c.st), "copy");
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(ncx), (n_low + 7) / 8), dim3(kB), 0, c.st, ncx, n_low, n_low, X, Cz,
+                       1, vecs);
+    OV_HIP(hipGetLastError(), "combine");
+    // 6. residuals |H v_i - mu_i v_i|
+    OV_TRY(apply_op(c.d, c.op, BRI_F64, c.mass, vecs, T, n_low, c.st, false));
+    OV_TRY(gamma5_comb(c, n_low, 0.0, nullptr, 1.0, T, HX));
+    for (int i = 0; i < n_low; ++i)
+        OV_TRY(lincomb(c, c.n, 1.0, HX + (size_t)i * c.n, -evals[i], vecs + (size_t)i * c.n, 0, nullptr, 0, nullptr,
+                       HX + (size_t)i * c.n));
+    OV_HIP(dot_partials_t<double>(c.n, n_low, HX, HX, c.part, nb, c.st), "residual partials");
+    OV_HIP(dot_finish(n_low, c.part, nb, c.red, c.st), "residual finish");
+    std::vector<double> rr((size_t)n_low * 2);
+    OV_HIP(hipMemcpyAsync(rr.data(), c.red, rr.size() * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy");
+    OV_HIP(hipStreamSynchronize(c.st), "synchronize");
+    for (int i = 0; i < n_low; ++i) resid[i] = std::sqrt(std::max(rr[2 * i], 0.0));
     return BRI_OK;
 }
 

@@ -163,3 +163,37 @@ def test_overlap_identities_16_32(bri):
     lhs = g5(dx) + ov(g5(x))
     rhs = ov(g5(dx)) / RHO
     assert float(torch.linalg.norm(lhs - rhs) / torch.linalg.norm(x)) <= 20 * err + 1e-10
+
+
+def test_lowmodes_and_deflated_sign(bri, setup):
+    """The 6 modes of H of smallest |eigenvalue| from 300 re-orthogonalised
+    Lanczos steps and Rayleigh-Ritz: eigenvalues against the oracle's dense
+    eigh, orthonormal, eigenvectors of the oracle's H; deflating them lets a
+    polynomial on the reduced interval [0.95 lambda_7^2, 1.05 lambda_max^2]
+    reach the exact sign, which the same polynomial without deflation misses."""
+    u, dk, ev, op = setup
+    log("low modes 4x2x2x4")
+    h = oov.hermitian_kernel(dk)
+    lam = np.linalg.eigvalsh(h)
+    lam = lam[np.argsort(np.abs(lam))]
+    n_low = 6
+    v0 = bri.bri_pack_spinor(DIMS, dev(synth.gaussian_spinor(DIMS, 8207, nrhs=1)), bri.F64)
+    V, mu, res = bri.bri_overlap_lowmodes(DIMS, op, -RHO, 300, v0, n_low)
+    assert np.abs(mu - lam[:n_low]).max() < 1e-9 * np.abs(lam).max()
+    assert res.max() < 1e-8
+    q = _flat(soa_to_canon(DIMS, V))
+    assert np.abs(q.conj() @ q.T - np.eye(n_low)).max() < 1e-10
+    for i in range(n_low):
+        assert np.linalg.norm(h @ q[i] - mu[i] * q[i]) < 1e-8
+    lo, hi = 0.95 * lam[n_low] ** 2, 1.05 * ev[-1]
+    deg = _degree(lo, hi, 1e-11)
+    psi = synth.gaussian_spinor(DIMS, 8208, nrhs=1)
+    x = bri.bri_pack_spinor(DIMS, dev(psi), bri.F64)
+    s = oov.sign_matrix(h)
+    want = s @ _flat(psi)[0]
+    out, err = bri.bri_sign_h(DIMS, op, -RHO, x, lo, hi, deg, low_vecs=V, low_evals=mu)
+    got = _flat(soa_to_canon(DIMS, out))[0]
+    assert np.linalg.norm(got - want) <= (err + 1e-8) * np.linalg.norm(want)
+    out0, _ = bri.bri_sign_h(DIMS, op, -RHO, x, lo, hi, deg)
+    got0 = _flat(soa_to_canon(DIMS, out0))[0]
+    assert np.linalg.norm(got0 - want) > 1e3 * np.linalg.norm(got - want)
