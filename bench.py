@@ -221,8 +221,8 @@ def production_operator(torch, bri, U64, dev, psi, tol=1e-10):
     (alpha 0.72), transporters back-projected to SU(3) and stored as two rows,
     and the clover term (c_SW = 1).  Build times, apply times per form (HIP
     events per launch), and the 12-source propagator solve to a true FP64
-    residual of 1e-10, mixed precision (FP32 two-row transporters and FP32
-    clover inside) against twelve plain FP64 solves."""
+    residual of 1e-10, mixed precision (FP32 or FP16 two-row transporters
+    and FP32 clover inside) against twelve plain FP64 solves."""
     import numpy as np
     import synth
     V = bri.volume(DIMS)
@@ -273,6 +273,16 @@ def production_operator(torch, bri, U64, dev, psi, tol=1e-10):
     _, im = bri.bri_solve_cgne_op(DIMS, hi, b, MASS, p, op_lo=lo)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
+    del lo
+    lo16 = bri.Operator(bri.bri_build_transporters_ex(DIMS, Us, bri.F16, 80, bri.W_SU3_2ROW), bri.W_SU3_2ROW,
+                        bri.bri_build_clover(DIMS, Us, 1.0, bri.F32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = bri.solve_params(tol=tol, inner_prec=bri.F16, inner_tol=1e-2, check_every=4)
+    _, ih = bri.bri_solve_cgne_op(DIMS, hi, b, MASS, p, op_lo=lo16)
+    torch.cuda.synchronize()
+    t_half = time.perf_counter() - t0
+    del lo16
     t0 = time.perf_counter()
     iters, worst = 0, 0.0
     p = bri.solve_params(tol=tol, inner_prec=bri.F64, check_every=4)
@@ -285,6 +295,9 @@ def production_operator(torch, bri, U64, dev, psi, tol=1e-10):
     out["solve_12rhs"] = {"tol": tol, "mixed_s": t_mixed, "plain_fp64_12x_s": t_plain,
                           "ratio_mixed_over_plain": t_mixed / t_plain, "mixed_iterations": im["iterations"],
                           "mixed_outer": im["outer"], "mixed_max_true_residual": max(im["true_residual"][:12]),
+                          "mixed_f16w_s": t_half, "ratio_mixed_f16w_over_plain": t_half / t_plain,
+                          "mixed_f16w_iterations": ih["iterations"], "mixed_f16w_outer": ih["outer"],
+                          "mixed_f16w_max_true_residual": max(ih["true_residual"][:12]),
                           "plain_iterations_total": iters, "plain_max_true_residual": worst}
     return out
 

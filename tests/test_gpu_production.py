@@ -270,3 +270,27 @@ def test_production_fullsize_sampled(bri):
         assert rel(g, want) <= TOL[(wp, sp)], (wp, sp)
         del op, x
         torch.cuda.empty_cache()
+
+
+def test_production_twelve_sources_mixed(bri):
+    """The 12 spin-colour point sources at 4^4 on the production operator
+    (smeared links, two-row SU(3) transporters, clover term), batched mixed
+    solve with FP16 transporters inside, to 1e-10; every column's residual
+    recomputed with the oracle."""
+    dims, mass = (4, 4, 4, 4), 0.1
+    u = synth.gauge_links(dims, 0.3, 7801)
+    src = synth.point_sources(dims)
+    log("production 12-source mixed solve 4^4")
+    U = bri.bri_ape_smear(dims, bri.bri_pack_links(dims, dev(u), bri.F64), 0.72)
+    hi = bri.Operator(bri.bri_build_transporters_ex(dims, U, bri.F64, 80, bri.W_SU3_2ROW), bri.W_SU3_2ROW,
+                      bri.bri_build_clover(dims, U, 1.0, bri.F64))
+    lo = bri.Operator(bri.bri_build_transporters_ex(dims, U, bri.F16, 80, bri.W_SU3_2ROW), bri.W_SU3_2ROW,
+                      bri.bri_build_clover(dims, U, 1.0, bri.F32))
+    p = bri.solve_params(tol=1e-10, inner_tol=1e-2, inner_prec=bri.F16)
+    X, info = bri.bri_solve_cgne_op(dims, hi, bri.bri_pack_spinor(dims, dev(src), bri.F64), mass, p, op_lo=lo)
+    assert info["converged"] and max(info["true_residual"][:12]) <= 1e-10
+    xs = soa_to_canon(dims, X)
+    us = smearing.ape(u, 0.72)
+    for r in range(12):
+        res = production.apply(us, xs[r], mass) - src[r]
+        assert np.linalg.norm(res) <= 2e-10 * np.linalg.norm(src[r]), r
