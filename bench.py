@@ -127,6 +127,12 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
     _, im = bri.bri_solve_cgne(DIMS, W64, b, MASS, p, W_lo=W32)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
+    # the same batched FP32 solve with FP64 refinement stopped at 1e-8
+    t0 = time.perf_counter()
+    p = bri.solve_params(tol=1e-8, inner_prec=bri.F32, inner_tol=1e-3, check_every=4)
+    _, i8 = bri.bri_solve_cgne(DIMS, W64, b, MASS, p, W_lo=W32)
+    torch.cuda.synchronize()
+    t_mixed8 = time.perf_counter() - t0
     del W32
     W16 = bri.bri_build_transporters(DIMS, U64, bri.F16, 80)
     torch.cuda.synchronize()
@@ -146,6 +152,8 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     return {"tol": tol, "mixed_s": t_mixed, "plain_fp64_12x_s": t_plain,
+            "mixed_tol_1e-8_s": t_mixed8, "mixed_tol_1e-8_iterations": i8["iterations"],
+            "mixed_tol_1e-8_max_true_residual": max(i8["true_residual"][:12]),
             "ratio_mixed_over_plain": t_mixed / t_plain,
             "mixed_iterations": im["iterations"], "mixed_outer": im["outer"],
             "mixed_max_true_residual": max(im["true_residual"][:12]),
@@ -185,6 +193,39 @@ def solve_cfg3(torch, bri, dev, tol=1e-10):
         for name in ("mixed_f32", "mixed_f16w"):
             row[name]["speedup_vs_plain"] = row["plain_fp64"]["s"] / row[name]["s"]
         out[f"m={m}"] = row
+    return out
+
+
+def variants_16_32(torch, bri, dev, steps=100):
+    """The 16^3 x 32 lattice (links eps 0.3, seed 2001; Gaussian spinor, seed
+    2002): 100 timed applications each of the stored (W80 and W40) and the
+    recompute variants in FP64 and FP32, one right-hand side."""
+    import numpy as np
+    import synth
+    dims = (16, 16, 16, 32)
+    V = bri.volume(dims)
+    u = torch.from_numpy(synth.gauge_links(dims, EPS, 2001)).to(dev)
+    psi = torch.from_numpy(synth.gaussian_spinor(dims, 2002, 1)).to(dev)
+    U64 = bri.bri_pack_links(dims, u, bri.F64)
+    out = {}
+    for prec, cb in ((bri.F64, 16), (bri.F32, 8)):
+        x = bri.bri_pack_spinor(dims, psi, prec)
+        name = "f64" if prec == bri.F64 else "f32"
+        for noff in (80, 40):
+            W = bri.bri_build_transporters(dims, U64, prec, noff)
+            _, p = timed_launches(torch, lambda: bri.bri_apply(dims, W, x, MASS), steps, 10)
+            ms = float(np.mean(p))
+            byts = bytes_per_site(noff, cb, cb) * V
+            out[f"stored_w{noff}_{name}"] = {"ms": ms, "applies_s": 1e3 / ms,
+                                             "gflops": FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9,
+                                             "alg_GBs": byts / (ms * 1e-3) / 1e9,
+                                             "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del W
+        Ux = U64 if prec == bri.F64 else bri.bri_pack_links(dims, u, bri.F32)
+        _, p = timed_launches(torch, lambda: bri.bri_apply(dims, Ux, x, MASS, variant=bri.RECOMPUTE), steps, 10)
+        ms = float(np.mean(p))
+        out[f"recompute_{name}"] = {"ms": ms, "applies_s": 1e3 / ms,
+                                    "gflops": FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9}
     return out
 
 
@@ -413,7 +454,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(launch_bytes),
                      "kernel": "k_apply_tiled<80,float2,float2,float,false,32,8,1,true,true,3,false>",
                      "alg_bytes_per_site": bps, "alg_bytes_per_launch": launch_bytes,
-                     "kernel_ms": per_ms},
+                     "kernel_ms": per_ms,
+                     # the same time priced at the minimum bytes of any stored scheme (W40)
+                     "frac_vs_w40_min": bytes_per_site(40, 8, 8) * V / (per_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "gflops": FLOPS_PER_SITE * V / (per_ms * 1e-3) / 1e9,
         "build_transporters_ms": build_ms,
         "input_generation_s": gen_s,
@@ -474,6 +517,7 @@ def main():
     if not a.no_extras and not a.no_solve:
         res["solve_12rhs"] = solve_comparison(torch, bri, U64, dev)
     if not a.no_extras:
+        res["variants_16x16x16x32"] = variants_16_32(torch, bri, dev)
         res["gradient_16x16x16x32"] = gradient_timing(torch, bri, dev)
     if not a.no_extras and not a.no_solve:
         res["solve_24x24x24x48"] = solve_cfg3(torch, bri, dev)
