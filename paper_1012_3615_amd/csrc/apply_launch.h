@@ -51,8 +51,9 @@ hipError_t gather(const Geom &g, const void *W, const void *in, void *out, doubl
 // Lx; 2..5 tiles 32x8, 16x16, 64x4, 16x8; 6, 7 tiles 32x8 and 16x16 with the
 // next transporter prefetched; 8 tile 32x8 with prefetch and the offsets of a
 // layer unrolled at compile time (rblk 1, 2); 9, 10 tiles 32x8 (rblk 1-3) and
-// 16x8 (rblk 2-4) with the offsets unrolled, no prefetch.  Tiles hold rblk in 1..4 right-hand sides per
-// thread (16x16 and 64x4: 1; 32x8 with prefetch: 1, 2).
+// 16x8 (rblk 2-4) with the offsets unrolled, no prefetch; 11, 12 tiles 24x8 and 48x4 with prefetch and
+// unrolled offsets (rblk 1, 2).  Tiles hold rblk in 1..4 right-hand sides per thread (16x16 and 64x4: 1;
+// 32x8, 24x8 and 48x4 with prefetch: 1, 2).
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void *in, void *out,
                   double diag, int nrhs, bool dag, hipStream_t st) {
@@ -68,9 +69,16 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         }
     }
     if (kernel == 1) {
-        // default shapes: transporter prefetch where it is instantiated
-        if (g.L[0] <= 16)
+        // default shapes: transporter prefetch where it is instantiated; the
+        // tile width follows Lx so that no lanes idle (24 and 48 wide tiles
+        // for extents that are multiples of those but not of 32)
+        const int lx = g.L[0];
+        if (lx <= 16)
             kernel = rblk == 1 ? 7 : 10;
+        else if (rblk <= 2 && lx % 32 != 0 && lx % 48 == 0)
+            kernel = 12;
+        else if (rblk <= 2 && lx % 32 != 0 && lx % 24 == 0)
+            kernel = 11;
         else
             kernel = rblk <= 2 ? 8 : rblk == 3 ? 9 : 2;
     }
@@ -96,6 +104,10 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         case 10 * 16 + 2: return tiled<NOFF, WS, SS, A, 16, 8, 2, false, true>(g, W, in, out, diag, nrhs, dag, st);
         case 10 * 16 + 3: return tiled<NOFF, WS, SS, A, 16, 8, 3, false, true>(g, W, in, out, diag, nrhs, dag, st);
         case 10 * 16 + 4: return tiled<NOFF, WS, SS, A, 16, 8, 4, false, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 11 * 16 + 1: return tiled<NOFF, WS, SS, A, 24, 8, 1, true, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 11 * 16 + 2: return tiled<NOFF, WS, SS, A, 24, 8, 2, true, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 12 * 16 + 1: return tiled<NOFF, WS, SS, A, 48, 4, 1, true, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 12 * 16 + 2: return tiled<NOFF, WS, SS, A, 48, 4, 2, true, true>(g, W, in, out, diag, nrhs, dag, st);
         default: return hipErrorInvalidValue;
     }
 }
