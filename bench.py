@@ -231,9 +231,9 @@ def variants_16_32(torch, bri, dev, steps=100):
 
 def gradient_timing(torch, bri, dev):
     """FP64 link gradient of S = Re<chi, D psi> at 16^3 x 32 (the gradient
-    lattice): forward = transporter build + apply, backward = transporter
-    build + apply_dag (psi gradient) + bri_grad_links (which rebuilds the
-    transporters itself)."""
+    lattice), as the autograd Function runs it: forward = transporter build
+    (80 offsets) + apply; backward = one FP64 40-offset transporter build
+    shared by apply_dag (psi gradient) and the link gradient."""
     import synth
     import numpy as np
     dims = (16, 16, 16, 32)
@@ -247,9 +247,9 @@ def gradient_timing(torch, bri, dev):
         return bri.bri_apply(dims, W, psi, MASS)
 
     def bwd():
-        W = bri.bri_build_transporters(dims, U, bri.F64, 80)
-        bri.bri_apply_dag(dims, W, chi, MASS)
-        return bri.bri_grad_links(dims, U, chi, psi)
+        W40 = bri.bri_build_transporters(dims, U, bri.F64, 40)
+        bri.bri_apply_dag(dims, W40, chi, MASS)
+        return bri.bri_grad_links(dims, U, chi, psi, W40=W40)
 
     _, pf = timed_launches(torch, fwd, 5, 2)
     _, pb = timed_launches(torch, bwd, 5, 2)

@@ -212,6 +212,14 @@ size_t bri_grad_workspace_bytes(bri_dims d);
 bri_status bri_grad_links(bri_dims d, const double *U_soa, const double *chi, const double *psi,
                           int32_t nrhs, double scale, double *gradU, void *work,
                           size_t work_bytes, void *stream);
+/* The same with the FP64 40-offset transporters of U given (built by
+ * bri_build_transporters(d, U_soa, W40, BRI_F64, 40, ...) in the same
+ * backward pass, e.g. for the psi gradient), so that they are built once.
+ * work: bri_grad_workspace_bytes_w(d). */
+size_t bri_grad_workspace_bytes_w(bri_dims d);
+bri_status bri_grad_links_w(bri_dims d, const double *U_soa, const double *W40, const double *chi,
+                            const double *psi, int32_t nrhs, double scale, double *gradU, void *work,
+                            size_t work_bytes, void *stream);
 
 /* ---- production operator (Sec. 5) -----------------------------------------
  * The operator of the paper's quenched tests uses (i) links after one APE

@@ -7,8 +7,9 @@ S = Re <chi, D psi>.  Hence
     d/dpsi :  D^dag grad_output            (bri_apply_dag)
     d/dU   :  link gradient of Re <grad_output, D psi>   (bri_grad_links)
 
-The transporters are rebuilt from U in the backward pass; only U and psi are
-saved.  All tensors are canonical complex128 device tensors:
+The transporters are rebuilt from U in the backward pass (once, as the FP64
+40-offset store shared by the psi gradient and the link gradient); only U and
+psi are saved.  All tensors are canonical complex128 device tensors:
 U [4, Lt, Lz, Ly, Lx, 3, 3], fields [nrhs, Lt, Lz, Ly, Lx, 4, 3].
 """
 from __future__ import annotations
@@ -43,12 +44,12 @@ class BriApply(torch.autograd.Function):
         Us = api.bri_pack_links(dims, U.contiguous(), api.F64)
         chi = api.bri_pack_spinor(dims, gout.contiguous(), api.F64)
         gU = gpsi = None
+        W40 = api.bri_build_transporters(dims, Us, api.F64, 40)
         if ctx.needs_input_grad[1]:
-            W = api.bri_build_transporters(dims, Us, api.F64, ctx.noff)
-            gpsi = api.bri_unpack_spinor(dims, api.bri_apply_dag(dims, W, chi, ctx.mass)).reshape(psi.shape)
+            gpsi = api.bri_unpack_spinor(dims, api.bri_apply_dag(dims, W40, chi, ctx.mass)).reshape(psi.shape)
         if ctx.needs_input_grad[0]:
             x = api.bri_pack_spinor(dims, psi.contiguous(), api.F64)
-            gU = api.bri_unpack_links(dims, api.bri_grad_links(dims, Us, chi, x))
+            gU = api.bri_unpack_links(dims, api.bri_grad_links(dims, Us, chi, x, W40=W40))
         return gU, gpsi, None, None
 
 

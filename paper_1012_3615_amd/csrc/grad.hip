@@ -138,8 +138,10 @@ __global__ __launch_bounds__(kB) void k_grad_recursion(Geom g, const double2 *__
     }
 }
 
-// step 3: gather onto the links
-__global__ __launch_bounds__(kB) void k_grad_gather(Geom g, const double2 *__restrict__ W80,
+// step 3: gather onto the links; the lower-level transporter W(x, m) is read
+// from the 40-offset FP64 store, at x when m is stored there, otherwise as
+// W(x+m, x)^dag from x+m
+__global__ __launch_bounds__(kB) void k_grad_gather(Geom g, const double2 *__restrict__ W40,
                                                     const double2 *__restrict__ G80,
                                                     double2 *__restrict__ gradU, double scale) {
     const int site = blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,8 +179,21 @@ __global__ __launch_bounds__(kB) void k_grad_gather(Geom g, const double2 *__res
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) P[a][b] = cmake(a == b ? 1.0 : 0.0, 0.0);
+        } else if (im > 40) {
+            ldm(W40 + (size_t)(im - 41) * 9 * V + x, V, P);
         } else {
-            ldm(W80 + (size_t)plane80_rt(im) * 9 * V + x, V, P);
+            int yc[4];
+            for (int nu = 0; nu < 4; ++nu) {
+                const int L = g.L[nu];
+                yc[nu] = (xc[nu] + m[nu] + L) % L;
+            }
+            const int y = yc[0] + g.L[0] * (yc[1] + g.L[1] * (yc[2] + g.L[2] * yc[3]));
+            cx<double> Q[3][3];
+            ldm(W40 + (size_t)(80 - im - 41) * 9 * V + y, V, Q);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) P[a][b] = cconj(Q[b][a]);
         }
         const double inv = 1.0 / k;
         if (n[mu] > 0) {
@@ -222,41 +237,85 @@ extern "C" {
 size_t bri_grad_workspace_bytes(bri_dims d) {
     Geom g;
     if (!dims_ok(d, &g)) return 0;
-    return (size_t)g.V * 9 * 16 * (80 + 40 + 80);
+    return (size_t)g.V * 9 * 16 * (40 + 80);
 }
+
+size_t bri_grad_workspace_bytes_w(bri_dims d) {
+    Geom g;
+    if (!dims_ok(d, &g)) return 0;
+    return (size_t)g.V * 9 * 16 * 80;
+}
+
+}  // extern "C"
+
+namespace bri {
+namespace {
+
+// the three gradient steps with given FP64 40-offset transporters W40 and the
+// transporter-gradient store G80
+bri_status grad_steps(const Geom &g, const double *U, const double2 *W40, const double *chi, const double *psi,
+                      int nrhs, double scale, double *gradU, double2 *G80, hipStream_t st) {
+    dim3 grid((g.V + kB - 1) / kB);
+    hipLaunchKernelGGL(k_grad_direct, grid, dim3(kB), 0, st, g, (const double2 *)chi, (const double2 *)psi, nrhs,
+                       G80);
+    hipLaunchKernelGGL(k_grad_recursion, grid, dim3(kB), 0, st, g, (const double2 *)U, G80);
+    hipLaunchKernelGGL(k_grad_gather, dim3(grid.x, 4), dim3(kB), 0, st, g, W40, (const double2 *)G80,
+                       (double2 *)gradU, scale);
+    return hip_check(hipGetLastError(), "gradient kernels");
+}
+
+bri_status grad_check(bri_dims d, Geom *g, const double *U, const double *chi, const double *psi, int32_t nrhs,
+                      double *gradU) {
+    if (!dims_ok(d, g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
+    if (!aligned(U) || !aligned(chi) || !aligned(psi) || !aligned(gradU))
+        return fail(BRI_E_ARG, "null or misaligned pointer");
+    const size_t lb = (size_t)g->V * 36 * 16;
+    if (overlap(gradU, lb, U, lb)) return fail(BRI_E_ARG, "gradU overlaps the links");
+    return BRI_OK;
+}
+
+}  // namespace
+}  // namespace bri
+
+extern "C" {
 
 bri_status bri_grad_links(bri_dims d, const double *U, const double *chi, const double *psi,
                           int32_t nrhs, double scale, double *gradU, void *work, size_t work_bytes,
                           void *stream) {
     g_last_error.clear();
     Geom g;
-    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
-    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
-    if (!aligned(U) || !aligned(chi) || !aligned(psi) || !aligned(gradU))
-        return fail(BRI_E_ARG, "null or misaligned pointer");
+    bri_status s = grad_check(d, &g, U, chi, psi, nrhs, gradU);
+    if (s != BRI_OK) return s;
     const size_t need = bri_grad_workspace_bytes(d);
     if (!aligned(work) || work_bytes < need)
         return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", need);
-    const size_t lb = (size_t)g.V * 36 * 16;
-    if (overlap(gradU, lb, U, lb) || overlap(work, need, gradU, lb))
-        return fail(BRI_E_ARG, "gradU overlaps its inputs or the workspace");
+    if (overlap(work, need, gradU, (size_t)g.V * 36 * 16))
+        return fail(BRI_E_ARG, "gradU overlaps the workspace");
     hipStream_t st = (hipStream_t)stream;
-    const size_t V = g.V;
-    double2 *W80 = (double2 *)work;
-    double2 *W40 = W80 + (size_t)80 * 9 * V;
-    double2 *G80 = W40 + (size_t)40 * 9 * V;
+    double2 *W40 = (double2 *)work;
+    double2 *G80 = W40 + (size_t)40 * 9 * g.V;
     // transporters rebuilt from the links (not kept from the forward pass)
-    bri_status s = hip_check(build_w40_f64(g, (const double2 *)U, W40, st), "build transporters");
+    s = hip_check(build_w40_f64(g, (const double2 *)U, W40, st), "build transporters");
     if (s != BRI_OK) return s;
-    s = hip_check(convert_w40(g, W40, W80, 0, 80, st), "expand transporters");
+    return grad_steps(g, U, W40, chi, psi, nrhs, scale, gradU, G80, st);
+}
+
+bri_status bri_grad_links_w(bri_dims d, const double *U, const double *W40, const double *chi, const double *psi,
+                            int32_t nrhs, double scale, double *gradU, void *work, size_t work_bytes,
+                            void *stream) {
+    g_last_error.clear();
+    Geom g;
+    bri_status s = grad_check(d, &g, U, chi, psi, nrhs, gradU);
     if (s != BRI_OK) return s;
-    dim3 grid((g.V + kB - 1) / kB);
-    hipLaunchKernelGGL(k_grad_direct, grid, dim3(kB), 0, st, g, (const double2 *)chi,
-                       (const double2 *)psi, nrhs, G80);
-    hipLaunchKernelGGL(k_grad_recursion, grid, dim3(kB), 0, st, g, (const double2 *)U, G80);
-    hipLaunchKernelGGL(k_grad_gather, dim3(grid.x, 4), dim3(kB), 0, st, g, (const double2 *)W80,
-                       (const double2 *)G80, (double2 *)gradU, scale);
-    return hip_check(hipGetLastError(), "gradient kernels");
+    if (!aligned(W40)) return fail(BRI_E_ARG, "null or misaligned pointer");
+    const size_t need = bri_grad_workspace_bytes_w(d);
+    if (!aligned(work) || work_bytes < need)
+        return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", need);
+    if (overlap(work, need, gradU, (size_t)g.V * 36 * 16) || overlap(work, need, W40, (size_t)g.V * 40 * 9 * 16))
+        return fail(BRI_E_ARG, "the workspace overlaps gradU or the transporters");
+    return grad_steps(g, U, (const double2 *)W40, chi, psi, nrhs, scale, gradU, (double2 *)work,
+                      (hipStream_t)stream);
 }
 
 }  // extern "C"

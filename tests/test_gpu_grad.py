@@ -178,3 +178,19 @@ def test_torch_gradcheck_tiny(torch, ag):
     P = torch.from_numpy(psi).cuda().requires_grad_(True)
     assert torch.autograd.gradcheck(lambda a, b: ag.apply(a, b, 0.3), (U, P), eps=1e-6,
                                     atol=1e-7, rtol=1e-6, fast_mode=True)
+
+
+def test_grad_with_given_transporters_matches(torch):
+    """bri_grad_links_w with the FP64 40-offset transporters built by the
+    caller equals bri_grad_links (which rebuilds them) bit for bit."""
+    import paper_1012_3615_amd as bri
+    dims = (4, 3, 4, 5)
+    u, chi, psi = _setup(dims, 5501)
+    log("grad with given W40")
+    U = bri.bri_pack_links(dims, torch.from_numpy(u).cuda(), bri.F64)
+    c = bri.bri_pack_spinor(dims, torch.from_numpy(chi).cuda(), bri.F64)
+    p = bri.bri_pack_spinor(dims, torch.from_numpy(psi).cuda(), bri.F64)
+    W40 = bri.bri_build_transporters(dims, U, bri.F64, 40)
+    a = bri.bri_grad_links(dims, U, c, p)
+    b = bri.bri_grad_links(dims, U, c, p, W40=W40)
+    assert torch.equal(a, b)
