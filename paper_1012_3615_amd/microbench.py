@@ -7,7 +7,8 @@
 Each variant builds its inputs (links exp(i 0.3 H), seed 4001; Gaussian
 spinors; the 12 point sources for the 12-RHS variant; for the production
 operator forms prod*: one APE step, back-projected transporters whole or as
-two rows, and the clover term), runs one untimed
+two rows, and the clover term; overlap_sign_24: sign(gamma5 D) at 24^3 x 48
+to 1e-10 for the smeared, projected kernel at mass -1), runs one untimed
 launch, then `reps` launches timed with HIP events on the current stream,
 and prints one line per variant.  `stream` times a plain device read of a
 8 GiB buffer (torch sum) and a 2 GiB copy, as a reference for the
@@ -87,6 +88,10 @@ def run(dims, names, reps=3, mass=0.1):
             out.append({"variant": "copy_2GiB", "ms": ms, "GBs": 2 * a.numel() / ms / 1e6})
             del a, b
             continue
+        if name == "overlap_sign_24":
+            out.append(_run_overlap(reps))
+            torch.cuda.empty_cache()
+            continue
         if name in PROD:
             out.append(_run_prod(dims, name, Ud, U64, psi, reps, mass))
             torch.cuda.empty_cache()
@@ -117,6 +122,30 @@ def run(dims, names, reps=3, mass=0.1):
         del Wv, x, y
         torch.cuda.empty_cache()
     return out
+
+
+def _run_overlap(reps):
+    """sign(gamma5 D(-1)) at 24^3 x 48 (links eps 0.4, seed 3001) for the
+    smeared, projected kernel, degree for 1e-10 from 300 Lanczos steps."""
+    dims = (24, 24, 24, 48)
+    Ud = synth.gauge_links_device(dims, 0.4, 3001)
+    Us = bri.bri_ape_smear(dims, bri.bri_pack_links(dims, Ud, bri.F64), 0.72)
+    del Ud
+    op = bri.Operator(bri.bri_build_transporters_ex(dims, Us, bri.F64, 80, bri.W_SU3_2ROW), bri.W_SU3_2ROW)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3003)
+    shp = (1,) + synth.lattice_shape(dims) + (4, 3)
+    v0 = bri.bri_pack_spinor(dims, torch.complex(torch.randn(shp, generator=gen, dtype=torch.float64, device="cuda"),
+                                                 torch.randn(shp, generator=gen, dtype=torch.float64, device="cuda")),
+                             bri.F64)
+    a, b, _ = bri.bri_lanczos(dims, op, -1.0, 300, v0)
+    r = bri.bri_ritz_values(a, b)
+    lo, hi = 0.9 * r[0], 1.05 * r[-1]
+    deg = bri.sign_degree(lo, hi, 1e-10)
+    y = torch.empty_like(v0)
+    ms = _time(lambda: bri.bri_sign_h(dims, op, -1.0, v0, lo, hi, deg, out=y, with_error=False), reps)
+    return {"variant": "overlap_sign_24", "ms": ms, "degree": deg, "D_applies": 2 * deg + 3,
+            "ms_per_D_apply": ms / (2 * deg + 3), "ritz": [float(r[0]), float(r[-1])]}
 
 
 def _run_prod(dims, name, Ud, U64, psi, reps, mass):
