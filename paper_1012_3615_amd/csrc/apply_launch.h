@@ -115,12 +115,25 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
 // Production-operator forms (80-offset store only): ROWS = 2 for the two-row
 // store of back-projected transporters, CLV for the clover term.  The tile
 // is the default one for the extent Lx (32x8 with prefetch and unrolled
-// offsets, or 16x16 / 16x8 for Lx <= 16); rblk 1 or 2 right-hand sides per
-// thread.
+// offsets, 24x8 or 48x4 when Lx is a multiple of 24 or 48 but not of 32, or
+// 16x16 / 16x8 for Lx <= 16); rblk 1 or 2 right-hand sides per thread.
 template <typename WS, typename SS, typename A, int ROWS, bool CLV>
 hipError_t stored_ext(const Geom &g, int rblk, const void *W, const void *in, void *out, double diag,
                       int nrhs, bool dag, hipStream_t st, const void *clover) {
-    const bool small = g.L[0] <= 16;
+    const int lx = g.L[0];
+    const bool small = lx <= 16;
+    if (!small && lx % 32 != 0 && (lx % 48 == 0 || lx % 24 == 0) && (rblk == 1 || rblk == 2)) {
+        // tile width follows Lx (no idle lanes), as for the core operator
+        if (lx % 48 == 0)
+            return rblk == 1 ? tiled<80, WS, SS, A, 48, 4, 1, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag,
+                                                                                  st, clover)
+                             : tiled<80, WS, SS, A, 48, 4, 2, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag,
+                                                                                  st, clover);
+        return rblk == 1 ? tiled<80, WS, SS, A, 24, 8, 1, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
+                                                                              clover)
+                         : tiled<80, WS, SS, A, 24, 8, 2, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
+                                                                              clover);
+    }
     if (rblk == 1)
         return small ? tiled<80, WS, SS, A, 16, 16, 1, true, false, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
                                                                              clover)
