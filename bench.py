@@ -391,7 +391,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {a.gpus}); "
               "the multi-GPU decomposition is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
 
