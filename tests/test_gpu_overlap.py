@@ -197,3 +197,22 @@ def test_lowmodes_and_deflated_sign(bri, setup):
     out0, _ = bri.bri_sign_h(DIMS, op, -RHO, x, lo, hi, deg)
     got0 = _flat(soa_to_canon(DIMS, out0))[0]
     assert np.linalg.norm(got0 - want) > 1e3 * np.linalg.norm(got - want)
+
+
+@pytest.mark.parametrize("rho,m", [(0.7, 0.0), (1.6, 0.1)])
+def test_overlap_other_rho(bri, setup, rho, m):
+    """D_ov,m at rho = 0.7 and 1.6 (kernel at mass -rho) against the dense exact
+    operator, degree chosen from the Ritz interval of that kernel."""
+    u, _, _, op = setup
+    log(f"overlap rho={rho} m={m}")
+    dk = oov.kernel_matrix(u, rho)
+    ev = oov.ritz_reference(dk)
+    lo, hi = 0.95 * ev[0], 1.05 * ev[-1]
+    deg = _degree(lo, hi, 1e-11)
+    psi = synth.gaussian_spinor(DIMS, 8209, nrhs=2)
+    x = bri.bri_pack_spinor(DIMS, dev(psi), bri.F64)
+    out, err = bri.bri_overlap_apply(DIMS, op, x, rho, m, lo, hi, deg)
+    want = (oov.overlap_matrix(dk, rho, m) @ _flat(psi).T).T
+    got = _flat(soa_to_canon(DIMS, out))
+    for r in range(2):
+        assert np.linalg.norm(got[r] - want[r]) <= (2 * rho * err + 1e-12) * np.linalg.norm(psi[r])

@@ -161,7 +161,7 @@ def test_clover_term_matches_oracle(bri):
 PREC = [(0, 0), (1, 1), (2, 1), (2, 2)]
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (32, 12, 2, 2), (24, 10, 2, 2)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (32, 12, 2, 2), (24, 10, 2, 2), (2, 3, 2, 2)])
 def test_production_operator_matches_oracle(bri, dims):
     """Smeared links, two-row SU(3) transporters and clover term, D and D^dag,
     one and three right-hand sides, every precision pair; (32,12,2,2) runs the
