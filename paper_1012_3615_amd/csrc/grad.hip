@@ -7,9 +7,9 @@
 // 2. Every transporter obeys the same-site recursion used to build it,
 //      W(x,n) = (1/k) sum_{mu in supp n} W(x, n - s_mu mu) L(x,n,mu),
 //      L = U_mu(x+n-mu) (s_mu = +1) or U_mu(x+n)^dag (s_mu = -1),
-//    so in reverse hop order (4 -> 2) each thread adds
-//      G_{n - s_mu mu}(x) += (1/k) G_n(x) L^dag
-//    to the lower-level transporters of its own site.
+//    so G_{n - s_mu mu}(x) receives (1/k) G_n(x) L^dag.  Steps 1 and 2 run
+//    as one pass in reverse hop order (4 -> 1): each lower-level gradient
+//    pulls these terms from its parents, which are final by then.
 // 3. Each link collects, without atomics, the product-rule terms of every
 //    (x, n, mu) whose last step runs over it:
 //      s_mu = +1: U_mu(y), y = x+n-mu:  += (1/k) W(x, n-mu)^dag G_n(x)
@@ -35,59 +35,53 @@ __device__ __forceinline__ void stm(double2 *p, size_t V, const cx<double> m[3][
     for (int e = 0; e < 9; ++e) st(p + e * V, m[e / 3][e % 3]);
 }
 
-// step 1: direct transporter gradients for all 80 offsets
-__global__ __launch_bounds__(kB) void k_grad_direct(Geom g, const double2 *__restrict__ chi,
-                                                    const double2 *__restrict__ psi, int nrhs,
-                                                    double2 *__restrict__ G80) {
-    const int site = blockIdx.x * blockDim.x + threadIdx.x;
-    if (site >= g.V) return;
-    const size_t V = (size_t)g.V;
-    int c[4];
-    coords(g, site, c);
-    const Nbr nb = make_nbr(g, c);
-#pragma unroll 1
-    for (int j = 0; j < 80; ++j) {
-        const int i = j < 40 ? j : j + 1;
-        const int nx = i % 3 - 1, ny = (i / 3) % 3 - 1, nz = (i / 9) % 3 - 1, nt = i / 27 - 1;
-        const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
-        const double lam = lam_rt<double>(k), rho = rho_rt<double>(k);
-        const int y = nbr_rt(nb, nx, ny, nz, nt);
-        cx<double> G[3][3];
+// direct gradient of the transporter of offset n at the site:
+// G = sum_rhs sum_s (C(n) chi(x))_s psi_s(x+n)^dag
+__device__ inline void grad_direct(const Nbr &nb, int site, size_t V, const double2 *__restrict__ chi,
+                                   const double2 *__restrict__ psi, int nrhs, const int n[4], cx<double> G[3][3]) {
+    const int k = (n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0);
+    const double lam = lam_rt<double>(k), rho = rho_rt<double>(k);
+    const int y = nbr_rt(nb, n[0], n[1], n[2], n[3]);
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) G[a][b] = cmake(0.0, 0.0);
-        for (int r = 0; r < nrhs; ++r) {
-            const double2 *xc = chi + (size_t)r * 12 * V + site;
-            const double2 *ps = psi + (size_t)r * 12 * V + y;
-            cx<double> ch[4][3], pp[4][3];
+        for (int b = 0; b < 3; ++b) G[a][b] = cmake(0.0, 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+        const double2 *xc = chi + (size_t)r * 12 * V + site;
+        const double2 *ps = psi + (size_t)r * 12 * V + y;
+        cx<double> ch[4][3], pp[4][3];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    ch[s][a] = ldc<double>(xc + (3 * s + a) * V);
-                    pp[s][a] = ldc<double>(ps + (3 * s + a) * V);
-                }
-            // phi = C(n) chi, colour by colour
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                cx<double> in4[4] = {ch[0][a], ch[1][a], ch[2][a], ch[3][a]};
-                cx<double> o[4] = {cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0)};
-                spin_accum_rt(o, in4, lam, rho, nx, ny, nz, nt);
-                // G[a][b] += sum_s phi_s[a] conj(psi_s[b])
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) G[a][b] = cmac(G[a][b], o[s], cconj(pp[s][b]));
+                ch[s][a] = ldc<double>(xc + (3 * s + a) * V);
+                pp[s][a] = ldc<double>(ps + (3 * s + a) * V);
             }
+        // phi = C(n) chi, colour by colour
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<double> in4[4] = {ch[0][a], ch[1][a], ch[2][a], ch[3][a]};
+            cx<double> o[4] = {cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0)};
+            spin_accum_rt(o, in4, lam, rho, n[0], n[1], n[2], n[3]);
+            // G[a][b] += sum_s phi_s[a] conj(psi_s[b])
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) G[a][b] = cmac(G[a][b], o[s], cconj(pp[s][b]));
         }
-        stm(G80 + (size_t)j * 9 * V + site, V, G);
     }
 }
 
-// step 2: reverse hop-order recursion at each site, levels 4 -> 2
-__global__ __launch_bounds__(kB) void k_grad_recursion(Geom g, const double2 *__restrict__ U,
-                                                       double2 *__restrict__ G80) {
+// steps 1 and 2 in one pass, level by level from 4 hops down to 1: the full
+// gradient of the transporter of offset P is its direct term plus what its
+// parents p = P + s e_nu (nu outside the support of P, s = +-1; one hop more)
+// pass down through their last link,
+//   G_P += (1/|p|) G_p L^dag,  L = U_nu(x+P) (s = +1) or U_nu(x+P-nu)^dag (s = -1),
+// the reverse of the same-site recursion that builds the transporters.  The
+// parents are final when their level is done, so every G is written once.
+__global__ __launch_bounds__(kB) void k_grad_pull(Geom g, const double2 *__restrict__ U,
+                                                  const double2 *__restrict__ chi, const double2 *__restrict__ psi,
+                                                  int nrhs, double2 *__restrict__ G80) {
     const int site = blockIdx.x * blockDim.x + threadIdx.x;
     if (site >= g.V) return;
     const size_t V = (size_t)g.V;
@@ -95,45 +89,48 @@ __global__ __launch_bounds__(kB) void k_grad_recursion(Geom g, const double2 *__
     coords(g, site, c);
     const Nbr nb = make_nbr(g, c);
 #pragma unroll 1
-    for (int k = 4; k >= 2; --k) {
+    for (int k = 4; k >= 1; --k) {
+        const double inv = 1.0 / (k + 1);
 #pragma unroll 1
         for (int i = 0; i < 81; ++i) {
             const int n[4] = {i % 3 - 1, (i / 3) % 3 - 1, (i / 9) % 3 - 1, i / 27 - 1};
             if ((n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0) != k) continue;
-            cx<double> Gn[3][3];
-            ldm(G80 + (size_t)plane80_rt(i) * 9 * V + site, V, Gn);
-            const double inv = 1.0 / k;
+            cx<double> G[3][3];
+            grad_direct(nb, site, V, chi, psi, nrhs, n, G);
 #pragma unroll 1
-            for (int mu = 0; mu < 4; ++mu) {
-                if (n[mu] == 0) continue;
-                int d[4] = {n[0], n[1], n[2], n[3]};
-                if (n[mu] > 0) d[mu] -= 1;  // link base site x+n-mu (forward) or x+n (backward)
-                const int yl = nbr_rt(nb, d[0], d[1], d[2], d[3]);
-                cx<double> l[3][3];
-                const double2 *pu = U + (size_t)mu * 9 * V + yl;
+            for (int nu = 0; nu < 4 && k < 4; ++nu) {
+                if (n[nu] != 0) continue;
+#pragma unroll 1
+                for (int sgn = -1; sgn <= 1; sgn += 2) {
+                    int p[4] = {n[0], n[1], n[2], n[3]};
+                    p[nu] = sgn;
+                    const int ip = (p[0] + 1) + 3 * (p[1] + 1) + 9 * (p[2] + 1) + 27 * (p[3] + 1);
+                    cx<double> Gp[3][3];
+                    ldm(G80 + (size_t)plane80_rt(ip) * 9 * V + site, V, Gp);
+                    // the parent's last link: base site x+P (forward) or x+P-nu (backward)
+                    int d[4] = {n[0], n[1], n[2], n[3]};
+                    if (sgn < 0) d[nu] = -1;
+                    const int yl = nbr_rt(nb, d[0], d[1], d[2], d[3]);
+                    cx<double> l[3][3];
+                    const double2 *pu = U + (size_t)nu * 9 * V + yl;
 #pragma unroll
-                for (int e = 0; e < 9; ++e) {
-                    cx<double> v = ldc<double>(pu + e * V);
-                    if (n[mu] > 0) l[e / 3][e % 3] = v; else l[e % 3][e / 3] = cconj(v);
-                }
-                // G_P += inv * Gn * l^dag
-                int m[4] = {n[0], n[1], n[2], n[3]};
-                m[mu] = 0;
-                const int im = (m[0] + 1) + 3 * (m[1] + 1) + 9 * (m[2] + 1) + 27 * (m[3] + 1);
-                double2 *pg = G80 + (size_t)plane80_rt(im) * 9 * V + site;
-                cx<double> P[3][3];
-                ldm(pg, V, P);
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        cx<double> t = cmake(0.0, 0.0);
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) t = cmac(t, Gn[a][q], cconj(l[b][q]));
-                        P[a][b] = caxpy(inv, t, P[a][b]);
+                    for (int e = 0; e < 9; ++e) {
+                        cx<double> v = ldc<double>(pu + e * V);
+                        if (sgn > 0) l[e / 3][e % 3] = v; else l[e % 3][e / 3] = cconj(v);
                     }
-                stm(pg, V, P);
+                    // G += inv * Gp * l^dag
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            cx<double> t = cmake(0.0, 0.0);
+#pragma unroll
+                            for (int q = 0; q < 3; ++q) t = cmac(t, Gp[a][q], cconj(l[b][q]));
+                            G[a][b] = caxpy(inv, t, G[a][b]);
+                        }
+                }
             }
+            stm(G80 + (size_t)plane80_rt(i) * 9 * V + site, V, G);
         }
     }
 }
@@ -256,9 +253,8 @@ namespace {
 bri_status grad_steps(const Geom &g, const double *U, const double2 *W40, const double *chi, const double *psi,
                       int nrhs, double scale, double *gradU, double2 *G80, hipStream_t st) {
     dim3 grid((g.V + kB - 1) / kB);
-    hipLaunchKernelGGL(k_grad_direct, grid, dim3(kB), 0, st, g, (const double2 *)chi, (const double2 *)psi, nrhs,
-                       G80);
-    hipLaunchKernelGGL(k_grad_recursion, grid, dim3(kB), 0, st, g, (const double2 *)U, G80);
+    hipLaunchKernelGGL(k_grad_pull, grid, dim3(kB), 0, st, g, (const double2 *)U, (const double2 *)chi,
+                       (const double2 *)psi, nrhs, G80);
     hipLaunchKernelGGL(k_grad_gather, dim3(grid.x, 4), dim3(kB), 0, st, g, W40, (const double2 *)G80,
                        (double2 *)gradU, scale);
     return hip_check(hipGetLastError(), "gradient kernels");
