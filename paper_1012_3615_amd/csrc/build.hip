@@ -98,32 +98,37 @@ __global__ __launch_bounds__(256) void k_build_level(Geom g, const double2 *__re
     });
 }
 
-// W40 (FP64) -> target store (precision WT, 40 or 80 offsets).  One thread per
-// (site, target plane).
+// W40 (FP64) -> target store (precision WT, 40 or 80 offsets).  One thread
+// per (site x, canonical offset n): it reads W(x, x+n) once and writes it to
+// the plane of n at x and, in the 80-offset store, its adjoint to the plane
+// of -n at x+n (W(x+n, x) = W(x, x+n)^dag); every output element is written
+// by exactly one thread.
 template <typename WT>
 __global__ __launch_bounds__(256) void k_convert(Geom g, const double2 *__restrict__ W40,
                                                  WT *__restrict__ W, int noff) {
     const int site = blockIdx.x * blockDim.x + threadIdx.x;
     if (site >= g.V) return;
-    const int j = blockIdx.y;
+    const int c = blockIdx.y;  // canonical plane, offset i = 41 + c
+    const int i = 41 + c;
     const size_t V = (size_t)g.V;
-    const int i = noff == 80 ? (j < 40 ? j : j + 1) : j + 41;
-    WT *o = W + (size_t)j * 9 * V + site;
-    if (i > 40) {
-        const double2 *p = W40 + (size_t)(i - 41) * 9 * V + site;
+    const double2 *p = W40 + (size_t)c * 9 * V + site;
+    cx<double> m[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) st(o + e * V, ldc<double>(p + e * V));
-    } else {
-        int c[4];
-        coords(g, site, c);
-        const Nbr nb = make_nbr(g, c);
+    for (int e = 0; e < 9; ++e) m[e] = ldc<double>(p + e * V);
+    WT *o = W + (size_t)(noff == 80 ? i - 1 : c) * 9 * V + site;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) st(o + e * V, m[e]);
+    if (noff == 80) {
+        int cc[4];
+        coords(g, site, cc);
+        const Nbr nb = make_nbr(g, cc);
         const int y = nb.at(off_n(i, 0), off_n(i, 1), off_n(i, 2), off_n(i, 3));
-        const double2 *p = W40 + (size_t)(80 - i - 41) * 9 * V + y;
+        WT *ob = W + (size_t)(80 - i) * 9 * V + y;  // plane of offset 80 - i (< 40)
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            // element (a,b) of W(x,x+n) = conj of element (b,a) of W(x+n,x)
+            // element (a,b) of the adjoint = conj of element (b,a)
             const int a = e / 3, b = e % 3;
-            st(o + e * V, cconj(ldc<double>(p + (3 * b + a) * V)));
+            st(ob + e * V, cconj(m[3 * b + a]));
         }
     }
 }
@@ -141,7 +146,7 @@ hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStrea
 }
 
 hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st) {
-    dim3 grid((g.V + kBlock - 1) / kBlock, noff);
+    dim3 grid((g.V + kBlock - 1) / kBlock, 40);
     if (wp == 0)
         hipLaunchKernelGGL(k_convert<double2>, grid, dim3(kBlock), 0, st, g, W40, (double2 *)W, noff);
     else if (wp == 1)

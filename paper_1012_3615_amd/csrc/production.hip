@@ -170,30 +170,34 @@ __global__ __launch_bounds__(kBlock) void k_clover(Geom g, const double2 *__rest
 }
 
 // W40 (FP64) -> two-row store: rows 0 and 1 of every transporter (the third
-// row of an SU(3) matrix follows from them).  One thread per (site, plane).
+// row of an SU(3) matrix follows from them).  One thread per (site x,
+// canonical offset n), as in the full conversion: rows 0, 1 of W(x, x+n) at
+// x and, for 80 offsets, rows 0, 1 of W(x, x+n)^dag at x+n under -n.
 template <typename WT>
 __global__ __launch_bounds__(kBlock) void k_convert_rows2(Geom g, const double2 *__restrict__ W40,
                                                           WT *__restrict__ W, int noff) {
     const int site = blockIdx.x * blockDim.x + threadIdx.x;
     if (site >= g.V) return;
-    const int j = blockIdx.y;
+    const int c = blockIdx.y;
+    const int i = 41 + c;
     const size_t V = (size_t)g.V;
-    const int i = noff == 80 ? (j < 40 ? j : j + 1) : j + 41;
-    WT *o = W + (size_t)j * 6 * V + site;
-    if (i > 40) {
-        const double2 *p = W40 + (size_t)(i - 41) * 9 * V + site;
+    const double2 *p = W40 + (size_t)c * 9 * V + site;
+    cd m[9];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) st(o + e * V, ldc<double>(p + e * V));
-    } else {
-        int c[4];
-        coords(g, site, c);
-        const Nbr nb = make_nbr(g, c);
+    for (int e = 0; e < 9; ++e) m[e] = ldc<double>(p + e * V);
+    WT *o = W + (size_t)(noff == 80 ? i - 1 : c) * 6 * V + site;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) st(o + e * V, m[e]);
+    if (noff == 80) {
+        int cc[4];
+        coords(g, site, cc);
+        const Nbr nb = make_nbr(g, cc);
         const int y = nb.at(off_n(i, 0), off_n(i, 1), off_n(i, 2), off_n(i, 3));
-        const double2 *p = W40 + (size_t)(80 - i - 41) * 9 * V + y;
+        WT *ob = W + (size_t)(80 - i) * 6 * V + y;
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
             const int a = e / 3, b = e % 3;
-            st(o + e * V, cconj(ldc<double>(p + (3 * b + a) * V)));
+            st(ob + e * V, cconj(m[3 * b + a]));
         }
     }
 }
@@ -231,7 +235,7 @@ hipError_t build_clover(const Geom &g, const double2 *U, void *C, int cp, double
 }
 
 hipError_t convert_w40_rows2(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st) {
-    dim3 grid((g.V + kBlock - 1) / kBlock, noff);
+    dim3 grid((g.V + kBlock - 1) / kBlock, 40);
     if (wp == 0)
         hipLaunchKernelGGL(k_convert_rows2<double2>, grid, dim3(kBlock), 0, st, g, W40, (double2 *)W, noff);
     else if (wp == 1)
