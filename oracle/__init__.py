@@ -34,9 +34,11 @@ without blocking or fusion:
 * ``production``  - the operator of Sec. 5: back-projected transporters plus
   the clover term;
 * ``overlap``     - the overlap operator with the Brillouin kernel (Sec. 7),
-  dense and exact for tiny lattices.
+  dense and exact for tiny lattices;
+* ``ultralocal``  - the generic class of Sec. 8 with any (lambda_k, rho_k)
+  table (Tab. rholambda: Wilson, hypercube, Brillouin columns).
 
 Parity status of each function is listed in the module docstrings.
 """
 from . import (constants, gamma, lattice, transporters, dirac, factorized, free, solver, grad,  # noqa: F401
-               projection, smearing, clover, production, overlap)
+               projection, smearing, clover, production, overlap, ultralocal)
