@@ -19,6 +19,10 @@ where
 
 The adjoint is written from D^dag(x,y) = D(y,x)^dag.
 
+``table`` (optional) replaces the Brillouin coefficients by another member of
+the generic class of Sec. 8 (``oracle.ultralocal``: lambda_0..4, rho_1..4);
+the transporters and the clover term stay as above.
+
 Parity: pinned through its parts (projection, smearing and clover modules)
 and, for the whole operator, gamma5-hermiticity, gauge covariance, the free
 limit (unit links: W_SU3 = 1, F = 0, so it equals the plain operator) and
@@ -34,6 +38,7 @@ from .dirac import coefficient_matrix, _colour, _spin
 from .lattice import all_offsets, dag, shift
 from .projection import project_sun
 from .transporters import make_site_getter, transporter, whole_lattice
+from . import ultralocal
 
 
 def transporter_su3(U, n, get=whole_lattice):
@@ -41,8 +46,12 @@ def transporter_su3(U, n, get=whole_lattice):
     return project_sun(transporter(U, n, get))
 
 
-def _apply(U, psi, mass, csw, get, psi_here):
-    lam, rho = operator_weights(mass)
+def _weights(mass, table):
+    return operator_weights(mass) if table is None else ultralocal.weights(table, mass)
+
+
+def _apply(U, psi, mass, csw, get, psi_here, table=None):
+    lam, rho = _weights(mass, table)
     out = lam[(0, 0, 0, 0)] * psi_here
     for n in all_offsets():
         w = transporter_su3(U, n, get)
@@ -52,21 +61,21 @@ def _apply(U, psi, mass, csw, get, psi_here):
     return out
 
 
-def apply(U, psi, mass, csw=CSW_TREE):
+def apply(U, psi, mass, csw=CSW_TREE, table=None):
     """D psi on the whole lattice; psi has shape (Lt, Lz, Ly, Lx, 4, 3)."""
-    return _apply(U, psi, mass, csw, whole_lattice, psi)
+    return _apply(U, psi, mass, csw, whole_lattice, psi, table)
 
 
-def apply_at(U, psi, mass, sites, csw=CSW_TREE):
+def apply_at(U, psi, mass, sites, csw=CSW_TREE, table=None):
     """(D psi)(x) at the sampled sites (N, 4) = (x, y, z, t); shape (N, 4, 3)."""
     dims = (psi.shape[3], psi.shape[2], psi.shape[1], psi.shape[0])
     get = make_site_getter(sites, dims)
-    return _apply(U, psi, mass, csw, get, get(psi, (0, 0, 0, 0)))
+    return _apply(U, psi, mass, csw, get, get(psi, (0, 0, 0, 0)), table)
 
 
-def apply_dag(U, psi, mass, csw=CSW_TREE):
+def apply_dag(U, psi, mass, csw=CSW_TREE, table=None):
     """D^dag psi from D^dag(x,y) = D(y,x)^dag."""
-    lam, rho = operator_weights(mass)
+    lam, rho = _weights(mass, table)
     out = np.conj(lam[(0, 0, 0, 0)]) * psi
     for n in all_offsets():
         back = tuple(-v for v in n)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import dirac, free, ultralocal
+from oracle import clover, dirac, free, production, smearing, ultralocal
 from oracle.gamma import gamma5, gammas
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -164,3 +164,32 @@ def test_apply_at_matches_whole_lattice(links):
     got = ultralocal.apply_at(u, psi, MASS, t, sites)
     want = np.stack([full[s[3], s[2], s[1], s[0]] for s in sites])
     assert rel(got, want) < 1e-14
+
+
+def test_production_form_with_wilson_table_is_wilson_clover(links):
+    """With back-projected transporters and the clover term, the Wilson column
+    gives the clover-improved Wilson operator of Sec. 1 (one-hop transporters
+    are the links themselves, already in SU(3))."""
+    dims, u = links
+    psi = synth.gaussian_spinor(dims, 8309)
+    got = production.apply(u, psi, MASS, csw=1.0, table=ultralocal.WILSON)
+    want = _wilson_hopping(u, psi, MASS) + clover.apply_clover(u, psi, 1.0)
+    assert rel(got, want) < 1e-14
+
+
+def test_production_form_with_table_free_limit_and_hermiticity():
+    dims = (3, 2, 3, 3)
+    psi = synth.gaussian_spinor(dims, 8310)
+    t = ultralocal.HYPERCUBE
+    unit = synth.unit_links(dims)
+    assert rel(production.apply(unit, psi, MASS, table=t), ultralocal.apply(unit, psi, MASS, t)) < 1e-14
+    u = smearing.ape(synth.gauge_links(dims, 0.4, 8311), 0.72)
+    g5 = gamma5()
+    sand = np.einsum("st,...tc->...sc", g5,
+                     production.apply(u, np.einsum("st,...tc->...sc", g5, psi), MASS, table=t))
+    assert rel(production.apply_dag(u, psi, MASS, table=t), sand) < 1e-13
+    sites = np.array([[0, 0, 0, 0], [2, 1, 2, 1]])
+    full = production.apply(u, psi, MASS, table=t)
+    part = production.apply_at(u, psi, MASS, sites, table=t)
+    for j, (x, y, z, tt) in enumerate(sites):
+        assert np.abs(part[j] - full[tt, z, y, x]).max() < 1e-14
