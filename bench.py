@@ -480,6 +480,15 @@ def main():
             extras[name] = d
 
         bench_variant("stored_w80_f32_dag", W, x32, 80, 8, 8, dag=True)
+        # the same stored apply for other members of the generic class of
+        # Sec. 8 (coefficients from a run-time table instead of constants)
+        for tname, tab in (("hypercube", bri.TABLE_HYPERCUBE), ("wilson", bri.TABLE_WILSON)):
+            opt = bri.Operator(W, coef=tab)
+            _, p = timed_launches(torch, lambda: bri.bri_apply_op(DIMS, opt, x32, MASS, out=out), 20, 10)
+            ms = float(np.mean(p))
+            gbs = bytes_per_site(80, 8, 8) * V / (ms * 1e-3) / 1e9
+            extras[f"table_{tname}_w80_f32"] = {"ms": ms, "applies_s": 1e3 / ms, "alg_GBs": gbs,
+                                                "hbm_frac": gbs / HBM_PEAK_GBS}
         W40 = bri.bri_build_transporters(DIMS, U64, bri.F32, 40)
         bench_variant("stored_w40_f32", W40, x32, 40, 8, 8)
         del W40

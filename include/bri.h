@@ -276,19 +276,35 @@ size_t bri_clover_bytes(bri_dims d, bri_prec p);
 bri_status bri_build_clover(bri_dims d, const double *U_soa, double csw, void *C, bri_prec c_prec,
                             void *stream);
 
-/* An operator: transporters, their form and, optionally, the clover term. */
+/* An operator: transporters, their form and, optionally, the clover term and
+ * the coefficients of another member of the generic ultralocal class of
+ * Sec. 8,
+ *   D(x,y) = sum_mu gamma_mu rho_mu(x-y) + lambda(x-y),
+ * where an offset n with k non-zero components carries lambda(n) = lambda_k
+ * and rho_mu(n) = rho_k n_mu (each of the 80 offsets counted once), made
+ * covariant with the same transporters:
+ *   (D psi)(x) = (lambda_0 + m) psi(x)
+ *     + sum_{n != 0} [lambda_k + rho_k sum_mu n_mu gamma_mu] W(x,x+n) psi(x+n).
+ * coef = {lambda_0, lambda_1, lambda_2, lambda_3, lambda_4, rho_1, rho_2,
+ * rho_3, rho_4} (Tab. rholambda lists the Wilson, hypercube and Brillouin
+ * columns); NULL is the Brillouin column.  The nine doubles are host memory,
+ * owned by the caller and read on every call that uses the operator; they
+ * must be finite (BRI_E_ARG otherwise).  The dagger of every member is the
+ * same stencil with rho -> -rho (lambda even, rho odd in n). */
 typedef struct {
     const void *W;       /* transporters (bri_build_transporters or _ex)                     */
     bri_prec w_prec;
-    int32_t n_offsets;   /* 40 or 80; 80 for BRI_W_SU3_2ROW or with a clover term           */
+    int32_t n_offsets;   /* 40 or 80; 80 for BRI_W_SU3_2ROW, a clover term or a table        */
     bri_wform w_form;
     const void *clover;  /* bri_build_clover output in the spinor precision; NULL: c_SW = 0  */
+    const double *coef;  /* 9 host doubles of the generic class; NULL: Brillouin            */
 } bri_operator;
 
 /* out = D in (dagger = 0) or D^dag in (dagger = 1) for the stored variant,
- * with the spinor and precision rules of bri_apply.  The two-row form and the
- * clover term use the default LDS-tile kernel (one or two right-hand sides
- * per thread); otherwise this is bri_apply / bri_apply_dag. */
+ * with the spinor and precision rules of bri_apply.  The two-row form, the
+ * clover term and a coefficient table use the default LDS-tile kernel (one or
+ * two right-hand sides per thread); otherwise this is bri_apply /
+ * bri_apply_dag. */
 bri_status bri_apply_op(bri_dims d, const bri_operator *op, bri_prec s_prec, double mass,
                         const void *in, void *out, int32_t nrhs, int32_t dagger, void *stream);
 

@@ -14,5 +14,5 @@ from .api import (  # noqa: F401
     W_AVERAGE, W_SU3, W_SU3_2ROW, Operator, bri_project_su3, bri_ape_smear, bri_build_transporters_ex,
     bri_build_clover, bri_apply_op, bri_solve_cgne_op,
     bri_lanczos, bri_ritz_values, bri_sign_h, bri_overlap_apply, bri_sign_approx_error, sign_degree,
-    bri_overlap_lowmodes,
+    bri_overlap_lowmodes, TABLE_WILSON, TABLE_HYPERCUBE, TABLE_BRILLOUIN,
 )

@@ -46,6 +46,7 @@ class bri_operator(ctypes.Structure):
         ("n_offsets", ctypes.c_int32),
         ("w_form", ctypes.c_int32),
         ("clover", ctypes.c_void_p),
+        ("coef", ctypes.c_void_p),
     ]
 
 

@@ -306,11 +306,27 @@ def bri_build_clover(dims, U_soa, csw=1.0, prec=F64):
     return C
 
 
-class Operator:
-    """Transporters (and form) plus an optional clover term; keeps the tensors alive."""
+# Coefficient tables of the generic ultralocal class (Sec. 8, Tab. rholambda):
+# (lambda_0, lambda_1, lambda_2, lambda_3, lambda_4, rho_1, rho_2, rho_3, rho_4).
+TABLE_WILSON = (4.0, -0.5, 0.0, 0.0, 0.0, 0.5, 0.0, 0.0, 0.0)
+TABLE_HYPERCUBE = (1.852720547, -0.060757866, -0.030036032, -0.015967620, -0.008426812,
+                   0.136846794, 0.032077284, 0.011058131, 0.004748991)
+TABLE_BRILLOUIN = (240 / 128, -8 / 128, -4 / 128, -2 / 128, -1 / 128, 64 / 432, 16 / 432, 4 / 432, 1 / 432)
 
-    def __init__(self, W, form=W_AVERAGE, clover=None):
+
+class Operator:
+    """Transporters (and form) plus an optional clover term and an optional
+    coefficient table of the generic class (nine numbers, lambda_0..4 then
+    rho_1..4; None is the Brillouin operator); keeps the tensors alive."""
+
+    def __init__(self, W, form=W_AVERAGE, clover=None, coef=None):
         self.W, self.form, self.clover = W, form, clover
+        if coef is not None:
+            coef = tuple(float(c) for c in coef)
+            if len(coef) != 9:
+                raise ValueError("a coefficient table has nine entries (lambda_0..4, rho_1..4)")
+            self._coef_c = (ctypes.c_double * 9)(*coef)
+        self.coef = coef
 
     def struct(self, dims):
         _need_cuda(self.W, self.clover)
@@ -324,6 +340,7 @@ class Operator:
         o.n_offsets = self.W.shape[0]
         o.w_form = self.form
         o.clover = self.clover.data_ptr() if self.clover is not None else None
+        o.coef = ctypes.addressof(self._coef_c) if self.coef is not None else None
         return o
 
 

@@ -23,14 +23,16 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
                       void *stream, bool dag);
 
 // A stored-transporter operator: W, its precision and offset count, the number
-// of stored rows per transporter (3, or 2 for the two-row SU(3) store) and
-// the clover term (nullptr for c_SW = 0).
+// of stored rows per transporter (3, or 2 for the two-row SU(3) store), the
+// clover term (nullptr for c_SW = 0) and the coefficient table of the generic
+// class (lambda_0..4, rho_1..4 on the host; nullptr for the Brillouin column).
 struct OpDesc {
     const void *W;
     bri_prec wp;
     int32_t noff;
     int rows;
     const void *clover;
+    const double *coef;
 };
 bri_status op_from_public(const bri_operator *op, OpDesc *out);
 bri_status apply_op(bri_dims d, const OpDesc &op, bri_prec sp, double mass, const void *in, void *out,

@@ -1,6 +1,7 @@
 // C ABI of the production-operator ingredients (Sec. 5): SU(3) projection,
 // APE smearing, back-projected transporters, the clover term, and the apply
-// of a general stored-transporter operator.
+// of a general stored-transporter operator (any member of the generic class
+// of Sec. 8).
 #include <cmath>
 
 #include "abi_internal.h"
@@ -12,13 +13,16 @@ bri_status op_from_public(const bri_operator *op, OpDesc *out) {
     if (!op) return fail(BRI_E_ARG, "null operator");
     if (op->w_form != BRI_W_AVERAGE && op->w_form != BRI_W_SU3 && op->w_form != BRI_W_SU3_2ROW)
         return fail(BRI_E_ARG, "invalid transporter form");
-    *out = OpDesc{op->W, op->w_prec, op->n_offsets, op->w_form == BRI_W_SU3_2ROW ? 2 : 3, op->clover};
+    if (op->coef)
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(op->coef[i])) return fail(BRI_E_ARG, "coefficient %d of the table is not finite", i);
+    *out = OpDesc{op->W, op->w_prec, op->n_offsets, op->w_form == BRI_W_SU3_2ROW ? 2 : 3, op->clover, op->coef};
     return BRI_OK;
 }
 
 bri_status apply_op(bri_dims d, const OpDesc &op, bri_prec sp, double mass, const void *in, void *out,
                     int32_t nrhs, void *stream, bool dag) {
-    if (op.rows == 3 && !op.clover)
+    if (op.rows == 3 && !op.clover && !op.coef)
         return apply_impl(d, BRI_STORED, op.W, op.wp, op.noff, sp, mass, in, out, nrhs, stream, dag);
     Geom g;
     if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
@@ -29,19 +33,19 @@ bri_status apply_op(bri_dims d, const OpDesc &op, bri_prec sp, double mass, cons
     const size_t sb = (size_t)g.V * 12 * nrhs * cbytes(sp);
     if (overlap(in, sb, out, sb)) return fail(BRI_E_ARG, "in and out overlap");
     if (op.noff != 80)
-        return fail(BRI_E_UNSUPPORTED, "the two-row store and the clover term need n_offsets = 80");
-    const double diag = lam_k(0) + mass;
+        return fail(BRI_E_UNSUPPORTED, "the two-row store, the clover term and a coefficient table need n_offsets = 80");
+    const double diag = (op.coef ? op.coef[0] : lam_k(0)) + mass;
     const int rblk = nrhs >= 2 ? 2 : 1;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (op.wp == BRI_F64 && sp == BRI_F64)
-        e = apply_prod_f64(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover);
+        e = apply_prod_f64(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover, op.coef);
     else if (op.wp == BRI_F32 && sp == BRI_F32)
-        e = apply_prod_f32(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover);
+        e = apply_prod_f32(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover, op.coef);
     else if (op.wp == BRI_F16 && sp == BRI_F32)
-        e = apply_prod_f16(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover);
+        e = apply_prod_f16(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover, op.coef);
     else if (op.wp == BRI_F16 && sp == BRI_F16)
-        e = apply_prod_f16h(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover);
+        e = apply_prod_f16h(g, op.rows, rblk, op.W, in, out, diag, nrhs, dag, st, op.clover, op.coef);
     else
         return fail(BRI_E_UNSUPPORTED, "unsupported (w_prec, s_prec) combination");
     return hip_check(e, "apply (production operator)");

@@ -10,10 +10,22 @@ namespace launch {
 
 constexpr int kGatherBlock = 256;
 
+// lambda_k, rho_k (k = 1..4) from a host table (lambda_0..4, rho_1..4), or
+// the Brillouin column of Tab. rholambda for nullptr
+template <typename A>
+Coef<A> make_coef(const double *table) {
+    Coef<A> c{};
+    for (int k = 1; k <= 4; ++k) {
+        c.lam[k] = (A)(table ? table[k] : lam_k(k));
+        c.rho[k] = (A)(table ? table[4 + k] : rho_k(k));
+    }
+    return c;
+}
+
 template <int NOFF, typename WS, typename SS, typename A, int TX, int TY, int R, bool PF = false,
-          bool UN = false, int ROWS = 3, bool CLV = false>
+          bool UN = false, int ROWS = 3, bool CLV = false, bool TAB = false>
 hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double diag, int nrhs,
-                 bool dag, hipStream_t st, const void *clover = nullptr) {
+                 bool dag, hipStream_t st, const void *clover = nullptr, const double *table = nullptr) {
     // the LDS of a workgroup is at most 160 KiB on gfx950
     constexpr size_t lds = sizeof(SS) * 12 * R * (TX + 2) * (TY + 2);
     if constexpr (lds > 160 * 1024) {
@@ -22,14 +34,15 @@ hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double
         const int ntx = (g.L[0] + TX - 1) / TX, nty = (g.L[1] + TY - 1) / TY;
         // one-dimensional grid, right-hand-side group fastest (see k_apply_tiled)
         dim3 grid(ntx * nty * g.L[2] * g.L[3] * ((nrhs + R - 1) / R));
+        const Coef<A> cf = make_coef<A>(table);
         if (dag)
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF, UN, ROWS, CLV>), grid,
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF, UN, ROWS, CLV, TAB>), grid,
                                dim3(TX * TY), 0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out,
-                               (A)diag, nrhs, (const SS *)clover);
+                               (A)diag, nrhs, (const SS *)clover, cf);
         else
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF, UN, ROWS, CLV>), grid,
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF, UN, ROWS, CLV, TAB>), grid,
                                dim3(TX * TY), 0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out,
-                               (A)diag, nrhs, (const SS *)clover);
+                               (A)diag, nrhs, (const SS *)clover, cf);
         return hipGetLastError();
     }
 }
@@ -112,51 +125,40 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
     }
 }
 
-// Production-operator forms (80-offset store only): ROWS = 2 for the two-row
-// store of back-projected transporters, CLV for the clover term.  The tile
-// is the default one for the extent Lx (32x8 with prefetch and unrolled
-// offsets, 24x8 or 48x4 when Lx is a multiple of 24 or 48 but not of 32, or
-// 16x16 / 16x8 for Lx <= 16); rblk 1 or 2 right-hand sides per thread.
+// Production-operator forms and the generic class (80-offset store only):
+// ROWS = 2 for the two-row store of back-projected transporters, CLV for the
+// clover term; the coefficients come from `table` (lambda_0..4, rho_1..4 of
+// the generic class of Sec. 8; nullptr: the Brillouin column).  The tile is
+// the default one for the extent Lx (32x8 with prefetch and unrolled offsets,
+// 24x8 or 48x4 when Lx is a multiple of 24 or 48 but not of 32, or 16x16 /
+// 16x8 for Lx <= 16); rblk 1 or 2 right-hand sides per thread.
 template <typename WS, typename SS, typename A, int ROWS, bool CLV>
 hipError_t stored_ext(const Geom &g, int rblk, const void *W, const void *in, void *out, double diag,
-                      int nrhs, bool dag, hipStream_t st, const void *clover) {
+                      int nrhs, bool dag, hipStream_t st, const void *clover, const double *table) {
+#define BRI_EXT(TX, TY, R, PF, UN) \
+    tiled<80, WS, SS, A, TX, TY, R, PF, UN, ROWS, CLV, true>(g, W, in, out, diag, nrhs, dag, st, clover, table)
     const int lx = g.L[0];
     const bool small = lx <= 16;
-    if (!small && lx % 32 != 0 && (lx % 48 == 0 || lx % 24 == 0) && (rblk == 1 || rblk == 2)) {
-        // tile width follows Lx (no idle lanes), as for the core operator
-        if (lx % 48 == 0)
-            return rblk == 1 ? tiled<80, WS, SS, A, 48, 4, 1, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag,
-                                                                                  st, clover)
-                             : tiled<80, WS, SS, A, 48, 4, 2, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag,
-                                                                                  st, clover);
-        return rblk == 1 ? tiled<80, WS, SS, A, 24, 8, 1, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
-                                                                              clover)
-                         : tiled<80, WS, SS, A, 24, 8, 2, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
-                                                                              clover);
-    }
-    if (rblk == 1)
-        return small ? tiled<80, WS, SS, A, 16, 16, 1, true, false, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
-                                                                             clover)
-                     : tiled<80, WS, SS, A, 32, 8, 1, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
-                                                                           clover);
-    if (rblk == 2)
-        return small ? tiled<80, WS, SS, A, 16, 8, 2, false, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
-                                                                            clover)
-                     : tiled<80, WS, SS, A, 32, 8, 2, true, true, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st,
-                                                                           clover);
-    return hipErrorInvalidValue;
+    if (rblk != 1 && rblk != 2) return hipErrorInvalidValue;
+    if (!small && lx % 32 != 0 && lx % 48 == 0) return rblk == 1 ? BRI_EXT(48, 4, 1, true, true) : BRI_EXT(48, 4, 2, true, true);
+    if (!small && lx % 32 != 0 && lx % 24 == 0) return rblk == 1 ? BRI_EXT(24, 8, 1, true, true) : BRI_EXT(24, 8, 2, true, true);
+    if (rblk == 1) return small ? BRI_EXT(16, 16, 1, true, false) : BRI_EXT(32, 8, 1, true, true);
+    return small ? BRI_EXT(16, 8, 2, false, true) : BRI_EXT(32, 8, 2, true, true);
+#undef BRI_EXT
 }
 
-// rows: 3 or 2; clover: nullptr for c_SW = 0
+// rows: 3 or 2; clover: nullptr for c_SW = 0; table: nullptr for the Brillouin column
 template <typename WS, typename SS, typename A>
 hipError_t stored_prod(const Geom &g, int rows, int rblk, const void *W, const void *in, void *out, double diag,
-                       int nrhs, bool dag, hipStream_t st, const void *clover) {
+                       int nrhs, bool dag, hipStream_t st, const void *clover, const double *table) {
     if (rows == 3 && clover)
-        return stored_ext<WS, SS, A, 3, true>(g, rblk, W, in, out, diag, nrhs, dag, st, clover);
+        return stored_ext<WS, SS, A, 3, true>(g, rblk, W, in, out, diag, nrhs, dag, st, clover, table);
     if (rows == 2 && clover)
-        return stored_ext<WS, SS, A, 2, true>(g, rblk, W, in, out, diag, nrhs, dag, st, clover);
+        return stored_ext<WS, SS, A, 2, true>(g, rblk, W, in, out, diag, nrhs, dag, st, clover, table);
     if (rows == 2)
-        return stored_ext<WS, SS, A, 2, false>(g, rblk, W, in, out, diag, nrhs, dag, st, nullptr);
+        return stored_ext<WS, SS, A, 2, false>(g, rblk, W, in, out, diag, nrhs, dag, st, nullptr, table);
+    if (rows == 3)
+        return stored_ext<WS, SS, A, 3, false>(g, rblk, W, in, out, diag, nrhs, dag, st, nullptr, table);
     return hipErrorInvalidValue;
 }
 

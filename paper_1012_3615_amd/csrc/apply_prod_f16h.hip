@@ -1,13 +1,14 @@
-// Production-operator forms of the stored apply (two-row SU(3) transporters,
-// clover term) instantiated for W storage __half2, spinor storage __half2 and float accumulation.
+// Production-operator and generic-class forms of the stored apply (two-row SU(3) transporters,
+// clover term, coefficient table) instantiated for W storage __half2, spinor storage __half2 and float accumulation.
 #include "apply_launch.h"
 #include "kernels.h"
 
 namespace bri {
 
 hipError_t apply_prod_f16h(const Geom &g, int rows, int rblk, const void *W, const void *in, void *out,
-                          double diag, int nrhs, bool dag, hipStream_t st, const void *clover) {
-    return launch::stored_prod<__half2, __half2, float>(g, rows, rblk, W, in, out, diag, nrhs, dag, st, clover);
+                          double diag, int nrhs, bool dag, hipStream_t st, const void *clover,
+                          const double *table) {
+    return launch::stored_prod<__half2, __half2, float>(g, rows, rblk, W, in, out, diag, nrhs, dag, st, clover, table);
 }
 
 }  // namespace bri

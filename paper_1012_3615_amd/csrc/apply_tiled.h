@@ -19,6 +19,8 @@ namespace bri {
 // Options for the production operator: ROWS = 2 reads the two-row store of
 // back-projected (SU(3)) transporters and rebuilds the third row; CLV adds
 // the clover term, a Hermitian 6x6 block per chirality and site, at n = 0.
+// TAB takes lambda_k, rho_k from the argument cf (any member of the generic
+// class of Sec. 8) instead of the Brillouin constants.
 template <int TX, int TY>
 struct TileShape {
     static constexpr int HX = TX + 2, HY = TY + 2, NH = HX * HY, NT = TX * TY;
@@ -26,12 +28,12 @@ struct TileShape {
 };
 
 template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R, bool PF = false,
-          bool UN = false, int ROWS = 3, bool CLV = false>
+          bool UN = false, int ROWS = 3, bool CLV = false, bool TAB = false>
 __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty,
                                                         const WS *__restrict__ W,
                                                         const SS *__restrict__ in,
                                                         SS *__restrict__ out, A diag, int nrhs,
-                                                        const SS *__restrict__ clover) {
+                                                        const SS *__restrict__ clover, Coef<A> cf) {
     using TS = TileShape<TX, TY>;
     __shared__ SS lds[R][12][TS::NH];
     // one-dimensional grid: tile-major, right-hand-side group fastest, so the
@@ -177,8 +179,9 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                     return;
                 }
                 const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
-                const A lam = lam_rt<A>(k);
-                const A rho = DAG ? -rho_rt<A>(k) : rho_rt<A>(k);
+                const A lam = TAB ? coef_pick(cf.lam, k) : lam_rt<A>(k);
+                const A rho0 = TAB ? coef_pick(cf.rho, k) : rho_rt<A>(k);
+                const A rho = DAG ? -rho0 : rho0;
                 cx<A> w[3][3];
                 if (PF) {
 #pragma unroll

@@ -20,12 +20,13 @@ BRI_DECL_APPLY(f32)
 BRI_DECL_APPLY(f16)
 BRI_DECL_APPLY(f16h)
 #undef BRI_DECL_APPLY
-// apply_prod_*.hip: production-operator forms of the stored apply (80
-// offsets; rows 3 or 2; clover in the spinor precision or nullptr)
+// apply_prod_*.hip: production-operator and generic-class forms of the
+// stored apply (80 offsets; rows 3 or 2; clover in the spinor precision or
+// nullptr; table lambda_0..4, rho_1..4 or nullptr for the Brillouin column)
 #define BRI_DECL_PROD(tag)                                                                         \
     hipError_t apply_prod_##tag(const Geom &g, int rows, int rblk, const void *W, const void *in,  \
                                 void *out, double diag, int nrhs, bool dag, hipStream_t st,        \
-                                const void *clover);
+                                const void *clover, const double *table);
 BRI_DECL_PROD(f64)
 BRI_DECL_PROD(f32)
 BRI_DECL_PROD(f16)

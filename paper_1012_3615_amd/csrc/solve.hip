@@ -267,8 +267,8 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     g_last_error.clear();
     if (!p) return fail(BRI_E_ARG, "null params or stats");
     if (p->n_offsets != 40 && p->n_offsets != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
-    const OpDesc hi{W_hi, BRI_F64, p->n_offsets, 3, nullptr};
-    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr};
+    const OpDesc hi{W_hi, BRI_F64, p->n_offsets, 3, nullptr, nullptr};
+    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr, nullptr};
     return solve_core(d, p, hi, lo, mass, b, x, nrhs, work, work_bytes, stats, stream);
 }
 

@@ -61,6 +61,20 @@ __device__ __forceinline__ T rho_rt(int k) {
     return k == 1 ? (T)(64.0 / 432.0) : k == 2 ? (T)(16.0 / 432.0) : k == 3 ? (T)(4.0 / 432.0) : (T)(1.0 / 432.0);
 }
 
+// Coefficients of a member of the generic ultralocal class (Sec. 8): the
+// offset classes k = 1..4 carry lambda_k and rho_k (index 0 unused; lambda_0
+// enters through the diagonal).  Passed by value as a kernel argument, so the
+// values sit in scalar registers.
+template <typename T>
+struct Coef {
+    T lam[5], rho[5];
+};
+// select by a wavefront-uniform k in 1..4 without indexing the argument array
+template <typename T>
+__device__ __forceinline__ T coef_pick(const T (&a)[5], int k) {
+    return k == 1 ? a[1] : k == 2 ? a[2] : k == 3 ? a[3] : a[4];
+}
+
 // neighbour site for a run-time offset (each n_mu in {-1,0,1})
 __device__ __forceinline__ int nbr_rt(const Nbr &nb, int nx, int ny, int nz, int nt) {
     const int a = nx < 0 ? nb.part[0][0] : nx > 0 ? nb.part[0][2] : nb.part[0][1];
