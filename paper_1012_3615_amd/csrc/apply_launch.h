@@ -23,7 +23,7 @@ Coef<A> make_coef(const double *table) {
 }
 
 template <int NOFF, typename WS, typename SS, typename A, int TX, int TY, int R, bool PF = false,
-          bool UN = false, int ROWS = 3, bool CLV = false, bool TAB = false>
+          bool UN = false, int ROWS = 3, bool CLV = false>
 hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double diag, int nrhs,
                  bool dag, hipStream_t st, const void *clover = nullptr, const double *table = nullptr) {
     // the LDS of a workgroup is at most 160 KiB on gfx950
@@ -36,11 +36,11 @@ hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double
         dim3 grid(ntx * nty * g.L[2] * g.L[3] * ((nrhs + R - 1) / R));
         const Coef<A> cf = make_coef<A>(table);
         if (dag)
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF, UN, ROWS, CLV, TAB>), grid,
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, true, TX, TY, R, PF, UN, ROWS, CLV>), grid,
                                dim3(TX * TY), 0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out,
                                (A)diag, nrhs, (const SS *)clover, cf);
         else
-            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF, UN, ROWS, CLV, TAB>), grid,
+            hipLaunchKernelGGL((k_apply_tiled<NOFF, WS, SS, A, false, TX, TY, R, PF, UN, ROWS, CLV>), grid,
                                dim3(TX * TY), 0, st, g, ntx, nty, (const WS *)W, (const SS *)in, (SS *)out,
                                (A)diag, nrhs, (const SS *)clover, cf);
         return hipGetLastError();
@@ -136,7 +136,7 @@ template <typename WS, typename SS, typename A, int ROWS, bool CLV>
 hipError_t stored_ext(const Geom &g, int rblk, const void *W, const void *in, void *out, double diag,
                       int nrhs, bool dag, hipStream_t st, const void *clover, const double *table) {
 #define BRI_EXT(TX, TY, R, PF, UN) \
-    tiled<80, WS, SS, A, TX, TY, R, PF, UN, ROWS, CLV, true>(g, W, in, out, diag, nrhs, dag, st, clover, table)
+    tiled<80, WS, SS, A, TX, TY, R, PF, UN, ROWS, CLV>(g, W, in, out, diag, nrhs, dag, st, clover, table)
     const int lx = g.L[0];
     const bool small = lx <= 16;
     if (rblk != 1 && rblk != 2) return hipErrorInvalidValue;

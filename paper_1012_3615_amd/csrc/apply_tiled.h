@@ -19,8 +19,12 @@ namespace bri {
 // Options for the production operator: ROWS = 2 reads the two-row store of
 // back-projected (SU(3)) transporters and rebuilds the third row; CLV adds
 // the clover term, a Hermitian 6x6 block per chirality and site, at n = 0.
-// TAB takes lambda_k, rho_k from the argument cf (any member of the generic
-// class of Sec. 8) instead of the Brillouin constants.
+// lambda_k and rho_k come from the by-value argument cf (any member of the
+// generic class of Sec. 8; the host fills in the Brillouin column by
+// default).  In scalar registers they also cost no vector registers: with
+// compile-time constants, which gfx9 VOP3 instructions cannot encode as
+// literals, the FP32 32x8 kernel held them in VGPRs (137 instead of 123,
+// three waves per SIMD instead of four).
 template <int TX, int TY>
 struct TileShape {
     static constexpr int HX = TX + 2, HY = TY + 2, NH = HX * HY, NT = TX * TY;
@@ -28,7 +32,7 @@ struct TileShape {
 };
 
 template <int NOFF, typename WS, typename SS, typename A, bool DAG, int TX, int TY, int R, bool PF = false,
-          bool UN = false, int ROWS = 3, bool CLV = false, bool TAB = false>
+          bool UN = false, int ROWS = 3, bool CLV = false>
 __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty,
                                                         const WS *__restrict__ W,
                                                         const SS *__restrict__ in,
@@ -179,9 +183,8 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                     return;
                 }
                 const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
-                const A lam = TAB ? coef_pick(cf.lam, k) : lam_rt<A>(k);
-                const A rho0 = TAB ? coef_pick(cf.rho, k) : rho_rt<A>(k);
-                const A rho = DAG ? -rho0 : rho0;
+                const A lam = coef_pick(cf.lam, k);
+                const A rho = DAG ? -coef_pick(cf.rho, k) : coef_pick(cf.rho, k);
                 cx<A> w[3][3];
                 if (PF) {
 #pragma unroll
