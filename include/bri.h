@@ -170,7 +170,8 @@ int32_t bri_get_apply_kernel(bri_prec w_prec, bri_prec s_prec);
  * inner_prec == BRI_F32 / BRI_F16: defect correction; the outer loop forms
  * r = b - D x in FP64 with W_hi, the inner CGNE solves D e = r in FP32
  * arithmetic with W_lo (F32 or F16 transporters, same n_offsets) to relative
- * inner_tol, and x += e.  b and x are FP64 SoA spinors ([rhs][12][V]); x holds
+ * inner_tol (or to max(inner_tol, tol / (2 r)) with r the worst relative
+ * true residual left, so the last cycle does not overshoot), and x += e.  b and x are FP64 SoA spinors ([rhs][12][V]); x holds
  * the initial guess on entry and the solution on exit.  All right-hand sides
  * iterate together (one fused apply per iteration) with their own scalars;
  * converged columns are frozen.  Reductions are deterministic FP64. */

@@ -3,7 +3,8 @@
 //
 // Outer loop (FP64, W_hi):  r = b - D x;  stop when |r_i|/|b_i| <= tol for
 //   every right-hand side i;  otherwise solve D e = r/|r| approximately and
-//   set x += |r| e.
+//   set x += |r| e.  The inner solve reduces its residual by inner_tol, or
+//   only by what the final tolerance still needs (times 1/2) when that is less.
 // Inner loop (CGNE, FP32 storage with W_lo in FP32 or FP16, or FP64 with
 //   W_hi for the plain solver), per right-hand side i:
 //     z = D^dag r, p = z, zz = |z|^2
@@ -221,17 +222,22 @@ static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc
         BRI_HIP(hipMemcpyAsync(scale, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c.st), "copy");
         BRI_HIP(hipMemcpyAsync(unscale, usc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c.st), "copy");
         int it = 0;
+        // worst relative residual among the unconverged columns
+        double worst = 0.0;
+        for (int i = 0; i < nrhs; ++i)
+            if (sc[i] > 0.0) worst = std::fmax(worst, std::sqrt(rr[2 * i] / std::fmax(bb[2 * i], 1e-300)));
         if (mixed) {
+            // reduce by inner_tol per cycle, but no further than the final
+            // tolerance needs (half of it, for the inner solve's rounding):
+            // the last cycle then stops early instead of overshooting
+            const double need = worst > 0.0 ? 0.5 * p->tol / worst : 0.5;
+            const double rel = std::fmin(0.5, std::fmax(p->inner_tol, need));
             float *r_lo = (float *)(c.w + L.r);
             BRI_HIP((convert<double, float>(n, nrhs, r_hi, r_lo, scale, c.st)), "convert");
-            BRI_TRY(inner_cgne<float>(c, lo, BRI_F32, p->inner_tol, p->max_iter - iters, p->check_every, &it,
-                                      &applies));
+            BRI_TRY(inner_cgne<float>(c, lo, BRI_F32, rel, p->max_iter - iters, p->check_every, &it, &applies));
             BRI_HIP(accum<float>(n, nrhs, (const float *)(c.w + L.e), x, unscale, c.st), "accumulate");
         } else {
             // plain FP64: aim the inner solve at the final tolerance of the worst column
-            double worst = 0.0;
-            for (int i = 0; i < nrhs; ++i)
-                if (sc[i] > 0.0) worst = std::fmax(worst, std::sqrt(rr[2 * i] / std::fmax(bb[2 * i], 1e-300)));
             const double rel = worst > 0.0 ? std::fmin(0.5, 0.5 * p->tol / worst) : 0.5;
             BRI_HIP((convert<double, double>(n, nrhs, r_hi, (double *)(c.w + L.r), scale, c.st)), "convert");
             BRI_TRY(inner_cgne<double>(c, hi, BRI_F64, rel, p->max_iter - iters, p->check_every, &it,
