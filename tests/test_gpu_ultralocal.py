@@ -13,6 +13,7 @@ import pytest
 
 import synth
 from oracle import production, smearing, ultralocal
+from oracle.gamma import gamma5
 from tests.helpers import dev, log, soa_to_canon
 
 pytestmark = pytest.mark.gpu
@@ -160,3 +161,32 @@ def test_overlap_with_hypercube_kernel(bri):
     got = soa_to_canon(dims, out).reshape(2, -1)
     for r in range(2):
         assert np.linalg.norm(got[r] - want[r]) <= (2 * err + 1e-12) * np.linalg.norm(psi[r])
+
+
+def test_table_fullsize_sampled(bri):
+    """32^3 x 64 (the benchmark's lattice and launch): the hypercube column
+    with FP32 and FP64 stored transporters, D and D^dag, on 64 random sites
+    plus corners computed site by site by the oracle."""
+    import torch
+    dims, mass, t = (32, 32, 32, 64), 0.1, TABLES["hypercube"]
+    u = synth.gauge_links(dims, 0.3, 4001)
+    psi = synth.gaussian_spinor(dims, 4002, nrhs=1)
+    rng = np.random.default_rng(8414)
+    sites = np.concatenate([np.stack([rng.integers(0, L, 64) for L in dims], axis=1),
+                            np.array([[0, 0, 0, 0], [31, 31, 31, 63], [0, 31, 0, 63]])])
+    ref = ultralocal.apply_at(u, psi[0], mass, t, sites)
+    # D^dag = gamma5 D gamma5 for every member of the class (pinned in the oracle tests)
+    g5 = gamma5()
+    p5 = np.einsum("st,...tc->...sc", g5, psi[0])
+    ref_dag = np.einsum("st,ntc->nsc", g5, ultralocal.apply_at(u, p5, mass, t, sites))
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    for p in (1, 0):
+        log(f"generic class fullsize prec={p}")
+        op = bri.Operator(bri.bri_build_transporters(dims, U, p, 80), coef=t)
+        x = bri.bri_pack_spinor(dims, dev(psi), p)
+        for dag, want in ((False, ref), (True, ref_dag)):
+            out = bri.bri_unpack_spinor(dims, bri.bri_apply_op(dims, op, x, mass, dagger=dag)).cpu().numpy()[0]
+            got = np.stack([out[tt, z, y, xx] for xx, y, z, tt in sites])
+            assert rel(got, want) <= TOL[p], (p, dag)
+        del op, x
+        torch.cuda.empty_cache()
