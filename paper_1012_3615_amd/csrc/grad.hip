@@ -8,8 +8,9 @@
 //      W(x,n) = (1/k) sum_{mu in supp n} W(x, n - s_mu mu) L(x,n,mu),
 //      L = U_mu(x+n-mu) (s_mu = +1) or U_mu(x+n)^dag (s_mu = -1),
 //    so G_{n - s_mu mu}(x) receives (1/k) G_n(x) L^dag.  Steps 1 and 2 run
-//    as one pass in reverse hop order (4 -> 1): each lower-level gradient
-//    pulls these terms from its parents, which are final by then.
+//    together, one launch per hop count in reverse order (4 -> 1): each
+//    lower-level gradient pulls these terms from its parents, which are
+//    final by then.
 // 3. Each link collects, without atomics, the product-rule terms of every
 //    (x, n, mu) whose last step runs over it:
 //      s_mu = +1: U_mu(y), y = x+n-mu:  += (1/k) W(x, n-mu)^dag G_n(x)
@@ -35,13 +36,20 @@ __device__ __forceinline__ void stm(double2 *p, size_t V, const cx<double> m[3][
     for (int e = 0; e < 9; ++e) st(p + e * V, m[e / 3][e % 3]);
 }
 
-// direct gradient of the transporter of offset n at the site:
+// site x + d (periodic) from the coordinates of x, by integer arithmetic (a
+// table of neighbour indices would be indexed at run time, i.e. in scratch)
+__device__ __forceinline__ int site_at(const Geom &g, const int c[4], int d0, int d1, int d2, int d3) {
+    auto w = [](int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); };
+    return w(c[0] + d0, g.L[0]) +
+           g.L[0] * (w(c[1] + d1, g.L[1]) + g.L[1] * (w(c[2] + d2, g.L[2]) + g.L[2] * w(c[3] + d3, g.L[3])));
+}
+
+// direct gradient of the transporter of offset n at the site (y = x + n):
 // G = sum_rhs sum_s (C(n) chi(x))_s psi_s(x+n)^dag
-__device__ inline void grad_direct(const Nbr &nb, int site, size_t V, const double2 *__restrict__ chi,
+__device__ inline void grad_direct(int site, int y, size_t V, const double2 *__restrict__ chi,
                                    const double2 *__restrict__ psi, int nrhs, const int n[4], cx<double> G[3][3]) {
     const int k = (n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0);
     const double lam = lam_rt<double>(k), rho = rho_rt<double>(k);
-    const int y = nbr_rt(nb, n[0], n[1], n[2], n[3]);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -72,78 +80,99 @@ __device__ inline void grad_direct(const Nbr &nb, int site, size_t V, const doub
     }
 }
 
-// steps 1 and 2 in one pass, level by level from 4 hops down to 1: the full
-// gradient of the transporter of offset P is its direct term plus what its
-// parents p = P + s e_nu (nu outside the support of P, s = +-1; one hop more)
-// pass down through their last link,
+// Offsets of each hop count k (index i = (nx+1) + 3(ny+1) + 9(nz+1) + 27(nt+1),
+// increasing): 1, 8, 24, 32, 16 of them.
+struct LevelTable {
+    signed char idx[5][32];
+    int count[5];
+};
+constexpr LevelTable make_levels() {
+    LevelTable t{};
+    for (int i = 0; i < 81; ++i) {
+        const int k = (i % 3 != 1) + ((i / 3) % 3 != 1) + ((i / 9) % 3 != 1) + (i / 27 != 1);
+        t.idx[k][t.count[k]++] = (signed char)i;
+    }
+    return t;
+}
+constexpr LevelTable kLevels = make_levels();
+__constant__ LevelTable c_levels = make_levels();
+
+// steps 1 and 2, one launch per hop count k from 4 down to 1: the full
+// gradient of the transporter of offset P (k hops) is its direct term plus
+// what its parents p = P + s e_nu (nu outside the support of P, s = +-1; one
+// hop more) pass down through their last link,
 //   G_P += (1/|p|) G_p L^dag,  L = U_nu(x+P) (s = +1) or U_nu(x+P-nu)^dag (s = -1),
 // the reverse of the same-site recursion that builds the transporters.  The
-// parents are final when their level is done, so every G is written once.
-__global__ __launch_bounds__(kB) void k_grad_pull(Geom g, const double2 *__restrict__ U,
-                                                  const double2 *__restrict__ chi, const double2 *__restrict__ psi,
-                                                  int nrhs, double2 *__restrict__ G80) {
-    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+// parents are final once the previous launch is done, so every G is written
+// once.  One thread per (site, offset of the level): the offsets of a block
+// of sites are consecutive blocks, kept on one XCD, so chi(x) and the psi
+// neighbours they share are read through that XCD's L2.
+__global__ __launch_bounds__(kB) void k_grad_level(Geom g, int k, const double2 *__restrict__ U,
+                                                   const double2 *__restrict__ chi,
+                                                   const double2 *__restrict__ psi, int nrhs,
+                                                   double2 *__restrict__ G80) {
+    const int cnt = c_levels.count[k];
+    const int lin = xcd_block(blockIdx.x, gridDim.x);
+    const int site = (lin / cnt) * kB + threadIdx.x;
     if (site >= g.V) return;
+    const int i = c_levels.idx[k][lin % cnt];
     const size_t V = (size_t)g.V;
     int c[4];
     coords(g, site, c);
-    const Nbr nb = make_nbr(g, c);
-#pragma unroll 1
-    for (int k = 4; k >= 1; --k) {
-        const double inv = 1.0 / (k + 1);
-#pragma unroll 1
-        for (int i = 0; i < 81; ++i) {
-            const int n[4] = {i % 3 - 1, (i / 3) % 3 - 1, (i / 9) % 3 - 1, i / 27 - 1};
-            if ((n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0) != k) continue;
-            cx<double> G[3][3];
-            grad_direct(nb, site, V, chi, psi, nrhs, n, G);
-#pragma unroll 1
-            for (int nu = 0; nu < 4 && k < 4; ++nu) {
-                if (n[nu] != 0) continue;
-#pragma unroll 1
-                for (int sgn = -1; sgn <= 1; sgn += 2) {
-                    int p[4] = {n[0], n[1], n[2], n[3]};
-                    p[nu] = sgn;
-                    const int ip = (p[0] + 1) + 3 * (p[1] + 1) + 9 * (p[2] + 1) + 27 * (p[3] + 1);
-                    cx<double> Gp[3][3];
-                    ldm(G80 + (size_t)plane80_rt(ip) * 9 * V + site, V, Gp);
-                    // the parent's last link: base site x+P (forward) or x+P-nu (backward)
-                    int d[4] = {n[0], n[1], n[2], n[3]};
-                    if (sgn < 0) d[nu] = -1;
-                    const int yl = nbr_rt(nb, d[0], d[1], d[2], d[3]);
-                    cx<double> l[3][3];
-                    const double2 *pu = U + (size_t)nu * 9 * V + yl;
+    const int n[4] = {i % 3 - 1, (i / 3) % 3 - 1, (i / 9) % 3 - 1, i / 27 - 1};
+    const double inv = 1.0 / (k + 1);
+    cx<double> G[3][3];
+    grad_direct(site, site_at(g, c, n[0], n[1], n[2], n[3]), V, chi, psi, nrhs, n, G);
+    // nu and sgn unrolled: the offset arrays are then indexed at compile time
+    // (registers, not scratch)
 #pragma unroll
-                    for (int e = 0; e < 9; ++e) {
-                        cx<double> v = ldc<double>(pu + e * V);
-                        if (sgn > 0) l[e / 3][e % 3] = v; else l[e % 3][e / 3] = cconj(v);
-                    }
-                    // G += inv * Gp * l^dag
+    for (int nu = 0; nu < 4; ++nu) {
+        if (k == 4 || n[nu] != 0) continue;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            int p[4] = {n[0], n[1], n[2], n[3]};
+            p[nu] = sgn;
+            const int ip = (p[0] + 1) + 3 * (p[1] + 1) + 9 * (p[2] + 1) + 27 * (p[3] + 1);
+            cx<double> Gp[3][3];
+            ldm(G80 + (size_t)plane80_rt(ip) * 9 * V + site, V, Gp);
+            // the parent's last link: base site x+P (forward) or x+P-nu (backward)
+            int d[4] = {n[0], n[1], n[2], n[3]};
+            if (sgn < 0) d[nu] = -1;
+            const int yl = site_at(g, c, d[0], d[1], d[2], d[3]);
+            cx<double> l[3][3];
+            const double2 *pu = U + (size_t)nu * 9 * V + yl;
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) {
-                            cx<double> t = cmake(0.0, 0.0);
-#pragma unroll
-                            for (int q = 0; q < 3; ++q) t = cmac(t, Gp[a][q], cconj(l[b][q]));
-                            G[a][b] = caxpy(inv, t, G[a][b]);
-                        }
-                }
+            for (int e = 0; e < 9; ++e) {
+                cx<double> v = ldc<double>(pu + e * V);
+                if (sgn > 0) l[e / 3][e % 3] = v; else l[e % 3][e / 3] = cconj(v);
             }
-            stm(G80 + (size_t)plane80_rt(i) * 9 * V + site, V, G);
+            // G += inv * Gp * l^dag
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    cx<double> t = cmake(0.0, 0.0);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) t = cmac(t, Gp[a][q], cconj(l[b][q]));
+                    G[a][b] = caxpy(inv, t, G[a][b]);
+                }
         }
     }
+    stm(G80 + (size_t)plane80_rt(i) * 9 * V + site, V, G);
 }
 
 // step 3: gather onto the links; the lower-level transporter W(x, m) is read
 // from the 40-offset FP64 store, at x when m is stored there, otherwise as
-// W(x+m, x)^dag from x+m
+// W(x+m, x)^dag from x+m.  The four directions of a block of sites are
+// consecutive blocks on one XCD: they read the same G and W planes around
+// those sites, which then come from that XCD's L2.
 __global__ __launch_bounds__(kB) void k_grad_gather(Geom g, const double2 *__restrict__ W40,
                                                     const double2 *__restrict__ G80,
                                                     double2 *__restrict__ gradU, double scale) {
-    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lin = xcd_block(blockIdx.x, gridDim.x);
+    const int mu = lin % 4;
+    const int site = (lin / 4) * kB + threadIdx.x;
     if (site >= g.V) return;
-    const int mu = blockIdx.y;
     const size_t V = (size_t)g.V;
     int c[4];
     coords(g, site, c);
@@ -253,9 +282,10 @@ namespace {
 bri_status grad_steps(const Geom &g, const double *U, const double2 *W40, const double *chi, const double *psi,
                       int nrhs, double scale, double *gradU, double2 *G80, hipStream_t st) {
     dim3 grid((g.V + kB - 1) / kB);
-    hipLaunchKernelGGL(k_grad_pull, grid, dim3(kB), 0, st, g, (const double2 *)U, (const double2 *)chi,
-                       (const double2 *)psi, nrhs, G80);
-    hipLaunchKernelGGL(k_grad_gather, dim3(grid.x, 4), dim3(kB), 0, st, g, W40, (const double2 *)G80,
+    for (int k = 4; k >= 1; --k)
+        hipLaunchKernelGGL(k_grad_level, dim3(grid.x * kLevels.count[k]), dim3(kB), 0, st, g, k, (const double2 *)U,
+                           (const double2 *)chi, (const double2 *)psi, nrhs, G80);
+    hipLaunchKernelGGL(k_grad_gather, dim3(grid.x * 4), dim3(kB), 0, st, g, W40, (const double2 *)G80,
                        (double2 *)gradU, scale);
     return hip_check(hipGetLastError(), "gradient kernels");
 }
