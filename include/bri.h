@@ -81,7 +81,11 @@ typedef enum {
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *bri_last_error(void);
-/* ABI revision of this header (incremented on incompatible change). */
+/* ABI revision of this header (incremented on incompatible change; 3 added
+ * the coefficient table to bri_operator).  bri_abi_version() returns the
+ * revision the library was built with; a caller compares it to
+ * BRI_ABI_VERSION. */
+#define BRI_ABI_VERSION 3
 int32_t bri_abi_version(void);
 
 /* ---- sizes (bytes) of the SoA buffers ----------------------------------- */

@@ -39,6 +39,10 @@ class bri_solve_stats(ctypes.Structure):
     ]
 
 
+# BRI_ABI_VERSION of include/bri.h that the structures below mirror
+ABI_VERSION = 3
+
+
 class bri_operator(ctypes.Structure):
     _fields_ = [
         ("W", ctypes.c_void_p),
@@ -119,4 +123,7 @@ def load(path=LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.bri_abi_version() != ABI_VERSION:
+        raise ImportError(f"{path} implements ABI revision {lib.bri_abi_version()}, this binding "
+                          f"revision {ABI_VERSION}: rebuild the library")
     return lib

@@ -118,7 +118,7 @@ extern "C" {
 
 const char *bri_last_error(void) { return g_last_error.c_str(); }
 
-int32_t bri_abi_version(void) { return 3; }
+int32_t bri_abi_version(void) { return BRI_ABI_VERSION; }
 
 size_t bri_spinor_bytes(bri_dims d, bri_prec p, int32_t nrhs) {
     Geom g;
