@@ -142,3 +142,22 @@ def _big_links(dims):
     if dims not in _big:
         _big[dims] = synth.gauge_links(dims, 0.4, 3001)
     return _big[dims]
+
+
+def test_maximum_rhs_count(bri):
+    """BRI_MAX_RHS (64) right-hand sides in one mixed solve on a 2^4 lattice
+    (each column frozen as it converges), and 65 rejected before any work."""
+    dims, mass = (2, 2, 2, 2), 0.2
+    u = synth.gauge_links(dims, 0.4, 8501)
+    b = synth.gaussian_spinor(dims, 8502, nrhs=64)
+    log("solve with 64 right-hand sides")
+    x, info = solve(bri, dims, u, b, mass, bri.F32, inner_tol=1e-3)
+    assert info["converged"]
+    for r in range(64):
+        assert oracle_residual(u, x[r], b[r], mass) <= 1.05e-10, r
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    W = bri.bri_build_transporters(dims, U, bri.F64, 80)
+    b65 = bri.bri_pack_spinor(dims, dev(np.concatenate([b, b[:1]])), bri.F64)
+    with pytest.raises(bri.BriError) as e:
+        bri.bri_solve_cgne(dims, W, b65, mass, bri.solve_params(tol=1e-10, inner_prec=bri.F64))
+    assert e.value.status == -1
