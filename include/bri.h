@@ -316,7 +316,8 @@ bri_status bri_apply_op(bri_dims d, const bri_operator *op, bri_prec s_prec, dou
 /* bri_solve_cgne for a general operator: op_hi in FP64 (w_prec F64, clover
  * F64) for the outer residual and the plain solver; op_lo for the inner
  * solve of defect correction (w_prec = p->inner_prec, clover F32), the same
- * operator at lower precision.  p->n_offsets is ignored (each operator
+ * operator at lower precision (a different coefficient table, or a clover
+ * term on one side only, is BRI_E_ARG).  p->n_offsets is ignored (each operator
  * carries its own).  Workspace: bri_solve_workspace_bytes. */
 bri_status bri_solve_cgne_op(bri_dims d, const bri_solve_params *p, const bri_operator *op_hi,
                              const bri_operator *op_lo, double mass, const double *b, double *x,

@@ -289,6 +289,12 @@ bri_status bri_solve_cgne_op(bri_dims d, const bri_solve_params *p, const bri_op
     if (p->inner_prec != BRI_F64) {
         s = op_from_public(op_lo, &lo);
         if (s != BRI_OK) return s;
+        // the inner operator is the same operator at lower precision
+        const double *ch = hi.coef, *cl = lo.coef;
+        bool same = (ch == nullptr) == (cl == nullptr);
+        for (int i = 0; same && ch && i < 9; ++i) same = ch[i] == cl[i];
+        if (!same || (hi.clover == nullptr) != (lo.clover == nullptr))
+            return fail(BRI_E_ARG, "op_lo must be op_hi at lower precision (same coefficient table and clover term)");
     }
     return solve_core(d, p, hi, lo, mass, b, x, nrhs, work, work_bytes, stats, stream);
 }

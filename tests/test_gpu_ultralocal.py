@@ -135,6 +135,12 @@ def test_table_rejections(bri):
         bri.bri_apply_op(dims, bri.Operator(W80, coef=bad), x, 0.1)
     with pytest.raises(ValueError, match="nine entries"):
         bri.Operator(W80, coef=(1.0, 2.0))
+    # the inner operator of a mixed solve must carry the same table
+    W32 = bri.bri_build_transporters(dims, U, bri.F32, 80)
+    p = bri.solve_params(tol=1e-10, inner_tol=1e-3, inner_prec=bri.F32)
+    with pytest.raises(bri.BriError, match="same coefficient table"):
+        bri.bri_solve_cgne_op(dims, bri.Operator(W80, coef=bri.TABLE_WILSON), x, 0.1, p,
+                              op_lo=bri.Operator(W32, coef=bri.TABLE_HYPERCUBE))
 
 
 def test_overlap_with_hypercube_kernel(bri):
