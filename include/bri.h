@@ -366,8 +366,9 @@ bri_status bri_ritz_values(int32_t k, const double *alpha, const double *beta, i
  * Rayleigh-Ritz for H on span{X}.  Outputs: vecs [n_low][12][V] orthonormal
  * (FP64), evals (host, signed eigenvalues of H by increasing |.|), resid
  * (host, |H v_i - evals_i v_i|).  The modes are exact only as far as the
- * residuals say; the cost is O(k^2) field reads for the re-orthogonalisation,
- * so this is meant for small lattices.  Workspace:
+ * residuals say; the cost is O(k^2) field reads for the re-orthogonalisation
+ * and k fields of basis memory (24^3 x 48, k = 160: 20 GB, about 2 s on one
+ * MI355X).  Workspace:
  * bri_lowmodes_workspace_bytes(d, k, n_low). */
 size_t bri_lowmodes_workspace_bytes(bri_dims d, int32_t k, int32_t n_low);
 bri_status bri_overlap_lowmodes(bri_dims d, const bri_operator *op, double mass, int32_t k, const double *v0,
