@@ -20,8 +20,12 @@ For S2 = phi^dag (D^dag D)^{-1} phi with X = (D^dag D)^{-1} phi the first
 variation is dS2 = -2 Re <D X, dD X>, so dS2/dU is the link gradient above with
 (chi, psi) = (-2 D X, X), and dS2/dphi = 2 X.
 
+``table`` (optional) takes another member of the generic class of Sec. 8
+(``oracle.ultralocal``); S then uses that operator.
+
 Parity: pinned (central finite differences of the oracle's own S, which is
-itself pinned; closed-form psi gradient).
+itself pinned, for the Brillouin operator and for a generic-class table;
+closed-form psi gradient).
 """
 from __future__ import annotations
 
@@ -33,18 +37,22 @@ from .lattice import all_offsets, shift, dag
 from .transporters import link_step, path_orderings, whole_lattice
 
 
-def action(U, chi, psi, mass):
+def action(U, chi, psi, mass, table=None):
     from .dirac import apply
-    return float(np.vdot(chi, apply(U, psi, mass)).real)
+    from . import ultralocal
+    d = apply(U, psi, mass) if table is None else ultralocal.apply(U, psi, mass, table)
+    return float(np.vdot(chi, d).real)
 
 
-def grad_psi(U, chi, mass):
-    return apply_dag(U, chi, mass)
+def grad_psi(U, chi, mass, table=None):
+    from . import ultralocal
+    return apply_dag(U, chi, mass) if table is None else ultralocal.apply_dag(U, chi, mass, table)
 
 
-def grad_links(U, chi, psi, mass):
+def grad_links(U, chi, psi, mass, table=None):
     """dS/dU for S = Re <chi, D psi>; same shape as U."""
-    lam, rho = operator_weights(mass)
+    from . import ultralocal
+    lam, rho = operator_weights(mass) if table is None else ultralocal.weights(table, mass)
     gu = np.zeros_like(U)
     for n in all_offsets():
         phi = np.einsum("ts,...tc->...sc", np.conj(coefficient_matrix(lam, rho, n)), chi)  # C^dag chi

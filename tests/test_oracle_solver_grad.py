@@ -92,3 +92,31 @@ def test_link_gradient_linear_in_chi_and_psi(grad_setup):
     # S is real-linear in chi: i*chi gives S' = Re<i chi, D psi> = Im<chi, D psi>
     s_re = grad.action(u, chi, psi, MASS)
     assert math.isfinite(s_re)
+
+
+def test_link_gradient_generic_table_central_difference(grad_setup):
+    """The same chain rule with the hypercube column of Tab. rholambda."""
+    from oracle import ultralocal
+    u, chi, psi = grad_setup
+    tab = ultralocal.HYPERCUBE
+    g = grad.grad_links(u, chi, psi, MASS, table=tab)
+    assert rel(g, grad.grad_links(u, chi, psi, MASS)) > 1e-3  # the table matters
+    gmax = np.abs(g).max()
+    rng = np.random.default_rng(46)
+    for _ in range(8):
+        idx = tuple(int(rng.integers(s)) for s in u.shape)
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            def s_of(h):
+                uu = u.copy()
+                uu[idx] += unit * h
+                return grad.action(uu, chi, psi, MASS, table=tab)
+            fd = _fd(s_of)
+            an = g[idx].real if part == "re" else g[idx].imag
+            assert abs(fd - an) <= 1e-6 * gmax, (idx, part, fd, an)
+    gp = grad.grad_psi(u, chi, MASS, table=tab)
+    idx = (1, 0, 2, 1, 3, 2)
+    def s_psi(h):
+        p = psi.copy()
+        p[idx] += h
+        return grad.action(u, chi, p, MASS, table=tab)
+    assert abs(_fd(s_psi) - gp[idx].real) <= 1e-7 * max(1.0, abs(gp[idx].real))
