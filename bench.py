@@ -173,7 +173,7 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
             "ratio_mixed_f16w_over_plain_batched": t_half / t_batched}
 
 
-def solve_cfg3(torch, bri, dev, tol=1e-10):
+def solve_24x48(torch, bri, dev, tol=1e-10):
     """24^3 x 48, links eps 0.4 (seed 3001), Gaussian right-hand side (seed
     3002), m in {0.05, 0.2, 0.5}: mixed precision (FP32 transporters, inner
     1e-3; FP16 transporters, inner 1e-2) against plain FP64 CGNE, all to a true
@@ -572,7 +572,7 @@ def main():
         res["variants_16x16x16x32"] = variants_16_32(torch, bri, dev)
         res["gradient_16x16x16x32"] = gradient_timing(torch, bri, dev)
     if not a.no_extras and not a.no_solve:
-        res["solve_24x24x24x48"] = solve_cfg3(torch, bri, dev)
+        res["solve_24x24x24x48"] = solve_24x48(torch, bri, dev)
     if not a.no_extras and not a.no_solve:
         del W, out
         torch.cuda.empty_cache()

@@ -82,7 +82,7 @@ typedef enum {
 /* Message for the last failing call on this thread ("" if none). */
 const char *bri_last_error(void);
 /* ABI revision of this header (incremented on incompatible change; 3 added
- * the coefficient table to bri_operator).  bri_abi_version() returns the
+ * the coefficient table to bri_operator and to the gradient calls).  bri_abi_version() returns the
  * revision the library was built with; a caller compares it to
  * BRI_ABI_VERSION. */
 #define BRI_ABI_VERSION 3
@@ -212,10 +212,12 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
  * entries as unconstrained complex numbers, through the path averaging of
  * the transporters.  The transporters are rebuilt from U inside the call
  * (not stored across calls).  The psi gradient is D^dag chi (bri_apply_dag).
- * work: bri_grad_workspace_bytes(d). */
+ * coef: NULL for the Brillouin operator, or the nine host doubles of another
+ * member of the generic class of Sec. 8 (as in bri_operator; BRI_E_ARG if
+ * not finite).  work: bri_grad_workspace_bytes(d). */
 size_t bri_grad_workspace_bytes(bri_dims d);
 bri_status bri_grad_links(bri_dims d, const double *U_soa, const double *chi, const double *psi,
-                          int32_t nrhs, double scale, double *gradU, void *work,
+                          int32_t nrhs, double scale, const double *coef, double *gradU, void *work,
                           size_t work_bytes, void *stream);
 /* The same with the FP64 40-offset transporters of U given (built by
  * bri_build_transporters(d, U_soa, W40, BRI_F64, 40, ...) in the same
@@ -223,8 +225,8 @@ bri_status bri_grad_links(bri_dims d, const double *U_soa, const double *chi, co
  * work: bri_grad_workspace_bytes_w(d). */
 size_t bri_grad_workspace_bytes_w(bri_dims d);
 bri_status bri_grad_links_w(bri_dims d, const double *U_soa, const double *W40, const double *chi,
-                            const double *psi, int32_t nrhs, double scale, double *gradU, void *work,
-                            size_t work_bytes, void *stream);
+                            const double *psi, int32_t nrhs, double scale, const double *coef, double *gradU,
+                            void *work, size_t work_bytes, void *stream);
 
 /* ---- production operator (Sec. 5) -----------------------------------------
  * The operator of the paper's quenched tests uses (i) links after one APE

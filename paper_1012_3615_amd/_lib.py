@@ -83,9 +83,9 @@ PROTOTYPES = {
     "bri_solve_cgne": (_i32, [_D, ctypes.POINTER(bri_solve_params), _vp, _vp, _dbl, _vp, _vp,
                               _i32, _vp, _sz, ctypes.POINTER(bri_solve_stats), _vp]),
     "bri_grad_workspace_bytes": (_sz, [_D]),
-    "bri_grad_links": (_i32, [_D, _vp, _vp, _vp, _i32, _dbl, _vp, _vp, _sz, _vp]),
+    "bri_grad_links": (_i32, [_D, _vp, _vp, _vp, _i32, _dbl, _vp, _vp, _vp, _sz, _vp]),
     "bri_grad_workspace_bytes_w": (_sz, [_D]),
-    "bri_grad_links_w": (_i32, [_D, _vp, _vp, _vp, _vp, _i32, _dbl, _vp, _vp, _sz, _vp]),
+    "bri_grad_links_w": (_i32, [_D, _vp, _vp, _vp, _vp, _i32, _dbl, _vp, _vp, _vp, _sz, _vp]),
     "bri_project_su3": (_i32, [ctypes.c_int64, _vp, _vp, _vp]),
     "bri_ape_smear": (_i32, [_D, _vp, _vp, _dbl, _vp]),
     "bri_transporter_bytes_ex": (_sz, [_D, _i32, _i32, _i32]),

@@ -535,9 +535,11 @@ def bri_overlap_apply(dims, op, psi, rho, m, lo, hi, degree, low_vecs=None, low_
 
 
 # ------------------------------------------------------------------ gradient
-def bri_grad_links(dims, U_soa, chi, psi, scale=1.0, W40=None):
+def bri_grad_links(dims, U_soa, chi, psi, scale=1.0, W40=None, coef=None):
     """scale * dS/dU (FP64 SoA links) for S = Re sum_rhs <chi, D psi>.  W40:
-    the FP64 40-offset transporters of U if already built (else rebuilt)."""
+    the FP64 40-offset transporters of U if already built (else rebuilt).
+    coef: None for the Brillouin operator, or a generic-class table (nine
+    numbers, as for Operator)."""
     _need_cuda(U_soa, chi, psi)
     V = volume(dims)
     _shape(U_soa, (4, 9, V, 2), "links")
@@ -546,6 +548,12 @@ def bri_grad_links(dims, U_soa, chi, psi, scale=1.0, W40=None):
     if prec_of(U_soa) != F64 or prec_of(chi) != F64 or prec_of(psi) != F64:
         raise ValueError("the link gradient is FP64")
     g = torch.empty_like(U_soa)
+    cf = None
+    if coef is not None:
+        coef = tuple(float(c) for c in coef)
+        if len(coef) != 9:
+            raise ValueError("a coefficient table has nine entries (lambda_0..4, rho_1..4)")
+        cf = (ctypes.c_double * 9)(*coef)
     if W40 is not None:
         _need_cuda(W40)
         _shape(W40, (40, 9, V, 2), "W40")
@@ -554,12 +562,13 @@ def bri_grad_links(dims, U_soa, chi, psi, scale=1.0, W40=None):
         nbytes = _lib_handle.bri_grad_workspace_bytes_w(_dims(dims))
         work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=U_soa.device)
         _check(_lib_handle.bri_grad_links_w(_dims(dims), _ptr(U_soa), _ptr(W40), _ptr(chi), _ptr(psi),
-                                            chi.shape[0], float(scale), _ptr(g), _ptr(work), nbytes, _stream()),
+                                            chi.shape[0], float(scale), cf, _ptr(g), _ptr(work), nbytes,
+                                            _stream()),
                "bri_grad_links_w")
         return g
     nbytes = _lib_handle.bri_grad_workspace_bytes(_dims(dims))
     work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=U_soa.device)
     _check(_lib_handle.bri_grad_links(_dims(dims), _ptr(U_soa), _ptr(chi), _ptr(psi), chi.shape[0],
-                                      float(scale), _ptr(g), _ptr(work), nbytes, _stream()),
+                                      float(scale), cf, _ptr(g), _ptr(work), nbytes, _stream()),
            "bri_grad_links")
     return g

@@ -10,18 +10,6 @@ namespace launch {
 
 constexpr int kGatherBlock = 256;
 
-// lambda_k, rho_k (k = 1..4) from a host table (lambda_0..4, rho_1..4), or
-// the Brillouin column of Tab. rholambda for nullptr
-template <typename A>
-Coef<A> make_coef(const double *table) {
-    Coef<A> c{};
-    for (int k = 1; k <= 4; ++k) {
-        c.lam[k] = (A)(table ? table[k] : lam_k(k));
-        c.rho[k] = (A)(table ? table[4 + k] : rho_k(k));
-    }
-    return c;
-}
-
 template <int NOFF, typename WS, typename SS, typename A, int TX, int TY, int R, bool PF = false,
           bool UN = false, int ROWS = 3, bool CLV = false>
 hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double diag, int nrhs,

@@ -1,5 +1,7 @@
 // Gradient of S = Re sum_rhs <chi, D psi> with respect to the links, through
 // the path averaging of the transporters (FP64).  g = dS/dRe U + i dS/dIm U.
+// D is the Brillouin operator or, with a coefficient table, any member of
+// the generic class of Sec. 8 (lambda_k, rho_k enter only the direct terms).
 //
 // 1. Per site x and offset n the transporter receives
 //      G_n(x) = sum_rhs sum_s (C(n)^dag chi(x))_s psi_s(x+n)^dag,
@@ -16,6 +18,8 @@
 //      s_mu = +1: U_mu(y), y = x+n-mu:  += (1/k) W(x, n-mu)^dag G_n(x)
 //      s_mu = -1: U_mu(y), y = x+n:     += (1/k) G_n(x)^dag W(x, n+mu)
 //    with W(x, 0) = 1.
+#include <cmath>
+
 #include "abi_internal.h"
 #include "stencil.h"
 #include "kernels.h"
@@ -47,9 +51,10 @@ __device__ __forceinline__ int site_at(const Geom &g, const int c[4], int d0, in
 // direct gradient of the transporter of offset n at the site (y = x + n):
 // G = sum_rhs sum_s (C(n) chi(x))_s psi_s(x+n)^dag
 __device__ inline void grad_direct(int site, int y, size_t V, const double2 *__restrict__ chi,
-                                   const double2 *__restrict__ psi, int nrhs, const int n[4], cx<double> G[3][3]) {
+                                   const double2 *__restrict__ psi, int nrhs, const int n[4], const Coef<double> &cf,
+                                   cx<double> G[3][3]) {
     const int k = (n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0);
-    const double lam = lam_rt<double>(k), rho = rho_rt<double>(k);
+    const double lam = coef_pick(cf.lam, k), rho = coef_pick(cf.rho, k);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -110,7 +115,7 @@ __constant__ LevelTable c_levels = make_levels();
 __global__ __launch_bounds__(kB) void k_grad_level(Geom g, int k, const double2 *__restrict__ U,
                                                    const double2 *__restrict__ chi,
                                                    const double2 *__restrict__ psi, int nrhs,
-                                                   double2 *__restrict__ G80) {
+                                                   double2 *__restrict__ G80, Coef<double> cf) {
     const int cnt = c_levels.count[k];
     const int lin = xcd_block(blockIdx.x, gridDim.x);
     const int site = (lin / cnt) * kB + threadIdx.x;
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(kB) void k_grad_level(Geom g, int k, const double2 
     const int n[4] = {i % 3 - 1, (i / 3) % 3 - 1, (i / 9) % 3 - 1, i / 27 - 1};
     const double inv = 1.0 / (k + 1);
     cx<double> G[3][3];
-    grad_direct(site, site_at(g, c, n[0], n[1], n[2], n[3]), V, chi, psi, nrhs, n, G);
+    grad_direct(site, site_at(g, c, n[0], n[1], n[2], n[3]), V, chi, psi, nrhs, n, cf, G);
     // nu and sgn unrolled: the offset arrays are then indexed at compile time
     // (registers, not scratch)
 #pragma unroll
@@ -280,19 +285,23 @@ namespace {
 // the three gradient steps with given FP64 40-offset transporters W40 and the
 // transporter-gradient store G80
 bri_status grad_steps(const Geom &g, const double *U, const double2 *W40, const double *chi, const double *psi,
-                      int nrhs, double scale, double *gradU, double2 *G80, hipStream_t st) {
+                      int nrhs, double scale, const double *coef, double *gradU, double2 *G80, hipStream_t st) {
     dim3 grid((g.V + kB - 1) / kB);
+    const Coef<double> cf = make_coef<double>(coef);
     for (int k = 4; k >= 1; --k)
         hipLaunchKernelGGL(k_grad_level, dim3(grid.x * kLevels.count[k]), dim3(kB), 0, st, g, k, (const double2 *)U,
-                           (const double2 *)chi, (const double2 *)psi, nrhs, G80);
+                           (const double2 *)chi, (const double2 *)psi, nrhs, G80, cf);
     hipLaunchKernelGGL(k_grad_gather, dim3(grid.x * 4), dim3(kB), 0, st, g, W40, (const double2 *)G80,
                        (double2 *)gradU, scale);
     return hip_check(hipGetLastError(), "gradient kernels");
 }
 
 bri_status grad_check(bri_dims d, Geom *g, const double *U, const double *chi, const double *psi, int32_t nrhs,
-                      double *gradU) {
+                      const double *coef, double *gradU) {
     if (!dims_ok(d, g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (coef)
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(coef[i])) return fail(BRI_E_ARG, "coefficient %d of the table is not finite", i);
     if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
     if (!aligned(U) || !aligned(chi) || !aligned(psi) || !aligned(gradU))
         return fail(BRI_E_ARG, "null or misaligned pointer");
@@ -307,11 +316,11 @@ bri_status grad_check(bri_dims d, Geom *g, const double *U, const double *chi, c
 extern "C" {
 
 bri_status bri_grad_links(bri_dims d, const double *U, const double *chi, const double *psi,
-                          int32_t nrhs, double scale, double *gradU, void *work, size_t work_bytes,
-                          void *stream) {
+                          int32_t nrhs, double scale, const double *coef, double *gradU, void *work,
+                          size_t work_bytes, void *stream) {
     g_last_error.clear();
     Geom g;
-    bri_status s = grad_check(d, &g, U, chi, psi, nrhs, gradU);
+    bri_status s = grad_check(d, &g, U, chi, psi, nrhs, coef, gradU);
     if (s != BRI_OK) return s;
     const size_t need = bri_grad_workspace_bytes(d);
     if (!aligned(work) || work_bytes < need)
@@ -324,15 +333,15 @@ bri_status bri_grad_links(bri_dims d, const double *U, const double *chi, const 
     // transporters rebuilt from the links (not kept from the forward pass)
     s = hip_check(build_w40_f64(g, (const double2 *)U, W40, st), "build transporters");
     if (s != BRI_OK) return s;
-    return grad_steps(g, U, W40, chi, psi, nrhs, scale, gradU, G80, st);
+    return grad_steps(g, U, W40, chi, psi, nrhs, scale, coef, gradU, G80, st);
 }
 
 bri_status bri_grad_links_w(bri_dims d, const double *U, const double *W40, const double *chi, const double *psi,
-                            int32_t nrhs, double scale, double *gradU, void *work, size_t work_bytes,
-                            void *stream) {
+                            int32_t nrhs, double scale, const double *coef, double *gradU, void *work,
+                            size_t work_bytes, void *stream) {
     g_last_error.clear();
     Geom g;
-    bri_status s = grad_check(d, &g, U, chi, psi, nrhs, gradU);
+    bri_status s = grad_check(d, &g, U, chi, psi, nrhs, coef, gradU);
     if (s != BRI_OK) return s;
     if (!aligned(W40)) return fail(BRI_E_ARG, "null or misaligned pointer");
     const size_t need = bri_grad_workspace_bytes_w(d);
@@ -340,7 +349,7 @@ bri_status bri_grad_links_w(bri_dims d, const double *U, const double *W40, cons
         return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", need);
     if (overlap(work, need, gradU, (size_t)g.V * 36 * 16) || overlap(work, need, W40, (size_t)g.V * 40 * 9 * 16))
         return fail(BRI_E_ARG, "the workspace overlaps gradU or the transporters");
-    return grad_steps(g, U, (const double2 *)W40, chi, psi, nrhs, scale, gradU, (double2 *)work,
+    return grad_steps(g, U, (const double2 *)W40, chi, psi, nrhs, scale, coef, gradU, (double2 *)work,
                       (hipStream_t)stream);
 }
 

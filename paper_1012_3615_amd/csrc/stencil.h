@@ -69,6 +69,18 @@ template <typename T>
 struct Coef {
     T lam[5], rho[5];
 };
+// lambda_k, rho_k (k = 1..4) from a host table (lambda_0..4, rho_1..4), or
+// the Brillouin column of Tab. rholambda for nullptr
+template <typename T>
+inline Coef<T> make_coef(const double *table) {
+    Coef<T> c{};
+    for (int k = 1; k <= 4; ++k) {
+        c.lam[k] = (T)(table ? table[k] : lam_k(k));
+        c.rho[k] = (T)(table ? table[4 + k] : rho_k(k));
+    }
+    return c;
+}
+
 // select by a wavefront-uniform k in 1..4 without indexing the argument array
 template <typename T>
 __device__ __forceinline__ T coef_pick(const T (&a)[5], int k) {

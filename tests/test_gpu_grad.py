@@ -37,11 +37,11 @@ def _setup(dims, seed, eps=0.3):
     return u, chi, psi
 
 
-def _ad_S(torch, ag, u, chi, psi, mass):
+def _ad_S(torch, ag, u, chi, psi, mass, coef=None):
     U = torch.from_numpy(u).cuda().requires_grad_(True)
     P = torch.from_numpy(psi).cuda().requires_grad_(True)
     C = torch.from_numpy(chi).cuda()
-    out = ag.apply(U, P, mass)
+    out = ag.apply(U, P, mass, 80, coef)
     S = torch.real(torch.vdot(C.reshape(-1), out.reshape(-1)))
     S.backward()
     return float(S), U.grad.cpu().numpy(), P.grad.cpu().numpy()
@@ -59,7 +59,7 @@ def test_link_and_psi_gradient_match_oracle(torch, ag, dims):
 
 
 def test_central_differences_8_4(torch, ag):
-    """cfg5 (8^4): AD against central differences of the GPU's own FP64 S."""
+    """8^4: AD against central differences of the GPU's own FP64 S."""
     import paper_1012_3615_amd as bri
     dims, mass, h = (8, 8, 8, 8), 0.1, 1e-6
     u, chi, psi = _setup(dims, 5001)
@@ -93,7 +93,7 @@ def test_central_differences_8_4(torch, ag):
 
 
 def test_local_differences_16_32(torch, ag):
-    """cfg5 (16^3 x 32): AD against central differences of S restricted to the
+    """16^3 x 32: AD against central differences of S restricted to the
     sites whose transporters contain the perturbed link, evaluated with the
     pointwise oracle and summed with math.fsum."""
     dims, mass, h = (16, 16, 16, 32), 0.1, 1e-6
@@ -194,3 +194,29 @@ def test_grad_with_given_transporters_matches(torch):
     a = bri.bri_grad_links(dims, U, c, p)
     b = bri.bri_grad_links(dims, U, c, p, W40=W40)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 2, 4, 2)])
+def test_generic_table_gradient_matches_oracle(torch, ag, dims):
+    """The same AD path for members of the generic class of Sec. 8 (hypercube
+    column, and a random table through bri_grad_links directly)."""
+    import paper_1012_3615_amd as bri
+    from oracle import ultralocal
+    mass = 0.1
+    u, chi, psi = _setup(dims, 5401)
+    tab = ultralocal.HYPERCUBE
+    log(f"generic-class grad vs oracle dims={dims}")
+    S, gU, gP = _ad_S(torch, ag, u, chi, psi, mass, coef=tab)
+    assert abs(S - ograd.action(u, chi[0], psi[0], mass, table=tab)) <= 1e-12 * abs(S)
+    assert rel(gU, ograd.grad_links(u, chi[0], psi[0], mass, table=tab)) < 1e-12
+    assert rel(gP[0], ograd.grad_psi(u, chi[0], mass, table=tab)) < 1e-12
+    rnd = tuple(float(v) for v in np.random.default_rng(5402).uniform(-1, 1, 9))
+    Us = bri.bri_pack_links(dims, torch.from_numpy(u).cuda(), bri.F64)
+    c = bri.bri_pack_spinor(dims, torch.from_numpy(chi).cuda(), bri.F64)
+    p = bri.bri_pack_spinor(dims, torch.from_numpy(psi).cuda(), bri.F64)
+    g = bri.bri_unpack_links(dims, bri.bri_grad_links(dims, Us, c, p, coef=rnd)).cpu().numpy()
+    assert rel(g, ograd.grad_links(u, chi[0], psi[0], mass, table=rnd)) < 1e-12
+    # the Brillouin column through the table is the default gradient bit for bit
+    a = bri.bri_grad_links(dims, Us, c, p)
+    b = bri.bri_grad_links(dims, Us, c, p, coef=bri.TABLE_BRILLOUIN)
+    assert bool((a == b).all())

@@ -246,7 +246,7 @@ def _smeared_near(u, sites, dims):
 
 
 def test_production_fullsize_sampled(bri):
-    """24^3 x 48 (eps = 0.4, the cfg3 lattice): 64 random sites plus corners,
+    """24^3 x 48 (eps = 0.4, the mixed-solve lattice): 64 random sites plus corners,
     FP64 and FP32 two-row transporters with the clover term."""
     import torch
     dims, mass = (24, 24, 24, 48), 0.1

@@ -33,7 +33,7 @@ def solve(bri, dims, u, b, mass, inner, tol=1e-10, inner_tol=1e-4, noff=80, **kw
 
 
 @pytest.mark.parametrize("inner,noff", [(0, 80), (0, 40), (1, 80), (1, 40), (2, 80)])
-def test_cfg1_solve_matches_dense_lu(bri, inner, noff):
+def test_4x4_solve_matches_dense_lu(bri, inner, noff):
     dims = (4, 4, 4, 4)
     u = synth.gauge_links(dims, 0.3, 1001)
     b = synth.gaussian_spinor(dims, 1003, nrhs=1)
@@ -118,7 +118,7 @@ def test_failure_paths_forced_from_host(bri):
 
 @pytest.mark.parametrize("mass", [0.05, 0.5])
 def test_24x48_mixed_sampled_residual(bri, mass):
-    """Full cfg3 lattice (24^3 x 48, eps 0.4): mixed FP16-transporter solve to
+    """Full 24^3 x 48 lattice (eps 0.4): mixed FP16-transporter solve to
     1e-10; the residual is checked at sampled sites with the pointwise oracle
     and in full with the library's own FP64 apply."""
     dims = (24, 24, 24, 48)
