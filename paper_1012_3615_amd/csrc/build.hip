@@ -8,8 +8,8 @@
 //            = U_mu(x+n)^dag     if s_mu = -1,
 // (grouping the k! paths by their last direction gives k groups of (k-1)!
 // paths, each of which is the (k-1)-hop average times the last link).
-// Levels are built in separate launches (1, 2, 3, 4 hops), in FP64, into the
-// 40-offset store (offsets whose last non-zero component is +1); the other
+// Levels are built in separate launches (1, 2, 3, 4 hops), one thread per
+// (site, offset), in FP64, into the 40-offset store (offsets whose last non-zero component is +1); the other
 // orientation of a lower-level transporter is read through
 // W(x, x+m) = W(x+m, x)^dag.
 #include "common.h"
@@ -30,11 +30,35 @@ __device__ __forceinline__ void load_mat(const double2 *p, size_t V, bool dagger
     }
 }
 
+// The canonical offsets (i > 40) of each hop count: 4, 12, 16, 8 of them.
+struct CanonLevels {
+    signed char idx[5][16];
+    int count[5];
+};
+constexpr CanonLevels make_canon() {
+    CanonLevels t{};
+    for (int i = 41; i < 81; ++i) {
+        const int k = off_k(i);
+        t.idx[k][t.count[k]++] = (signed char)i;
+    }
+    return t;
+}
+constexpr CanonLevels kCanon = make_canon();
+__constant__ CanonLevels c_canon = make_canon();
+
+// One thread per (site, canonical offset of the level): the offsets of a
+// block of sites are consecutive blocks on one XCD, so the lower-level
+// transporters and links they share are read through its L2.  The offset
+// is uniform in a block; its code is selected by a uniform branch, so the
+// offset arithmetic stays compile-time.
 template <int K>
 __global__ __launch_bounds__(256) void k_build_level(Geom g, const double2 *__restrict__ U,
                                                      double2 *__restrict__ W40) {
-    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int cnt = kCanon.count[K];
+    const int lin = xcd_block(blockIdx.x, gridDim.x);
+    const int site = (lin / cnt) * blockDim.x + threadIdx.x;
     if (site >= g.V) return;
+    const int target = c_canon.idx[K][lin % cnt];
     const size_t V = (size_t)g.V;
     int c[4];
     coords(g, site, c);
@@ -43,6 +67,7 @@ __global__ __launch_bounds__(256) void k_build_level(Geom g, const double2 *__re
     static_for<41, 81>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (off_k(i) == K) {
+            if (i != target) return;
             constexpr int n[4] = {off_n(i, 0), off_n(i, 1), off_n(i, 2), off_n(i, 3)};
             cx<double> acc[3][3];
 #pragma unroll
@@ -137,11 +162,11 @@ constexpr int kBlock = 256;
 }  // namespace
 
 hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st) {
-    dim3 grid((g.V + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_build_level<1>, grid, dim3(kBlock), 0, st, g, U, W40);
-    hipLaunchKernelGGL(k_build_level<2>, grid, dim3(kBlock), 0, st, g, U, W40);
-    hipLaunchKernelGGL(k_build_level<3>, grid, dim3(kBlock), 0, st, g, U, W40);
-    hipLaunchKernelGGL(k_build_level<4>, grid, dim3(kBlock), 0, st, g, U, W40);
+    const unsigned nb = (g.V + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_build_level<1>, dim3(nb * kCanon.count[1]), dim3(kBlock), 0, st, g, U, W40);
+    hipLaunchKernelGGL(k_build_level<2>, dim3(nb * kCanon.count[2]), dim3(kBlock), 0, st, g, U, W40);
+    hipLaunchKernelGGL(k_build_level<3>, dim3(nb * kCanon.count[3]), dim3(kBlock), 0, st, g, U, W40);
+    hipLaunchKernelGGL(k_build_level<4>, dim3(nb * kCanon.count[4]), dim3(kBlock), 0, st, g, U, W40);
     return hipGetLastError();
 }
 
