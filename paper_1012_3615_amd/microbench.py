@@ -51,6 +51,7 @@ PROD = {
     "prod2c_f16": (bri.F16, bri.F32, bri.W_SU3_2ROW, True, 1),
     "prod2c_f64": (bri.F64, bri.F64, bri.W_SU3_2ROW, True, 1),
     "prod2c12_f32": (bri.F32, bri.F32, bri.W_SU3_2ROW, True, 12),
+    "prod2c12_f16": (bri.F16, bri.F32, bri.W_SU3_2ROW, True, 12),
 }
 
 
