@@ -204,9 +204,7 @@ bri_status bri_build_transporters(bri_dims d, const double *U, void *W, bri_prec
         return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", need);
     if (overlap(work, need, W, bri_transporter_bytes(d, wp, noff)))
         return fail(BRI_E_ARG, "workspace overlaps the transporter store");
-    bri_status s = hip_check(build_w40_f64(g, (const double2 *)U, (double2 *)work, st), "build transporters");
-    if (s != BRI_OK) return s;
-    return hip_check(convert_w40(g, (const double2 *)work, W, (int)wp, noff, st), "convert transporters");
+    return hip_check(build_cast(g, (const double2 *)U, (double2 *)work, W, (int)wp, noff, st), "build transporters");
 }
 
 bri_status bri_apply(bri_dims d, bri_variant v, const void *W, bri_prec wp, int32_t noff,

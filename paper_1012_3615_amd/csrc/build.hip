@@ -51,9 +51,14 @@ __constant__ CanonLevels c_canon = make_canon();
 // transporters and links they share are read through its L2.  The offset
 // is uniform in a block; its code is selected by a uniform branch, so the
 // offset arithmetic stays compile-time.
-template <int K>
+// Wout (optional): the target store (precision WT, 40 or 80 offsets), written
+// as soon as a transporter is final (the cast fused into the build: own plane
+// at x and, for 80 offsets, the adjoint at x+n under -n).  keep_stage = false
+// skips the FP64 stage write (the last level, whose stage nothing reads).
+template <int K, typename WT>
 __global__ __launch_bounds__(256) void k_build_level(Geom g, const double2 *__restrict__ U,
-                                                     double2 *__restrict__ W40) {
+                                                     double2 *__restrict__ W40, WT *__restrict__ Wout, int noff,
+                                                     bool keep_stage) {
     constexpr int cnt = kCanon.count[K];
     const int lin = xcd_block(blockIdx.x, gridDim.x);
     const int site = (lin / cnt) * blockDim.x + threadIdx.x;
@@ -114,11 +119,26 @@ __global__ __launch_bounds__(256) void k_build_level(Geom g, const double2 *__re
                 }
             });
             constexpr double inv = 1.0 / K;
-            double2 *o = W40 + (size_t)plane40(i) * 9 * V + site;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) st(o + (3 * a + b) * V, cscale(inv, acc[a][b]));
+                for (int b = 0; b < 3; ++b) acc[a][b] = cscale(inv, acc[a][b]);
+            if (keep_stage) {
+                double2 *o = W40 + (size_t)plane40(i) * 9 * V + site;
+#pragma unroll
+                for (int e = 0; e < 9; ++e) st(o + e * V, acc[e / 3][e % 3]);
+            }
+            if (Wout) {
+                WT *o = Wout + (size_t)(noff == 80 ? i - 1 : plane40(i)) * 9 * V + site;
+#pragma unroll
+                for (int e = 0; e < 9; ++e) st(o + e * V, acc[e / 3][e % 3]);
+                if (noff == 80) {
+                    const int y = nb.at(n[0], n[1], n[2], n[3]);
+                    WT *ob = Wout + (size_t)(80 - i) * 9 * V + y;  // plane of offset 80 - i (< 40)
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) st(ob + e * V, cconj(acc[e % 3][e / 3]));
+                }
+            }
         }
     });
 }
@@ -161,13 +181,32 @@ __global__ __launch_bounds__(256) void k_convert(Geom g, const double2 *__restri
 constexpr int kBlock = 256;
 }  // namespace
 
-hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st) {
+namespace {
+template <typename WT>
+hipError_t build_levels(const Geom &g, const double2 *U, double2 *W40, WT *Wout, int noff, hipStream_t st) {
     const unsigned nb = (g.V + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_build_level<1>, dim3(nb * kCanon.count[1]), dim3(kBlock), 0, st, g, U, W40);
-    hipLaunchKernelGGL(k_build_level<2>, dim3(nb * kCanon.count[2]), dim3(kBlock), 0, st, g, U, W40);
-    hipLaunchKernelGGL(k_build_level<3>, dim3(nb * kCanon.count[3]), dim3(kBlock), 0, st, g, U, W40);
-    hipLaunchKernelGGL(k_build_level<4>, dim3(nb * kCanon.count[4]), dim3(kBlock), 0, st, g, U, W40);
+    const bool last_stage = Wout == nullptr;  // the 4-hop stage is read only when it is the output
+    hipLaunchKernelGGL((k_build_level<1, WT>), dim3(nb * kCanon.count[1]), dim3(kBlock), 0, st, g, U, W40, Wout,
+                       noff, true);
+    hipLaunchKernelGGL((k_build_level<2, WT>), dim3(nb * kCanon.count[2]), dim3(kBlock), 0, st, g, U, W40, Wout,
+                       noff, true);
+    hipLaunchKernelGGL((k_build_level<3, WT>), dim3(nb * kCanon.count[3]), dim3(kBlock), 0, st, g, U, W40, Wout,
+                       noff, true);
+    hipLaunchKernelGGL((k_build_level<4, WT>), dim3(nb * kCanon.count[4]), dim3(kBlock), 0, st, g, U, W40, Wout,
+                       noff, last_stage);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st) {
+    return build_levels<double2>(g, U, W40, nullptr, 40, st);
+}
+
+hipError_t build_cast(const Geom &g, const double2 *U, double2 *stage, void *W, int wp, int noff, hipStream_t st) {
+    if (wp == 0) return build_levels<double2>(g, U, stage, (double2 *)W, noff, st);
+    if (wp == 1) return build_levels<float2>(g, U, stage, (float2 *)W, noff, st);
+    if (wp == 2) return build_levels<__half2>(g, U, stage, (__half2 *)W, noff, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st) {

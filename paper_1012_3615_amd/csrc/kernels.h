@@ -38,6 +38,9 @@ hipError_t apply_recompute(const Geom &g, int up, int sp, const void *U, const v
 // build.hip: FP64 40-offset store, then conversion
 hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st);
 hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st);
+// the same in one pass: levels 1-3 staged in FP64 (stage: 40-offset FP64
+// store), every transporter cast into W as soon as it is built
+hipError_t build_cast(const Geom &g, const double2 *U, double2 *stage, void *W, int wp, int noff, hipStream_t st);
 
 // production.hip
 hipError_t project_su3_soa(const double2 *A, double2 *Y, int64_t n, hipStream_t st);
