@@ -21,7 +21,7 @@ constexpr int kBlock = 256;
 template <typename LS, typename SS, typename A>
 hipError_t launch_recompute(const Geom &g, const void *U, const void *in, void *out, double diag,
                             int nrhs, bool dag, hipStream_t st) {
-    dim3 grid((g.V + kBlock - 1) / kBlock, nrhs);
+    dim3 grid((g.V + 15) / 16, nrhs);  // 16 sites x 16 orthants per workgroup
     if (dag)
         hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, true>), grid, dim3(kBlock), 0, st, g,
                            (const LS *)U, (const SS *)in, (SS *)out, (A)diag);
