@@ -301,17 +301,17 @@ bri_status bri_build_clover(bri_dims d, const double *U_soa, double csw, void *C
 typedef struct {
     const void *W;       /* transporters (bri_build_transporters or _ex)                     */
     bri_prec w_prec;
-    int32_t n_offsets;   /* 40 or 80; 80 for BRI_W_SU3_2ROW, a clover term or a table        */
+    int32_t n_offsets;   /* 40 or 80; 80 for BRI_W_SU3_2ROW or with a clover term           */
     bri_wform w_form;
     const void *clover;  /* bri_build_clover output in the spinor precision; NULL: c_SW = 0  */
     const double *coef;  /* 9 host doubles of the generic class; NULL: Brillouin            */
 } bri_operator;
 
 /* out = D in (dagger = 0) or D^dag in (dagger = 1) for the stored variant,
- * with the spinor and precision rules of bri_apply.  The two-row form, the
- * clover term and a coefficient table use the default LDS-tile kernel (one or
- * two right-hand sides per thread); otherwise this is bri_apply /
- * bri_apply_dag. */
+ * with the spinor and precision rules of bri_apply.  The two-row form and the
+ * clover term use the default LDS-tile kernel (one or two right-hand sides
+ * per thread); otherwise this is bri_apply / bri_apply_dag (same kernel
+ * selection), with the operator's coefficient table if it has one. */
 bri_status bri_apply_op(bri_dims d, const bri_operator *op, bri_prec s_prec, double mass,
                         const void *in, void *out, int32_t nrhs, int32_t dagger, void *stream);
 

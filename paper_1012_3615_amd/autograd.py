@@ -25,14 +25,11 @@ def _dims_of(U):
 
 class BriApply(torch.autograd.Function):
     """out = D[U] psi (Eq. def_pref, c_SW = 0); with `coef`, any member of the
-    generic class of Sec. 8 (nine numbers, lambda_0..4 then rho_1..4; the
-    80-offset store)."""
+    generic class of Sec. 8 (nine numbers, lambda_0..4 then rho_1..4)."""
 
     @staticmethod
     def forward(ctx, U, psi, mass, n_offsets=80, coef=None):
         dims = _dims_of(U)
-        if coef is not None and n_offsets != 80:
-            raise ValueError("a coefficient table needs the 80-offset store")
         Us = api.bri_pack_links(dims, U.contiguous(), api.F64)
         W = api.bri_build_transporters(dims, Us, api.F64, n_offsets)
         x = api.bri_pack_spinor(dims, psi.contiguous(), api.F64)
@@ -49,24 +46,16 @@ class BriApply(torch.autograd.Function):
         Us = api.bri_pack_links(dims, U.contiguous(), api.F64)
         chi = api.bri_pack_spinor(dims, gout.contiguous(), api.F64)
         gU = gpsi = None
-        if ctx.coef is None:
-            W40 = api.bri_build_transporters(dims, Us, api.F64, 40)
-            if ctx.needs_input_grad[1]:
-                gpsi = api.bri_unpack_spinor(dims, api.bri_apply_dag(dims, W40, chi, ctx.mass)).reshape(psi.shape)
-            if ctx.needs_input_grad[0]:
-                x = api.bri_pack_spinor(dims, psi.contiguous(), api.F64)
-                gU = api.bri_unpack_links(dims, api.bri_grad_links(dims, Us, chi, x, W40=W40))
-        else:
-            # a table needs the 80-offset store for D^dag; the link gradient
-            # rebuilds the 40-offset store it gathers from
-            if ctx.needs_input_grad[1]:
-                op = api.Operator(api.bri_build_transporters(dims, Us, api.F64, 80), coef=ctx.coef)
-                gpsi = api.bri_unpack_spinor(dims, api.bri_apply_op(dims, op, chi, ctx.mass, dagger=True))
-                gpsi = gpsi.reshape(psi.shape)
-                del op
-            if ctx.needs_input_grad[0]:
-                x = api.bri_pack_spinor(dims, psi.contiguous(), api.F64)
-                gU = api.bri_unpack_links(dims, api.bri_grad_links(dims, Us, chi, x, coef=ctx.coef))
+        W40 = api.bri_build_transporters(dims, Us, api.F64, 40)
+        if ctx.needs_input_grad[1]:
+            if ctx.coef is None:
+                y = api.bri_apply_dag(dims, W40, chi, ctx.mass)
+            else:
+                y = api.bri_apply_op(dims, api.Operator(W40, coef=ctx.coef), chi, ctx.mass, dagger=True)
+            gpsi = api.bri_unpack_spinor(dims, y).reshape(psi.shape)
+        if ctx.needs_input_grad[0]:
+            x = api.bri_pack_spinor(dims, psi.contiguous(), api.F64)
+            gU = api.bri_unpack_links(dims, api.bri_grad_links(dims, Us, chi, x, W40=W40, coef=ctx.coef))
         return gU, gpsi, None, None, None
 
 

@@ -69,7 +69,7 @@ int snap_rblk(int want, int nrhs) {
 
 bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int32_t noff,
                       bri_prec sp, double mass, const void *in, void *out, int32_t nrhs,
-                      void *stream, bool dag) {
+                      void *stream, bool dag, const double *table) {
     Geom g;
     if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
@@ -78,8 +78,9 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
         return fail(BRI_E_ARG, "null or misaligned (16 B) pointer");
     const size_t sb = (size_t)g.V * 12 * nrhs * cbytes(sp);
     if (overlap(in, sb, out, sb)) return fail(BRI_E_ARG, "in and out overlap");
-    const double diag = lam_k(0) + mass;
+    const double diag = (table ? table[0] : lam_k(0)) + mass;
     hipStream_t st = (hipStream_t)stream;
+    if (table && v != BRI_STORED) return fail(BRI_E_UNSUPPORTED, "a coefficient table needs stored transporters");
     if (v == BRI_STORED) {
         if (noff != 40 && noff != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
         const bool combo = (wp == BRI_F64 && sp == BRI_F64) || (wp == BRI_F32 && sp == BRI_F32) ||
@@ -98,7 +99,7 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
                 rblk = 2;  // LDS of a 32x8 tile
         }
         return hip_check(apply_stored(g, noff, (int)wp, (int)sp, kernel, rblk, W, in, out, diag, nrhs,
-                                      dag, st),
+                                      dag, st, table),
                          "apply (stored)");
     }
     if (v == BRI_RECOMPUTE) {

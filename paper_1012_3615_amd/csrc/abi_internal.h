@@ -18,9 +18,11 @@ size_t cbytes(bri_prec p);
 bool prec_ok(bri_prec p);
 bool aligned(const void *p);
 bool overlap(const void *a, size_t na, const void *b, size_t nb);
+// table: lambda_0..4, rho_1..4 of the generic class (host), nullptr for the
+// Brillouin operator; the stored variant only
 bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int32_t noff,
                       bri_prec sp, double mass, const void *in, void *out, int32_t nrhs,
-                      void *stream, bool dag);
+                      void *stream, bool dag, const double *table = nullptr);
 
 // A stored-transporter operator: W, its precision and offset count, the number
 // of stored rows per transporter (3, or 2 for the two-row SU(3) store), the

@@ -22,8 +22,8 @@ bri_status op_from_public(const bri_operator *op, OpDesc *out) {
 
 bri_status apply_op(bri_dims d, const OpDesc &op, bri_prec sp, double mass, const void *in, void *out,
                     int32_t nrhs, void *stream, bool dag) {
-    if (op.rows == 3 && !op.clover && !op.coef)
-        return apply_impl(d, BRI_STORED, op.W, op.wp, op.noff, sp, mass, in, out, nrhs, stream, dag);
+    if (op.rows == 3 && !op.clover)
+        return apply_impl(d, BRI_STORED, op.W, op.wp, op.noff, sp, mass, in, out, nrhs, stream, dag, op.coef);
     Geom g;
     if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
     if (!prec_ok(op.wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
@@ -33,7 +33,7 @@ bri_status apply_op(bri_dims d, const OpDesc &op, bri_prec sp, double mass, cons
     const size_t sb = (size_t)g.V * 12 * nrhs * cbytes(sp);
     if (overlap(in, sb, out, sb)) return fail(BRI_E_ARG, "in and out overlap");
     if (op.noff != 80)
-        return fail(BRI_E_UNSUPPORTED, "the two-row store, the clover term and a coefficient table need n_offsets = 80");
+        return fail(BRI_E_UNSUPPORTED, "the two-row store and the clover term need n_offsets = 80");
     const double diag = (op.coef ? op.coef[0] : lam_k(0)) + mass;
     const int rblk = nrhs >= 2 ? 2 : 1;
     hipStream_t st = (hipStream_t)stream;

@@ -33,11 +33,13 @@ hipError_t launch_recompute(const Geom &g, const void *U, const void *in, void *
 }  // namespace
 
 hipError_t apply_stored(const Geom &g, int noff, int wp, int sp, int kernel, int rblk, const void *W,
-                        const void *in, void *out, double diag, int nrhs, bool dag, hipStream_t st) {
-    if (wp == 0 && sp == 0) return apply_stored_f64(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st);
-    if (wp == 1 && sp == 1) return apply_stored_f32(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st);
-    if (wp == 2 && sp == 1) return apply_stored_f16(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st);
-    if (wp == 2 && sp == 2) return apply_stored_f16h(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st);
+                        const void *in, void *out, double diag, int nrhs, bool dag, hipStream_t st,
+                        const double *table) {
+    if (wp == 0 && sp == 0) return apply_stored_f64(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st, table);
+    if (wp == 1 && sp == 1) return apply_stored_f32(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st, table);
+    if (wp == 2 && sp == 1) return apply_stored_f16(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st, table);
+    if (wp == 2 && sp == 2)
+        return apply_stored_f16h(g, noff, kernel, rblk, W, in, out, diag, nrhs, dag, st, table);
     return hipErrorInvalidValue;
 }
 

@@ -10,7 +10,7 @@ namespace bri {
 template <int NOFF, typename WS, typename SS, typename A, bool DAG, int R>
 __global__ __launch_bounds__(256) void k_apply_stored(Geom g, const WS *__restrict__ W,
                                                       const SS *__restrict__ in,
-                                                      SS *__restrict__ out, A diag, int nrhs) {
+                                                      SS *__restrict__ out, A diag, int nrhs, Coef<A> cf) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int site = blk * blockDim.x + threadIdx.x;
     if (site >= g.V) return;
@@ -47,8 +47,8 @@ __global__ __launch_bounds__(256) void k_apply_stored(Geom g, const WS *__restri
         }
         const int j = i < 40 ? i : i - 1;
         const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
-        const A lam = lam_rt<A>(k);
-        const A rho = DAG ? -rho_rt<A>(k) : rho_rt<A>(k);
+        const A lam = coef_pick(cf.lam, k);
+        const A rho = DAG ? -coef_pick(cf.rho, k) : coef_pick(cf.rho, k);
         const int y = nbr_rt(nb, nx, ny, nz, nt);
         cx<A> w[3][3];
         if (NOFF == 80 || i > 40) {

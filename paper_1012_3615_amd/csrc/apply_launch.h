@@ -37,14 +37,15 @@ hipError_t tiled(const Geom &g, const void *W, const void *in, void *out, double
 
 template <int NOFF, typename WS, typename SS, typename A, int R>
 hipError_t gather(const Geom &g, const void *W, const void *in, void *out, double diag, int nrhs,
-                  bool dag, hipStream_t st) {
+                  bool dag, hipStream_t st, const double *table) {
     dim3 grid((g.V + kGatherBlock - 1) / kGatherBlock, (nrhs + R - 1) / R);
+    const Coef<A> cf = make_coef<A>(table);
     if (dag)
         hipLaunchKernelGGL((k_apply_stored<NOFF, WS, SS, A, true, R>), grid, dim3(kGatherBlock), 0, st,
-                           g, (const WS *)W, (const SS *)in, (SS *)out, (A)diag, nrhs);
+                           g, (const WS *)W, (const SS *)in, (SS *)out, (A)diag, nrhs, cf);
     else
         hipLaunchKernelGGL((k_apply_stored<NOFF, WS, SS, A, false, R>), grid, dim3(kGatherBlock), 0,
-                           st, g, (const WS *)W, (const SS *)in, (SS *)out, (A)diag, nrhs);
+                           st, g, (const WS *)W, (const SS *)in, (SS *)out, (A)diag, nrhs, cf);
     return hipGetLastError();
 }
 
@@ -57,15 +58,15 @@ hipError_t gather(const Geom &g, const void *W, const void *in, void *out, doubl
 // 32x8, 24x8 and 48x4 with prefetch: 1, 2).
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void *in, void *out,
-                  double diag, int nrhs, bool dag, hipStream_t st) {
+                  double diag, int nrhs, bool dag, hipStream_t st, const double *table) {
     if (kernel == 0) {
         switch (rblk) {
-            case 1: return gather<NOFF, WS, SS, A, 1>(g, W, in, out, diag, nrhs, dag, st);
-            case 2: return gather<NOFF, WS, SS, A, 2>(g, W, in, out, diag, nrhs, dag, st);
-            case 3: return gather<NOFF, WS, SS, A, 3>(g, W, in, out, diag, nrhs, dag, st);
-            case 4: return gather<NOFF, WS, SS, A, 4>(g, W, in, out, diag, nrhs, dag, st);
-            case 6: return gather<NOFF, WS, SS, A, 6>(g, W, in, out, diag, nrhs, dag, st);
-            case 12: return gather<NOFF, WS, SS, A, 12>(g, W, in, out, diag, nrhs, dag, st);
+            case 1: return gather<NOFF, WS, SS, A, 1>(g, W, in, out, diag, nrhs, dag, st, table);
+            case 2: return gather<NOFF, WS, SS, A, 2>(g, W, in, out, diag, nrhs, dag, st, table);
+            case 3: return gather<NOFF, WS, SS, A, 3>(g, W, in, out, diag, nrhs, dag, st, table);
+            case 4: return gather<NOFF, WS, SS, A, 4>(g, W, in, out, diag, nrhs, dag, st, table);
+            case 6: return gather<NOFF, WS, SS, A, 6>(g, W, in, out, diag, nrhs, dag, st, table);
+            case 12: return gather<NOFF, WS, SS, A, 12>(g, W, in, out, diag, nrhs, dag, st, table);
             default: return hipErrorInvalidValue;
         }
     }
@@ -84,31 +85,31 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
             kernel = rblk <= 2 ? 8 : rblk == 3 ? 9 : 2;
     }
     switch (kernel * 16 + rblk) {
-        case 2 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1>(g, W, in, out, diag, nrhs, dag, st);
-        case 2 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2>(g, W, in, out, diag, nrhs, dag, st);
-        case 2 * 16 + 3: return tiled<NOFF, WS, SS, A, 32, 8, 3>(g, W, in, out, diag, nrhs, dag, st);
-        case 2 * 16 + 4: return tiled<NOFF, WS, SS, A, 32, 8, 4>(g, W, in, out, diag, nrhs, dag, st);
-        case 3 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 16, 1>(g, W, in, out, diag, nrhs, dag, st);
-        case 4 * 16 + 1: return tiled<NOFF, WS, SS, A, 64, 4, 1>(g, W, in, out, diag, nrhs, dag, st);
-        case 5 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 8, 1>(g, W, in, out, diag, nrhs, dag, st);
-        case 5 * 16 + 2: return tiled<NOFF, WS, SS, A, 16, 8, 2>(g, W, in, out, diag, nrhs, dag, st);
-        case 5 * 16 + 3: return tiled<NOFF, WS, SS, A, 16, 8, 3>(g, W, in, out, diag, nrhs, dag, st);
-        case 5 * 16 + 4: return tiled<NOFF, WS, SS, A, 16, 8, 4>(g, W, in, out, diag, nrhs, dag, st);
-        case 6 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 6 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 7 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 16, 1, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 8 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, true, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 8 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, true, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 9 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, false, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 9 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, false, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 9 * 16 + 3: return tiled<NOFF, WS, SS, A, 32, 8, 3, false, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 10 * 16 + 2: return tiled<NOFF, WS, SS, A, 16, 8, 2, false, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 10 * 16 + 3: return tiled<NOFF, WS, SS, A, 16, 8, 3, false, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 10 * 16 + 4: return tiled<NOFF, WS, SS, A, 16, 8, 4, false, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 11 * 16 + 1: return tiled<NOFF, WS, SS, A, 24, 8, 1, true, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 11 * 16 + 2: return tiled<NOFF, WS, SS, A, 24, 8, 2, true, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 12 * 16 + 1: return tiled<NOFF, WS, SS, A, 48, 4, 1, true, true>(g, W, in, out, diag, nrhs, dag, st);
-        case 12 * 16 + 2: return tiled<NOFF, WS, SS, A, 48, 4, 2, true, true>(g, W, in, out, diag, nrhs, dag, st);
+        case 2 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 2 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 2 * 16 + 3: return tiled<NOFF, WS, SS, A, 32, 8, 3>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 2 * 16 + 4: return tiled<NOFF, WS, SS, A, 32, 8, 4>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 3 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 16, 1>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 4 * 16 + 1: return tiled<NOFF, WS, SS, A, 64, 4, 1>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 5 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 8, 1>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 5 * 16 + 2: return tiled<NOFF, WS, SS, A, 16, 8, 2>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 5 * 16 + 3: return tiled<NOFF, WS, SS, A, 16, 8, 3>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 5 * 16 + 4: return tiled<NOFF, WS, SS, A, 16, 8, 4>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 6 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 6 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 7 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 16, 1, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 8 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 8 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 9 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1, false, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 9 * 16 + 2: return tiled<NOFF, WS, SS, A, 32, 8, 2, false, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 9 * 16 + 3: return tiled<NOFF, WS, SS, A, 32, 8, 3, false, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 10 * 16 + 2: return tiled<NOFF, WS, SS, A, 16, 8, 2, false, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 10 * 16 + 3: return tiled<NOFF, WS, SS, A, 16, 8, 3, false, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 10 * 16 + 4: return tiled<NOFF, WS, SS, A, 16, 8, 4, false, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 11 * 16 + 1: return tiled<NOFF, WS, SS, A, 24, 8, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 11 * 16 + 2: return tiled<NOFF, WS, SS, A, 24, 8, 2, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 12 * 16 + 1: return tiled<NOFF, WS, SS, A, 48, 4, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 12 * 16 + 2: return tiled<NOFF, WS, SS, A, 48, 4, 2, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
         default: return hipErrorInvalidValue;
     }
 }
@@ -145,9 +146,7 @@ hipError_t stored_prod(const Geom &g, int rows, int rblk, const void *W, const v
         return stored_ext<WS, SS, A, 2, true>(g, rblk, W, in, out, diag, nrhs, dag, st, clover, table);
     if (rows == 2)
         return stored_ext<WS, SS, A, 2, false>(g, rblk, W, in, out, diag, nrhs, dag, st, nullptr, table);
-    if (rows == 3)
-        return stored_ext<WS, SS, A, 3, false>(g, rblk, W, in, out, diag, nrhs, dag, st, nullptr, table);
-    return hipErrorInvalidValue;
+    return hipErrorInvalidValue;  // rows 3 without a clover term: stored()
 }
 
 }  // namespace launch

@@ -10,11 +10,12 @@ namespace bri {
 
 // apply.hip
 hipError_t apply_stored(const Geom &g, int noff, int wp, int sp, int kernel, int rblk, const void *W,
-                        const void *in, void *out, double diag, int nrhs, bool dag, hipStream_t st);
+                        const void *in, void *out, double diag, int nrhs, bool dag, hipStream_t st,
+                        const double *table = nullptr);
 #define BRI_DECL_APPLY(tag)                                                                        \
     hipError_t apply_stored_##tag(const Geom &g, int noff, int kernel, int rblk, const void *W,    \
                                   const void *in, void *out, double diag, int nrhs, bool dag,     \
-                                  hipStream_t st);
+                                  hipStream_t st, const double *table);
 BRI_DECL_APPLY(f64)
 BRI_DECL_APPLY(f32)
 BRI_DECL_APPLY(f16)

@@ -50,16 +50,41 @@ def test_table_apply_matches_oracle(bri, dims):
     for name, t in TABLES.items():
         want = np.stack([ultralocal.apply(u, psi[r], mass, t) for r in range(3)])
         want_dag = np.stack([ultralocal.apply_dag(u, psi[r], mass, t) for r in range(3)])
-        for p in (0, 1):
-            log(f"generic class {name} {dims} prec={p}")
-            op = bri.Operator(bri.bri_build_transporters(dims, U, p, 80), coef=t)
+        for p, noff in ((0, 80), (1, 80), (0, 40), (1, 40)):
+            log(f"generic class {name} {dims} prec={p} noff={noff}")
+            op = bri.Operator(bri.bri_build_transporters(dims, U, p, noff), coef=t)
             for nr in (1, 3):
                 x = bri.bri_pack_spinor(dims, dev(psi[:nr]), p)
                 got = soa_to_canon(dims, bri.bri_apply_op(dims, op, x, mass))
                 gdg = soa_to_canon(dims, bri.bri_apply_op(dims, op, x, mass, dagger=True))
                 for r in range(nr):
-                    assert rel(got[r], want[r]) <= TOL[p], (name, p, nr, r)
-                    assert rel(gdg[r], want_dag[r]) <= TOL[p], (name, p, nr, r, "dag")
+                    assert rel(got[r], want[r]) <= TOL[p], (name, p, noff, nr, r)
+                    assert rel(gdg[r], want_dag[r]) <= TOL[p], (name, p, noff, nr, r, "dag")
+
+
+def test_table_every_kernel_configuration(bri):
+    """The table reaches every stored-apply kernel: the gather form (kernel 0,
+    several right-hand sides per thread) and each tile shape, against the
+    oracle, FP64, 40 and 80 offsets."""
+    dims, mass, t = (6, 5, 3, 4), 0.1, TABLES["random"]
+    u = synth.gauge_links(dims, 0.4, 8415)
+    psi = synth.gaussian_spinor(dims, 8416, nrhs=3)
+    want = np.stack([ultralocal.apply(u, psi[r], mass, t) for r in range(3)])
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    x = bri.bri_pack_spinor(dims, dev(psi), bri.F64)
+    try:
+        for noff in (80, 40):
+            op = bri.Operator(bri.bri_build_transporters(dims, U, bri.F64, noff), coef=t)
+            for kernel, rblk in ((0, 3), (0, 1), (2, 2), (3, 1), (5, 3), (8, 2), (9, 3), (10, 2), (11, 1), (12, 2)):
+                log(f"generic class kernel {kernel} rblk {rblk} noff {noff}")
+                bri.bri_set_apply_kernel(bri.F64, bri.F64, kernel)
+                bri.bri_set_rhs_block(bri.F64, bri.F64, rblk)
+                got = soa_to_canon(dims, bri.bri_apply_op(dims, op, x, mass))
+                for r in range(3):
+                    assert rel(got[r], want[r]) <= TOL[0], (kernel, rblk, noff, r)
+    finally:
+        bri.bri_set_apply_kernel(bri.F64, bri.F64, 1)
+        bri.bri_set_rhs_block(bri.F64, bri.F64, 0)
 
 
 @pytest.mark.parametrize("dims", [(8, 4, 4, 4), (32, 4, 2, 2)])
@@ -125,9 +150,6 @@ def test_table_rejections(bri):
     dims = (4, 4, 4, 4)
     U = bri.bri_pack_links(dims, dev(synth.gauge_links(dims, 0.3, 8410)), bri.F64)
     x = bri.bri_pack_spinor(dims, dev(synth.gaussian_spinor(dims, 8411, nrhs=1)), bri.F64)
-    W40 = bri.bri_build_transporters(dims, U, bri.F64, 40)
-    with pytest.raises(bri.BriError, match="n_offsets = 80"):
-        bri.bri_apply_op(dims, bri.Operator(W40, coef=bri.TABLE_WILSON), x, 0.1)
     W80 = bri.bri_build_transporters(dims, U, bri.F64, 80)
     bad = list(bri.TABLE_WILSON)
     bad[6] = float("nan")
