@@ -2,6 +2,7 @@
 // (storage of W, storage of the spinors, accumulation); each apply_*.hip
 // translation unit instantiates one triple.
 #pragma once
+#include <type_traits>
 #include "apply_gather.h"
 #include "apply_tiled.h"
 
@@ -54,7 +55,7 @@ hipError_t gather(const Geom &g, const void *W, const void *in, void *out, doubl
 // next transporter prefetched; 8 tile 32x8 with prefetch and the offsets of a
 // layer unrolled at compile time (rblk 1, 2); 9, 10 tiles 32x8 (rblk 1-3) and
 // 16x8 (rblk 2-4) with the offsets unrolled, no prefetch; 11, 12 tiles 24x8 and 48x4 with prefetch and
-// unrolled offsets (rblk 1, 2).  Tiles hold rblk in 1..4 right-hand sides per thread (16x16 and 64x4: 1;
+// unrolled offsets (rblk 1, 2); 13 tile 32x16 with prefetch and unrolled offsets (rblk 1).  Tiles hold rblk in 1..4 right-hand sides per thread (16x16 and 64x4: 1;
 // 32x8, 24x8 and 48x4 with prefetch: 1, 2).
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void *in, void *out,
@@ -81,6 +82,9 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
             kernel = 12;
         else if (rblk <= 2 && lx % 32 != 0 && lx % 24 == 0)
             kernel = 11;
+        else if (NOFF == 80 && std::is_same<WS, float2>::value && std::is_same<SS, float2>::value && rblk == 1 &&
+                 lx % 32 == 0 && g.L[1] % 16 == 0)
+            kernel = 13;  // 32x16 (halo 1.2x a tile's sites instead of 1.33x): faster for FP32 W80 only
         else
             kernel = rblk <= 2 ? 8 : rblk == 3 ? 9 : 2;
     }
@@ -110,6 +114,7 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         case 11 * 16 + 2: return tiled<NOFF, WS, SS, A, 24, 8, 2, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
         case 12 * 16 + 1: return tiled<NOFF, WS, SS, A, 48, 4, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
         case 12 * 16 + 2: return tiled<NOFF, WS, SS, A, 48, 4, 2, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 13 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 16, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
         default: return hipErrorInvalidValue;
     }
 }
@@ -120,7 +125,8 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
 // the generic class of Sec. 8; nullptr: the Brillouin column).  The tile is
 // the default one for the extent Lx (32x8 with prefetch and unrolled offsets,
 // 24x8 or 48x4 when Lx is a multiple of 24 or 48 but not of 32, or 16x16 /
-// 16x8 for Lx <= 16); rblk 1 or 2 right-hand sides per thread.
+// 16x8 for Lx <= 16; the 32x16 tile of the plain FP32 apply was slower
+// here); rblk 1 or 2 right-hand sides per thread.
 template <typename WS, typename SS, typename A, int ROWS, bool CLV>
 hipError_t stored_ext(const Geom &g, int rblk, const void *W, const void *in, void *out, double diag,
                       int nrhs, bool dag, hipStream_t st, const void *clover, const double *table) {

@@ -11,7 +11,7 @@ from tests.helpers import dev, log
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims", [(8, 4, 4, 6), (5, 3, 2, 6), (24, 4, 2, 4)])
+@pytest.mark.parametrize("dims", [(8, 4, 4, 6), (5, 3, 2, 6), (24, 4, 2, 4), (32, 16, 2, 2)])
 @pytest.mark.parametrize("wp,sp,noff", [(0, 0, 80), (1, 1, 80), (1, 1, 40), (2, 1, 80), (2, 2, 80)])
 def test_all_configurations_bitwise_equal(dims, wp, sp, noff):
     import torch

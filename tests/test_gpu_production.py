@@ -245,12 +245,14 @@ def _smeared_near(u, sites, dims):
     return vs
 
 
-def test_production_fullsize_sampled(bri):
-    """24^3 x 48 (eps = 0.4, the mixed-solve lattice): 64 random sites plus corners,
-    FP64 and FP32 two-row transporters with the clover term."""
+@pytest.mark.parametrize("dims", [(24, 24, 24, 48), (32, 16, 4, 4)])
+def test_production_fullsize_sampled(bri, dims):
+    """24^3 x 48 (eps = 0.4, the mixed-solve lattice; 24x8 tiles) and
+    32x16x4x4 (32x8 tiles with Ly a multiple of 16): 64 random sites plus
+    corners, FP64 and FP32 two-row transporters with the clover term."""
     import torch
-    dims, mass = (24, 24, 24, 48), 0.1
-    log("production fullsize: host inputs")
+    mass = 0.1
+    log(f"production sampled {dims}: host inputs")
     u = synth.gauge_links(dims, 0.4, 3001)
     psi = synth.gaussian_spinor(dims, 3002, nrhs=1)
     rng = np.random.default_rng(7701)
@@ -261,7 +263,7 @@ def test_production_fullsize_sampled(bri):
     assert np.isfinite(want).all()
     U = bri.bri_ape_smear(dims, bri.bri_pack_links(dims, dev(u), bri.F64), 0.72)
     for wp, sp in [(0, 0), (1, 1)]:
-        log(f"production fullsize w={wp} s={sp}")
+        log(f"production sampled {dims} w={wp} s={sp}")
         op = bri.Operator(bri.bri_build_transporters_ex(dims, U, wp, 80, bri.W_SU3_2ROW), bri.W_SU3_2ROW,
                           bri.bri_build_clover(dims, U, 1.0, sp))
         x = bri.bri_pack_spinor(dims, dev(psi), sp)
