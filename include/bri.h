@@ -148,9 +148,9 @@ int32_t bri_get_rhs_block(bri_prec w_prec, bri_prec s_prec);
  *   1  LDS tiles, shape chosen from Lx (default): each workgroup stages the
  *      spinor of its x-y tile plus a one-site halo layer by layer in LDS;
  *      for Lx > 16 a 32x8 tile (24x8 or 48x4 when Lx is a multiple of 24 or
- *      48 but not of 32; 32x16 for FP32 transporters (80 offsets) and
- *      spinors, one right-hand side per thread, when Lx is a multiple of 32
- *      and Ly of 16) with the
+ *      48 but not of 32; 32x16 for FP32 or FP64 transporters (80 offsets)
+ *      with spinors of the same precision, one right-hand side per thread,
+ *      when Lx is a multiple of 32 and Ly of 16) with the
  *      next transporter prefetched and each layer's offsets unrolled; for
  *      Lx <= 16 a 16x16 tile (one right-hand side per thread) or 16x8
  *      (several);

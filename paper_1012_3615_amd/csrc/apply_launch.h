@@ -82,9 +82,9 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
             kernel = 12;
         else if (rblk <= 2 && lx % 32 != 0 && lx % 24 == 0)
             kernel = 11;
-        else if (NOFF == 80 && std::is_same<WS, float2>::value && std::is_same<SS, float2>::value && rblk == 1 &&
+        else if (NOFF == 80 && std::is_same<WS, SS>::value && !std::is_same<WS, __half2>::value && rblk == 1 &&
                  lx % 32 == 0 && g.L[1] % 16 == 0)
-            kernel = 13;  // 32x16 (halo 1.2x a tile's sites instead of 1.33x): faster for FP32 W80 only
+            kernel = 13;  // 32x16 (halo 1.2x a tile's sites instead of 1.33x): faster for FP32 and FP64 W80
         else
             kernel = rblk <= 2 ? 8 : rblk == 3 ? 9 : 2;
     }
