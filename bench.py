@@ -70,6 +70,22 @@ def timed_launches(torch, fn, steps, warmup):
     return total, [s.elapsed_time(e) for s, e in ev]
 
 
+def batch_ms(torch, fn, steps, warmup):
+    """Mean ms per launch of `steps` back-to-back launches bracketed by one
+    event pair: for sub-millisecond kernels an event pair per launch adds its
+    own gap between launches."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
 def cpu_baseline(u, psi, got, target_s=15.0):
     """The CPU oracle as it stands (plain numpy, FP64), on sampled sites of the
     same 32^3 x 64 workload, scaled to applications/s of the whole lattice;
@@ -209,8 +225,9 @@ def solve_24x48(torch, bri, dev, tol=1e-10):
 
 def variants_16_32(torch, bri, dev, steps=100):
     """The 16^3 x 32 lattice (links eps 0.3, seed 2001; Gaussian spinor, seed
-    2002): 100 timed applications each of the stored (W80 and W40) and the
-    recompute variants in FP64 and FP32, one right-hand side."""
+    2002): 100 back-to-back applications each of the stored (W80 and W40) and
+    the recompute variants in FP64 and FP32, one right-hand side, timed as a
+    batch."""
     import numpy as np
     import synth
     dims = (16, 16, 16, 32)
@@ -224,8 +241,7 @@ def variants_16_32(torch, bri, dev, steps=100):
         name = "f64" if prec == bri.F64 else "f32"
         for noff in (80, 40):
             W = bri.bri_build_transporters(dims, U64, prec, noff)
-            _, p = timed_launches(torch, lambda: bri.bri_apply(dims, W, x, MASS), steps, 10)
-            ms = float(np.mean(p))
+            ms = batch_ms(torch, lambda: bri.bri_apply(dims, W, x, MASS), steps, 10)
             byts = bytes_per_site(noff, cb, cb) * V
             out[f"stored_w{noff}_{name}"] = {"ms": ms, "applies_s": 1e3 / ms,
                                              "gflops": FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9,
@@ -233,8 +249,7 @@ def variants_16_32(torch, bri, dev, steps=100):
                                              "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del W
         Ux = U64 if prec == bri.F64 else bri.bri_pack_links(dims, u, bri.F32)
-        _, p = timed_launches(torch, lambda: bri.bri_apply(dims, Ux, x, MASS, variant=bri.RECOMPUTE), steps, 10)
-        ms = float(np.mean(p))
+        ms = batch_ms(torch, lambda: bri.bri_apply(dims, Ux, x, MASS, variant=bri.RECOMPUTE), steps, 10)
         out[f"recompute_{name}"] = {"ms": ms, "applies_s": 1e3 / ms,
                                     "gflops": FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9}
     return out

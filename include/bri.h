@@ -152,16 +152,16 @@ int32_t bri_get_rhs_block(bri_prec w_prec, bri_prec s_prec);
  *      with spinors of the same precision, one right-hand side per thread,
  *      when Lx is a multiple of 32 and Ly of 16) with the
  *      next transporter prefetched and each layer's offsets unrolled; for
- *      Lx <= 16 a 16x16 tile (one right-hand side per thread) or 16x8
- *      (several);
+ *      Lx <= 16 a 16x16 tile (one right-hand side per thread; 16x4 with
+ *      unrolled offsets for FP32 when Lx = 16) or 16x8 (several);
  *   2..5   LDS tiles of 32x8, 16x16, 64x4 or 16x8 sites;
  *   6, 7   tiles 32x8, 16x16 with transporter prefetch;
  *   8      tile 32x8 with prefetch and each layer's offsets unrolled;
  *   9, 10  tiles 32x8, 16x8 with the offsets unrolled, no prefetch;
  *   11, 12 tiles 24x8, 48x4 with prefetch and unrolled offsets (chosen by
  *          code 1 when Lx is a multiple of 24 or 48 but not of 32);
- *   13     tile 32x16 with prefetch and unrolled offsets, one right-hand
- *          side per thread;
+ *   13, 14 tiles 32x16, 16x4 with prefetch and unrolled offsets, one
+ *          right-hand side per thread;
  *   0      direct neighbour gathers through the caches.
  * A tile kernel holds 1-4 right-hand sides per thread (bri_set_rhs_block,
  * clamped to what the shape supports).  All add the 81 terms of a site in

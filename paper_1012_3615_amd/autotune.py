@@ -22,11 +22,11 @@ CACHE = os.environ.get("BRI_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "bri_autotune.json"))
 TILES = {2: "tile32x8", 3: "tile16x16", 4: "tile64x4", 5: "tile16x8", 6: "tile32x8pf", 7: "tile16x16pf",
          8: "tile32x8pfu", 9: "tile32x8u", 10: "tile16x8u", 11: "tile24x8pfu", 12: "tile48x4pfu",
-         13: "tile32x16pfu"}
-TILE_X = {2: 32, 3: 16, 4: 64, 5: 16, 6: 32, 7: 16, 8: 32, 9: 32, 10: 16, 11: 24, 12: 48, 13: 32}
+         13: "tile32x16pfu", 14: "tile16x4pfu"}
+TILE_X = {2: 32, 3: 16, 4: 64, 5: 16, 6: 32, 7: 16, 8: 32, 9: 32, 10: 16, 11: 24, 12: 48, 13: 32, 14: 16}
 # right-hand sides per thread instantiated for each tile code
 TILE_RBLK = {2: (1, 2, 3, 4), 3: (1,), 4: (1,), 5: (1, 2, 3, 4), 6: (1, 2), 7: (1,), 8: (1, 2),
-             9: (1, 2, 3), 10: (2, 3, 4), 11: (1, 2), 12: (1, 2), 13: (1,)}
+             9: (1, 2, 3), 10: (2, 3, 4), 11: (1, 2), 12: (1, 2), 13: (1,), 14: (1,)}
 RBLKS = (1, 2, 3, 4, 6, 12)
 
 

@@ -90,7 +90,7 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
         int rblk = nrhs == 1 ? 1 : snap_rblk(g_rhs_block[wp][sp], nrhs);
         if (kernel >= 1) {
             // LDS tiles hold 1..4 right-hand sides per thread (shapes 16x16, 64x4: 1)
-            if (kernel == 3 || kernel == 4 || kernel == 7 || kernel == 13) rblk = 1;
+            if (kernel == 3 || kernel == 4 || kernel == 7 || kernel == 13 || kernel == 14) rblk = 1;
             if ((kernel == 6 || kernel == 8 || kernel == 11 || kernel == 12) && rblk > 2) rblk = 2;
             if (kernel == 9 && rblk > 3) rblk = 3;
             if (kernel == 10 && rblk < 2) rblk = 2;
@@ -235,7 +235,7 @@ bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
 bri_status bri_set_apply_kernel(bri_prec wp, bri_prec sp, int32_t kernel) {
     g_last_error.clear();
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    if (kernel < 0 || kernel > 13) return fail(BRI_E_ARG, "kernel must be in 0..13");
+    if (kernel < 0 || kernel > 14) return fail(BRI_E_ARG, "kernel must be in 0..14");
     g_apply_kernel[wp][sp] = kernel;
     return BRI_OK;
 }

@@ -55,7 +55,7 @@ hipError_t gather(const Geom &g, const void *W, const void *in, void *out, doubl
 // next transporter prefetched; 8 tile 32x8 with prefetch and the offsets of a
 // layer unrolled at compile time (rblk 1, 2); 9, 10 tiles 32x8 (rblk 1-3) and
 // 16x8 (rblk 2-4) with the offsets unrolled, no prefetch; 11, 12 tiles 24x8 and 48x4 with prefetch and
-// unrolled offsets (rblk 1, 2); 13 tile 32x16 with prefetch and unrolled offsets (rblk 1).  Tiles hold rblk in 1..4 right-hand sides per thread (16x16 and 64x4: 1;
+// unrolled offsets (rblk 1, 2); 13, 14 tiles 32x16 and 16x4 with prefetch and unrolled offsets (rblk 1).  Tiles hold rblk in 1..4 right-hand sides per thread (16x16 and 64x4: 1;
 // 32x8, 24x8 and 48x4 with prefetch: 1, 2).
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void *in, void *out,
@@ -76,7 +76,9 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         // tile width follows Lx so that no lanes idle (24 and 48 wide tiles
         // for extents that are multiples of those but not of 32)
         const int lx = g.L[0];
-        if (lx <= 16)
+        if (lx == 16 && rblk == 1 && std::is_same<WS, float2>::value && std::is_same<SS, float2>::value)
+            kernel = 14;  // 16x4 with unrolled offsets: four times the workgroups of 16x16 on small lattices
+        else if (lx <= 16)
             kernel = rblk == 1 ? 7 : 10;
         else if (rblk <= 2 && lx % 32 != 0 && lx % 48 == 0)
             kernel = 12;
@@ -115,6 +117,7 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
         case 12 * 16 + 1: return tiled<NOFF, WS, SS, A, 48, 4, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
         case 12 * 16 + 2: return tiled<NOFF, WS, SS, A, 48, 4, 2, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
         case 13 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 16, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
+        case 14 * 16 + 1: return tiled<NOFF, WS, SS, A, 16, 4, 1, true, true>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);
         default: return hipErrorInvalidValue;
     }
 }

@@ -25,7 +25,7 @@ PREC = {"f64": 0, "f32": 1, "f16": 2}
 
 # lattices: the 4^4 case, ragged volumes (not multiples of the 256-thread
 # block), extent-2 directions (x+1 == x-1), and a multi-block case
-LATTICES = [(4, 4, 4, 4), (5, 3, 2, 6), (2, 2, 2, 2), (6, 4, 4, 8)]
+LATTICES = [(4, 4, 4, 4), (5, 3, 2, 6), (2, 2, 2, 2), (6, 4, 4, 8), (16, 6, 2, 2)]
 
 
 @pytest.fixture(scope="module")
