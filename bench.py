@@ -70,20 +70,38 @@ def timed_launches(torch, fn, steps, warmup):
     return total, [s.elapsed_time(e) for s, e in ev]
 
 
-def batch_ms(torch, fn, steps, warmup):
-    """Mean ms per launch of `steps` back-to-back launches bracketed by one
-    event pair: for sub-millisecond kernels an event pair per launch adds its
-    own gap between launches."""
+def batch_ms(torch, fn, steps, warmup, out=None):
+    """Mean ms per launch of `steps` launches captured once in a HIP graph and
+    replayed between one event pair: sub-millisecond kernels launched one by
+    one from Python wait for the host (and an event pair per launch adds its
+    own gap).  With `out`, the first and the last replay are checked against
+    the eager result bit for bit."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    ref = out.clone() if out is not None else None
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(steps):
+            fn()
+    graph.replay()
+    torch.cuda.synchronize()
+    if ref is not None and not torch.equal(out, ref):
+        raise RuntimeError("graph replay differs from the eager apply")
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
-    for _ in range(steps):
-        fn()
+    for _ in range(3):
+        graph.replay()
     e.record()
     torch.cuda.synchronize()
-    return s.elapsed_time(e) / steps
+    if ref is not None and not torch.equal(out, ref):
+        raise RuntimeError("graph replay differs from the eager apply")
+    return s.elapsed_time(e) / (3 * steps)
 
 
 def cpu_baseline(u, psi, got, target_s=15.0):
@@ -226,8 +244,8 @@ def solve_24x48(torch, bri, dev, tol=1e-10):
 def variants_16_32(torch, bri, dev, steps=100):
     """The 16^3 x 32 lattice (links eps 0.3, seed 2001; Gaussian spinor, seed
     2002): 100 back-to-back applications each of the stored (W80 and W40) and
-    the recompute variants in FP64 and FP32, one right-hand side, timed as a
-    batch."""
+    the recompute variants in FP64 and FP32, one right-hand side, captured
+    in a HIP graph and timed on its replays."""
     import numpy as np
     import synth
     dims = (16, 16, 16, 32)
@@ -241,7 +259,8 @@ def variants_16_32(torch, bri, dev, steps=100):
         name = "f64" if prec == bri.F64 else "f32"
         for noff in (80, 40):
             W = bri.bri_build_transporters(dims, U64, prec, noff)
-            ms = batch_ms(torch, lambda: bri.bri_apply(dims, W, x, MASS), steps, 10)
+            y = torch.empty_like(x)
+            ms = batch_ms(torch, lambda: bri.bri_apply(dims, W, x, MASS, out=y), steps, 10, out=y)
             byts = bytes_per_site(noff, cb, cb) * V
             out[f"stored_w{noff}_{name}"] = {"ms": ms, "applies_s": 1e3 / ms,
                                              "gflops": FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9,
@@ -249,7 +268,9 @@ def variants_16_32(torch, bri, dev, steps=100):
                                              "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del W
         Ux = U64 if prec == bri.F64 else bri.bri_pack_links(dims, u, bri.F32)
-        ms = batch_ms(torch, lambda: bri.bri_apply(dims, Ux, x, MASS, variant=bri.RECOMPUTE), steps, 10)
+        y = torch.empty_like(x)
+        ms = batch_ms(torch, lambda: bri.bri_apply(dims, Ux, x, MASS, variant=bri.RECOMPUTE, out=y), steps, 10,
+                      out=y)
         out[f"recompute_{name}"] = {"ms": ms, "applies_s": 1e3 / ms,
                                     "gflops": FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9}
     return out
