@@ -593,12 +593,14 @@ def main():
         bench_variant("stored_w80_f32_12rhs", W, x12, 80, 8, 8, steps=5)
         extras["stored_w80_f32_12rhs"]["autotuned"] = name
         extras["stored_w80_f32_12rhs"]["autotune_ms"] = table
+        autotune.reset(bri.F32, bri.F32)  # the tuned choice would govern every later FP32 apply
         del x12
         x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F64)
         W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
         name, _, _ = autotune.tune(DIMS, W64, x12, MASS, reps=2)
         bench_variant("stored_w80_f64_12rhs", W64, x12, 80, 16, 16, steps=3)
         extras["stored_w80_f64_12rhs"]["autotuned"] = name
+        autotune.reset(bri.F64, bri.F64)
         del x12, W64, src
         torch.cuda.empty_cache()
         res["extras"] = extras

@@ -8,6 +8,10 @@ or 12 right-hand sides per thread)
 with HIP events on the current stream, installs the fastest through
 bri_set_apply_kernel / bri_set_rhs_block, and caches the choice in a JSON
 file keyed by (extents, w_prec, s_prec, n_offsets, nrhs, device name).
+
+The installed choice is library state per precision pair, not per shape: it
+governs every later apply with those precisions, whatever the lattice or
+number of right-hand sides, until reset() restores the built-in selection.
 """
 from __future__ import annotations
 
@@ -75,8 +79,15 @@ def _install(w_prec, s_prec, kernel, rblk):
     api.bri_set_rhs_block(w_prec, s_prec, rblk)
 
 
+def reset(w_prec, s_prec):
+    """Restore the built-in selection (kernel code 1, two right-hand sides
+    per thread where the tile holds several) for one precision pair."""
+    _install(w_prec, s_prec, 1, 0)
+
+
 def tune(dims, W, psi, mass=0.1, reps=5, use_cache=True):
-    """Pick and install the fastest configuration for apply(W, psi).
+    """Pick and install the fastest configuration for apply(W, psi); it stays
+    installed for the precision pair of (W, psi) until reset().
     Returns (name, ms, table of all timings)."""
     w_prec, s_prec = api.prec_of(W), api.prec_of(psi)
     n_off, nrhs = W.shape[0], psi.shape[0]

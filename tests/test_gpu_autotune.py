@@ -55,6 +55,10 @@ def test_autotuner_installs_a_configuration(tmp_path, monkeypatch):
         assert name in table and ms == min(table.values())
         again = autotune.tune(dims, W, x)          # served from the cache
         assert again[0] == name
+        kernel = bri.bri_get_apply_kernel(1, 1)
+        assert name.startswith(autotune.TILES.get(kernel, "gather"))
+        autotune.reset(1, 1)
+        assert (bri.bri_get_apply_kernel(1, 1), bri.bri_get_rhs_block(1, 1)) == (1, 2)
     finally:
         bri.bri_set_apply_kernel(1, 1, old[0])
         bri.bri_set_rhs_block(1, 1, old[1])
