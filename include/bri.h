@@ -85,7 +85,7 @@ const char *bri_last_error(void);
  * the coefficient table to bri_operator and to the gradient calls).  bri_abi_version() returns the
  * revision the library was built with; a caller compares it to
  * BRI_ABI_VERSION. */
-#define BRI_ABI_VERSION 3
+#define BRI_ABI_VERSION 4
 int32_t bri_abi_version(void);
 
 /* ---- sizes (bytes) of the SoA buffers ----------------------------------- */
@@ -136,6 +136,21 @@ bri_status bri_apply(bri_dims d, bri_variant v, const void *W_or_U, bri_prec w_p
 bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W_or_U, bri_prec w_prec,
                          int32_t n_offsets, bri_prec s_prec, double mass, const void *in,
                          void *out, int32_t nrhs, void *stream);
+
+/* ---- the Wilson comparison operator (Sec. 1; Wilson column of Tab. rholambda)
+ * out = D_W in (dagger = 0) or D_W^dag in (dagger = 1), with
+ *   (D_W psi)(x) = (4 + m) psi(x) - 1/2 sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                            + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)]
+ * and D_W^dag the same with gamma_mu -> -gamma_mu (the gamma matrices of the
+ * Brillouin apply).  U = SoA links [mu][9][V] and in/out = SoA spinors
+ * [rhs][12][V], all device memory in prec (F64 or F32; F16 gives
+ * BRI_E_UNSUPPORTED); accumulation in prec.  It is the 9-point operator the
+ * paper compares the Brillouin operator with; the same operator is the Wilson
+ * row of the generic class (bri_operator.coef), which reads all 80
+ * transporters.  nrhs in [1, 65535]; in and out must not overlap; pointers
+ * 16-byte aligned (BRI_E_ARG otherwise).  Enqueued on stream, asynchronous. */
+bri_status bri_apply_wilson(bri_dims d, const void *U_soa, bri_prec prec, double mass, const void *in,
+                            void *out, int32_t nrhs, int32_t dagger, void *stream);
 
 /* Choose the number of right-hand sides held per thread in the fused
  * multi-RHS apply (1, 2, 3, 4, 6 or 12; 0 restores the built-in default of 2)

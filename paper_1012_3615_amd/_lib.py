@@ -40,7 +40,7 @@ class bri_solve_stats(ctypes.Structure):
 
 
 # BRI_ABI_VERSION of include/bri.h that the structures below mirror
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class bri_operator(ctypes.Structure):
@@ -75,6 +75,7 @@ PROTOTYPES = {
     "bri_build_transporters": (_i32, [_D, _vp, _vp, _i32, _i32, _vp, _sz, _vp]),
     "bri_apply": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
     "bri_apply_dag": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
+    "bri_apply_wilson": (_i32, [_D, _vp, _i32, _dbl, _vp, _vp, _i32, _i32, _vp]),
     "bri_set_rhs_block": (_i32, [_i32, _i32, _i32]),
     "bri_get_rhs_block": (_i32, [_i32, _i32]),
     "bri_set_apply_kernel": (_i32, [_i32, _i32, _i32]),

@@ -186,6 +186,24 @@ def bri_apply_dag(dims, W_or_U, psi, mass, variant=STORED, out=None):
     return _apply(_lib_handle.bri_apply_dag, "bri_apply_dag", dims, W_or_U, psi, mass, variant, out)
 
 
+def bri_apply_wilson(dims, U, psi, mass, dagger=False, out=None):
+    """out = D_W psi (or D_W^dag psi), the Wilson operator straight from the
+    SoA links U; U and psi in the same precision (F64 or F32)."""
+    _need_cuda(U, psi, out)
+    V = volume(dims)
+    _shape(psi, (psi.shape[0], 12, V, 2), "spinor")
+    _shape(U, (4, 9, V, 2), "links")
+    if U.dtype != psi.dtype:
+        raise ValueError("links and spinor must have the same precision")
+    if out is None:
+        out = torch.empty_like(psi)
+    elif out.shape != psi.shape or out.dtype != psi.dtype:
+        raise ValueError("out must match the input spinor's shape and dtype")
+    _check(_lib_handle.bri_apply_wilson(_dims(dims), _ptr(U), prec_of(U), float(mass), _ptr(psi), _ptr(out),
+                                        psi.shape[0], int(bool(dagger)), _stream()), "bri_apply_wilson")
+    return out
+
+
 def bri_set_rhs_block(w_prec, s_prec, rhs_per_thread):
     _check(_lib_handle.bri_set_rhs_block(w_prec, s_prec, rhs_per_thread), "bri_set_rhs_block")
 

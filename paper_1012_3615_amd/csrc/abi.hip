@@ -222,6 +222,22 @@ bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W, bri_prec wp, 
     return apply_impl(d, v, W, wp, noff, sp, mass, in, out, nrhs, stream, true);
 }
 
+bri_status bri_apply_wilson(bri_dims d, const void *U, bri_prec prec, double mass, const void *in, void *out,
+                            int32_t nrhs, int32_t dagger, void *stream) {
+    g_last_error.clear();
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (prec != BRI_F64 && prec != BRI_F32) return fail(BRI_E_UNSUPPORTED, "the Wilson apply runs in F64 or F32");
+    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
+    if (dagger != 0 && dagger != 1) return fail(BRI_E_ARG, "dagger must be 0 or 1");
+    if (!aligned(U) || !aligned(in) || !aligned(out))
+        return fail(BRI_E_ARG, "null or misaligned (16 B) pointer");
+    const size_t sb = (size_t)g.V * 12 * nrhs * cbytes(prec);
+    if (overlap(in, sb, out, sb)) return fail(BRI_E_ARG, "in and out overlap");
+    return hip_check(apply_wilson(g, (int)prec, U, in, out, 4.0 + mass, nrhs, dagger != 0, (hipStream_t)stream),
+                     "apply (Wilson)");
+}
+
 bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
     g_last_error.clear();
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");

@@ -36,6 +36,10 @@ BRI_DECL_PROD(f16h)
 hipError_t apply_recompute(const Geom &g, int up, int sp, const void *U, const void *in, void *out,
                            double diag, int nrhs, bool dag, hipStream_t st);
 
+// wilson.hip: the Wilson comparison operator from SoA links (prec 0 = FP64, 1 = FP32)
+hipError_t apply_wilson(const Geom &g, int prec, const void *U, const void *in, void *out, double diag,
+                        int nrhs, bool dag, hipStream_t st);
+
 // build.hip: FP64 40-offset store, then conversion
 hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st);
 hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st);

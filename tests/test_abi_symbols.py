@@ -60,7 +60,7 @@ def test_size_queries(lib):
     assert lib.bri_transporter_bytes(d, 1, 39) == 0
     assert lib.bri_build_workspace_bytes(d, 0, 40) == 0
     assert lib.bri_build_workspace_bytes(d, 1, 80) == V * 40 * 9 * 16
-    assert lib.bri_abi_version() == 3
+    assert lib.bri_abi_version() == 4
     # production-operator forms: two-row SU(3) store and the clover term
     assert lib.bri_transporter_bytes_ex(d, 1, 80, 0) == V * 80 * 9 * 8
     assert lib.bri_transporter_bytes_ex(d, 1, 80, 1) == V * 80 * 9 * 8
@@ -95,6 +95,10 @@ def test_argument_errors_without_device(lib):
     op.w_form = 7
     assert lib.bri_apply_op(d, ctypes.byref(op), 1, 0.1, None, None, 1, 0, None) == -1
     assert b"form" in lib.bri_last_error()
+    assert lib.bri_apply_wilson(d, None, 1, 0.1, None, None, 1, 0, None) == -1
+    assert b"pointer" in lib.bri_last_error()
+    assert lib.bri_apply_wilson(d, None, 2, 0.1, None, None, 1, 0, None) == -2
+    assert lib.bri_apply_wilson(d, None, 1, 0.1, None, None, 1, 2, None) == -1
     assert lib.bri_build_transporters_ex(d, None, None, 1, 80, 2, None, 0, None) == -1
     assert lib.bri_ape_smear(d, None, None, 0.72, None) == -1
     assert lib.bri_build_clover(d, None, 1.0, None, 1, None) == -1

@@ -1,0 +1,116 @@
+"""GPU parity of the Wilson comparison operator (Sec. 1; the Wilson column
+of Tab. rholambda) applied straight from the links, against the oracle's
+generic-class apply with the Wilson table (pinned against the hopping form
+of the Wilson operator in the oracle tests).
+
+Tolerances as for the Brillouin operator: FP64 1e-12, FP32 1e-5 (relative
+2-norm against the FP64 oracle); at 32^3 x 64 on sampled sites."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ultralocal
+from oracle.gamma import gamma5
+from tests.helpers import dev, log, soa_to_canon
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def bri():
+    import paper_1012_3615_amd as m
+    return m
+
+
+# L = 2 in a direction (forward and backward neighbour coincide), odd
+# extents, a volume that is not a multiple of the 256-site workgroup
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 5, 3, 4), (2, 3, 2, 5), (16, 6, 2, 2)])
+def test_wilson_matches_oracle(bri, dims):
+    mass = 0.1
+    u = synth.gauge_links(dims, 0.4, 8701)
+    psi = synth.gaussian_spinor(dims, 8702, nrhs=3)
+    want = np.stack([ultralocal.apply(u, psi[r], mass, ultralocal.WILSON) for r in range(3)])
+    want_dag = np.stack([ultralocal.apply_dag(u, psi[r], mass, ultralocal.WILSON) for r in range(3)])
+    for p in (0, 1):
+        log(f"wilson {dims} prec={p}")
+        U = bri.bri_pack_links(dims, dev(u), p)
+        for nr in (1, 3):
+            x = bri.bri_pack_spinor(dims, dev(psi[:nr]), p)
+            got = soa_to_canon(dims, bri.bri_apply_wilson(dims, U, x, mass))
+            gdg = soa_to_canon(dims, bri.bri_apply_wilson(dims, U, x, mass, dagger=True))
+            for r in range(nr):
+                assert rel(got[r], want[r]) < TOL[p], (p, nr, r)
+                assert rel(gdg[r], want_dag[r]) < TOL[p], (p, nr, r, "dag")
+
+
+def test_wilson_gamma5_hermiticity_and_free_field(bri):
+    """D_W^dag = gamma5 D_W gamma5 on random links; on unit links a plane wave
+    e^{ik.x} u is mapped to the Wilson symbol times u (momenta allowed by the
+    periodic lattice)."""
+    dims = (8, 4, 6, 4)
+    mass = 0.05
+    u = synth.gauge_links(dims, 0.4, 8703)
+    psi = synth.gaussian_spinor(dims, 8704, nrhs=1)
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    x = bri.bri_pack_spinor(dims, dev(psi), bri.F64)
+    g5psi = np.einsum("st,...tc->...sc", gamma5(), psi)
+    x5 = bri.bri_pack_spinor(dims, dev(g5psi), bri.F64)
+    dag = soa_to_canon(dims, bri.bri_apply_wilson(dims, U, x, mass, dagger=True))[0]
+    g5dg5 = np.einsum("st,...tc->...sc", gamma5(), soa_to_canon(dims, bri.bri_apply_wilson(dims, U, x5, mass))[0])
+    assert rel(dag, g5dg5) < 1e-13
+    # free field
+    lx, ly, lz, lt = dims
+    k = 2 * np.pi * np.array([1 / lx, 2 / ly, 1 / lz, 3 / lt])
+    t, z, y, xx = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx), indexing="ij")
+    ph = np.exp(1j * (k[0] * xx + k[1] * y + k[2] * z + k[3] * t))
+    rng = np.random.default_rng(8705)
+    spin = rng.normal(size=(4, 3)) + 1j * rng.normal(size=(4, 3))
+    wave = ph[..., None, None] * spin
+    unit = np.zeros_like(u)
+    unit[..., 0, 0] = unit[..., 1, 1] = unit[..., 2, 2] = 1
+    Uu = bri.bri_pack_links(dims, dev(unit), bri.F64)
+    got = soa_to_canon(dims, bri.bri_apply_wilson(dims, Uu, bri.bri_pack_spinor(dims, dev(wave[None]), bri.F64),
+                                                  mass))[0]
+    sym = ultralocal.fourier_sum(k, mass, ultralocal.WILSON)
+    want = ph[..., None, None] * np.einsum("st,tc->sc", sym, spin)
+    assert rel(got, want) < 1e-13
+
+
+def test_wilson_full_size_sampled(bri):
+    """32^3 x 64, FP32, one right-hand side, the launch the bench times:
+    64 random sites (and the eight corners) against the pointwise oracle."""
+    dims = (32, 32, 32, 64)
+    mass = 0.1
+    log("wilson 32^3x64 sampled")
+    u = synth.gauge_links(dims, 0.3, 4001)
+    psi = synth.gaussian_spinor(dims, 4002, nrhs=1)
+    U = bri.bri_pack_links(dims, dev(u), bri.F32)
+    x = bri.bri_pack_spinor(dims, dev(psi), bri.F32)
+    got = soa_to_canon(dims, bri.bri_apply_wilson(dims, U, x, mass))[0]
+    rng = np.random.default_rng(8706)
+    sites = np.stack([rng.integers(0, L, 64) for L in dims], axis=1)
+    corners = np.array([[a * (dims[0] - 1), b * (dims[1] - 1), 0, c * (dims[3] - 1)]
+                        for a in (0, 1) for b in (0, 1) for c in (0, 1)])
+    sites = np.concatenate([sites, corners])
+    want = ultralocal.apply_at(u, psi[0], mass, ultralocal.WILSON, sites)
+    g = np.stack([got[t, z, y, xx] for xx, y, z, t in sites])
+    assert rel(g, want) < TOL[1]
+
+
+def test_wilson_rejects_bad_arguments(bri):
+    import torch
+    dims = (4, 4, 4, 4)
+    U = torch.zeros((4, 9, 256, 2), dtype=torch.float16, device="cuda")
+    x = torch.zeros((1, 12, 256, 2), dtype=torch.float16, device="cuda")
+    with pytest.raises(Exception):
+        bri.bri_apply_wilson(dims, U, x, 0.1)
+    U = torch.zeros((4, 9, 256, 2), dtype=torch.float32, device="cuda")
+    x = torch.zeros((1, 12, 256, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        bri.bri_apply_wilson(dims, U, x, 0.1)
