@@ -276,6 +276,33 @@ def variants_16_32(torch, bri, dev, steps=100):
     return out
 
 
+def wilson_comparison(torch, bri, u, x32, brillouin_ms, dev, steps=50):
+    """The Wilson operator (the paper's comparison operator, applied from the
+    links, half-spinor hops) on the same 32^3 x 64 links and spinor, FP32
+    and FP64, one right-hand side; `steps` applications captured in a HIP
+    graph and timed on its replays.  The ratio of the headline Brillouin
+    launch to the FP32 Wilson launch is the cost of one D_B application in
+    Wilson applications on this GPU (the paper's conjecture: near 1 where
+    both are bound by memory traffic).  Algorithmic bytes per site: the four
+    links of the site plus the spinor read and written (each neighbour
+    spinor and backward link counted once, at its own site)."""
+    import numpy as np
+    V = int(np.prod(DIMS))
+    out = {}
+    for prec, cb, name in ((bri.F32, 8, "f32"), (bri.F64, 16, "f64")):
+        U = bri.bri_pack_links(DIMS, torch.from_numpy(u).to(dev), prec)
+        x = x32 if prec == bri.F32 else bri.bri_pack_spinor(DIMS, bri.bri_unpack_spinor(DIMS, x32), bri.F64)
+        y = torch.empty_like(x)
+        ms = batch_ms(torch, lambda: bri.bri_apply_wilson(DIMS, U, x, MASS, out=y), steps, 10, out=y)
+        bps = 36 * cb + 24 * cb
+        out[f"wilson_{name}"] = {"ms": ms, "applies_s": 1e3 / ms, "alg_bytes_per_site": bps,
+                                 "alg_GBs": bps * V / (ms * 1e-3) / 1e9,
+                                 "hbm_frac": bps * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del U, x, y
+    out["brillouin_f32_over_wilson_f32"] = brillouin_ms / out["wilson_f32"]["ms"]
+    return out
+
+
 def gradient_timing(torch, bri, dev):
     """FP64 link gradient of S = Re<chi, D psi> at 16^3 x 32 (the gradient
     lattice), as the autograd Function runs it: forward = transporter build
@@ -605,6 +632,8 @@ def main():
         torch.cuda.empty_cache()
         res["extras"] = extras
 
+    if not a.no_extras:
+        res["wilson_32x32x32x64"] = wilson_comparison(torch, bri, u, x32, per_ms, dev)
     if not a.no_extras and not a.no_solve:
         res["solve_12rhs"] = solve_comparison(torch, bri, U64, dev)
     if not a.no_extras:

@@ -27,45 +27,52 @@ __device__ __forceinline__ cx<A> times_i(cx<A> z) { return {-z.im, z.re}; }
 template <typename A>
 __device__ __forceinline__ cx<A> times_mi(cx<A> z) { return {z.im, -z.re}; }
 
-// (o0, o1) = B_mu (l0, l1)
-template <int MU, typename A>
-__device__ __forceinline__ void b_mul(cx<A> l0, cx<A> l1, cx<A> &o0, cx<A> &o1) {
-    if (MU == 0) { o0 = times_mi(l1); o1 = times_mi(l0); }
-    if (MU == 1) { o0 = {-l1.re, -l1.im}; o1 = l0; }
-    if (MU == 2) { o0 = times_mi(l0); o1 = times_i(l1); }
-    if (MU == 3) { o0 = l0; o1 = l1; }
+// (o0, o1) = B_mu (l0, l1); mu is the same for every lane (uniform branches)
+template <typename A>
+__device__ __forceinline__ void b_mul(int mu, cx<A> l0, cx<A> l1, cx<A> &o0, cx<A> &o1) {
+    if (mu == 0) { o0 = times_mi(l1); o1 = times_mi(l0); }
+    else if (mu == 1) { o0 = {-l1.re, -l1.im}; o1 = l0; }
+    else if (mu == 2) { o0 = times_mi(l0); o1 = times_i(l1); }
+    else { o0 = l0; o1 = l1; }
 }
 
 // (o2, o3) = B_mu^dag (u0, u1)
-template <int MU, typename A>
-__device__ __forceinline__ void bdag_mul(cx<A> u0, cx<A> u1, cx<A> &o2, cx<A> &o3) {
-    if (MU == 0) { o2 = times_i(u1); o3 = times_i(u0); }
-    if (MU == 1) { o2 = u1; o3 = {-u0.re, -u0.im}; }
-    if (MU == 2) { o2 = times_i(u0); o3 = times_mi(u1); }
-    if (MU == 3) { o2 = u0; o3 = u1; }
+template <typename A>
+__device__ __forceinline__ void bdag_mul(int mu, cx<A> u0, cx<A> u1, cx<A> &o2, cx<A> &o3) {
+    if (mu == 0) { o2 = times_i(u1); o3 = times_i(u0); }
+    else if (mu == 1) { o2 = u1; o3 = {-u0.re, -u0.im}; }
+    else if (mu == 2) { o2 = times_i(u0); o3 = times_mi(u1); }
+    else { o2 = u0; o3 = u1; }
 }
 
-// acc += -1/2 (1 - s gamma_mu) W psi(y), W = U_mu(x) for the forward hop
-// (N = +1), U_mu(x-mu)^dag for the backward hop (N = -1); s = N, or -N for D^dag.
-template <int MU, int N, bool DAG, typename T, typename A>
-__device__ __forceinline__ void wilson_hop(const Geom &g, const int c[4], int site, size_t V,
+// acc += -1/2 (1 - s gamma_mu) W psi(y) for hop = 2 mu + (0: forward, 1:
+// backward): W = U_mu(x), y = x + mu for the forward hop, W = U_mu(x-mu)^dag,
+// y = x - mu for the backward one; s = +1 forward, -1 backward (negated for
+// D^dag).  Everything lane-dependent is computed from the run-time hop, so
+// the compiler cannot hoist the addresses of all eight hops out of the loop.
+template <bool DAG, typename T, typename A>
+__device__ __forceinline__ void wilson_hop(int hop, const Geom &g, const int c[4], int site, size_t V,
                                            const T *__restrict__ U, const T *__restrict__ q,
                                            cx<A> (&acc)[4][3]) {
-    const int L = g.L[MU], str = g.stride[MU];
-    const int y = N > 0 ? (c[MU] == L - 1 ? site - (L - 1) * str : site + str)
-                        : (c[MU] == 0 ? site + (L - 1) * str : site - str);
-    const A s = (A)(DAG ? -N : N);
+    const int mu = hop >> 1;
+    const bool fwd = (hop & 1) == 0;
+    const int L = g.L[mu], str = g.stride[mu];
+    const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
+    const int y = fwd ? (cm == L - 1 ? site - (L - 1) * str : site + str)
+                      : (cm == 0 ? site + (L - 1) * str : site - str);
+    const A s = (fwd != DAG) ? (A)1 : (A)-1;
+    const T *qy = q + y;
     cx<A> h[2][3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const cx<A> u0 = ldc<A>(q + (size_t)(0 + b) * V + y), u1 = ldc<A>(q + (size_t)(3 + b) * V + y);
-        const cx<A> l0 = ldc<A>(q + (size_t)(6 + b) * V + y), l1 = ldc<A>(q + (size_t)(9 + b) * V + y);
+        const cx<A> u0 = ldc<A>(qy + (size_t)(0 + b) * V), u1 = ldc<A>(qy + (size_t)(3 + b) * V);
+        const cx<A> l0 = ldc<A>(qy + (size_t)(6 + b) * V), l1 = ldc<A>(qy + (size_t)(9 + b) * V);
         cx<A> t0, t1;
-        b_mul<MU>(l0, l1, t0, t1);
+        b_mul(mu, l0, l1, t0, t1);
         h[0][b] = caxpy(-s, t0, u0);
         h[1][b] = caxpy(-s, t1, u1);
     }
-    const T *p = U + (size_t)MU * 9 * V + (N > 0 ? site : y);
+    const T *p = U + (size_t)mu * 9 * V + (fwd ? site : y);
     cx<A> w[3][3];
 #pragma unroll
     for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + (size_t)e * V);
@@ -73,7 +80,7 @@ __device__ __forceinline__ void wilson_hop(const Geom &g, const int c[4], int si
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         cx<A> y0, y1;
-        if (N > 0) {
+        if (fwd) {
             y0 = cmul(w[a][0], h[0][0]);
             y1 = cmul(w[a][0], h[1][0]);
 #pragma unroll
@@ -93,54 +100,148 @@ __device__ __forceinline__ void wilson_hop(const Geom &g, const int c[4], int si
         acc[0][a] = caxpy(-half, y0, acc[0][a]);
         acc[1][a] = caxpy(-half, y1, acc[1][a]);
         cx<A> t2, t3;
-        bdag_mul<MU>(y0, y1, t2, t3);
+        bdag_mul(mu, y0, y1, t2, t3);
         acc[2][a] = caxpy(half * s, t2, acc[2][a]);
         acc[3][a] = caxpy(half * s, t3, acc[3][a]);
     }
 }
 
-// One thread = one site of one right-hand side (blockIdx.y).  Neighbour
-// spinors and the backward links come through the caches; the site blocks
-// of one XCD are consecutive, so a neighbour in y, z or t was read shortly
-// before by a block of the same XCD.
+// The t hops from registers: U_mu(x - t)^dag h with h the backward projection
+// of psi(x - t) is what the forward t hop of the site below has at hand (its
+// link and its spinor), so a thread owns one (x, y, z) and walks a chunk of t
+// values, carrying that product and the spinor it loaded for its forward hop
+// to the next step.  The x, y and z hops read their neighbours through the
+// caches (the threads of those neighbours read the same data at about the
+// same step).
+template <typename T, typename A>
+__device__ __forceinline__ void load_spinor(const T *__restrict__ p, size_t V, cx<A> (&v)[4][3]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[s][a] = ldc<A>(p + (size_t)(3 * s + a) * V);
+}
+
+// (1 - s gamma_t) psi has upper part h = psi_u - s psi_l (B_t = 1)
+template <typename A>
+__device__ __forceinline__ void project_t(const cx<A> (&v)[4][3], A s, cx<A> (&h)[2][3]) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        h[0][b] = caxpy(-s, v[2][b], v[0][b]);
+        h[1][b] = caxpy(-s, v[3][b], v[1][b]);
+    }
+}
+
+// acc += -1/2 (1 - s gamma_t) applied to the colour-multiplied upper part y
+template <typename A>
+__device__ __forceinline__ void reconstruct_t(const cx<A> (&y)[2][3], A s, cx<A> (&acc)[4][3]) {
+    const A half = (A)0.5;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[0][a] = caxpy(-half, y[0][a], acc[0][a]);
+        acc[1][a] = caxpy(-half, y[1][a], acc[1][a]);
+        acc[2][a] = caxpy(half * s, y[0][a], acc[2][a]);
+        acc[3][a] = caxpy(half * s, y[1][a], acc[3][a]);
+    }
+}
+
+// y = W^dag h
+template <typename A>
+__device__ __forceinline__ void mul_dag(const cx<A> (&w)[3][3], const cx<A> (&h)[2][3], cx<A> (&y)[2][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        y[0][a] = cmul(cconj(w[0][a]), h[0][0]);
+        y[1][a] = cmul(cconj(w[0][a]), h[1][0]);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+            y[0][a] = cmacc(y[0][a], w[b][a], h[0][b]);
+            y[1][a] = cmacc(y[1][a], w[b][a], h[1][b]);
+        }
+    }
+}
+
 template <typename T, typename A, bool DAG>
 __global__ __launch_bounds__(256) void k_wilson(Geom g, const T *__restrict__ U, const T *__restrict__ in,
-                                                T *__restrict__ out, A diag) {
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int site = blk * blockDim.x + threadIdx.x;
-    if (site >= g.V) return;
+                                                T *__restrict__ out, A diag, int tchunk) {
+    const int v3 = g.stride[3];  // Lx Ly Lz
+    const int s3 = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (s3 >= v3) return;
+    const int lt = g.L[3];
+    const int t0 = blockIdx.y * tchunk;
+    const int t1 = min(t0 + tchunk, lt);
     const size_t V = (size_t)g.V;
-    const T *q = in + (size_t)blockIdx.y * 12 * V;
-    int c[4];
-    coords(g, site, c);
-    cx<A> acc[4][3];
+    const T *q = in + (size_t)blockIdx.z * 12 * V;
+    T *o = out + (size_t)blockIdx.z * 12 * V;
+    const T *Ut = U + (size_t)3 * 9 * V;
+    const A sf = DAG ? (A)-1 : (A)1;  // s of the forward hops; -sf for the backward ones
+
+    // carry = U_t(x, t0-1)^dag (1 + sf gamma_t)-projection of psi(x, t0-1)
+    cx<A> carry[2][3], nxt[4][3];
+    {
+        const int sb = s3 + (t0 == 0 ? lt - 1 : t0 - 1) * v3;
+        cx<A> v[4][3], h[2][3], w[3][3];
+        load_spinor(q + sb, V, v);
+        project_t(v, -sf, h);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+        for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(Ut + (size_t)e * V + sb);
+        mul_dag(w, h, carry);
+    }
+    load_spinor(q + s3 + t0 * v3, V, nxt);
+
+#pragma unroll 1
+    for (int t = t0; t < t1; ++t) {
+        const int site = s3 + t * v3;
+        int c[4];
+        coords(g, site, c);
+        cx<A> acc[4][3], hb[2][3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) acc[s][a] = cscale(diag, ldc<A>(q + (size_t)(3 * s + a) * V + site));
-    wilson_hop<0, +1, DAG>(g, c, site, V, U, q, acc);
-    wilson_hop<0, -1, DAG>(g, c, site, V, U, q, acc);
-    wilson_hop<1, +1, DAG>(g, c, site, V, U, q, acc);
-    wilson_hop<1, -1, DAG>(g, c, site, V, U, q, acc);
-    wilson_hop<2, +1, DAG>(g, c, site, V, U, q, acc);
-    wilson_hop<2, -1, DAG>(g, c, site, V, U, q, acc);
-    wilson_hop<3, +1, DAG>(g, c, site, V, U, q, acc);
-    wilson_hop<3, -1, DAG>(g, c, site, V, U, q, acc);
-    T *o = out + (size_t)blockIdx.y * 12 * V + site;
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+            for (int a = 0; a < 3; ++a) acc[s][a] = cscale(diag, nxt[s][a]);
+        project_t(nxt, -sf, hb);  // for the backward t hop of the next step
+#pragma unroll 1
+        for (int hop = 0; hop < 6; ++hop) wilson_hop<DAG>(hop, g, c, site, V, U, q, acc);
+        // loaded after the x, y, z hops: live across them it costs 24 (FP32)
+        // or 48 (FP64) registers per lane
+        const int sn = s3 + (t == lt - 1 ? 0 : t + 1) * v3;
+        load_spinor(q + sn, V, nxt);
+        // forward t hop from the spinor just loaded; its link also makes the carry
+        cx<A> w[3][3], h[2][3], y[2][3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) st(o + (size_t)(3 * s + a) * V, acc[s][a]);
+        for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(Ut + (size_t)e * V + site);
+        project_t(nxt, sf, h);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            y[0][a] = cmul(w[a][0], h[0][0]);
+            y[1][a] = cmul(w[a][0], h[1][0]);
+#pragma unroll
+            for (int b = 1; b < 3; ++b) {
+                y[0][a] = cmac(y[0][a], w[a][b], h[0][b]);
+                y[1][a] = cmac(y[1][a], w[a][b], h[1][b]);
+            }
+        }
+        reconstruct_t(y, sf, acc);
+        reconstruct_t(carry, -sf, acc);  // backward t hop
+        mul_dag(w, hb, carry);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) st(o + (size_t)(3 * s + a) * V + site, acc[s][a]);
+    }
 }
 
 template <typename T, typename A>
 hipError_t launch(const Geom &g, const void *U, const void *in, void *out, double diag, int nrhs, bool dag,
                   hipStream_t st) {
-    const dim3 grid((g.V + 255) / 256, nrhs), block(256);
+    const int lt = g.L[3], v3 = g.stride[3];
+    // chunks of 8 t values (one halo spinor and link per 8 sites) unless that
+    // leaves fewer than four workgroups per CU
+    int tchunk = 8;
+    while (tchunk > 1 && (long long)((v3 + 255) / 256) * ((lt + tchunk - 1) / tchunk) * nrhs < 1024) tchunk /= 2;
+    const dim3 grid((v3 + 255) / 256, (lt + tchunk - 1) / tchunk, nrhs), block(256);
     if (dag)
-        k_wilson<T, A, true><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag);
+        k_wilson<T, A, true><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag, tchunk);
     else
-        k_wilson<T, A, false><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag);
+        k_wilson<T, A, false><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag, tchunk);
     return hipGetLastError();
 }
 

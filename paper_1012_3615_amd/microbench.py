@@ -8,7 +8,8 @@ Each variant builds its inputs (links exp(i 0.3 H), seed 4001; Gaussian
 spinors; the 12 point sources for the 12-RHS variant; for the production
 operator forms prod*: one APE step, back-projected transporters whole or as
 two rows, and the clover term; overlap_sign_24: sign(gamma5 D) at 24^3 x 48
-to 1e-10 for the smeared, projected kernel at mass -1), runs one untimed
+to 1e-10 for the smeared, projected kernel at mass -1; wilson_f32/_f64: the
+Wilson comparison operator from the links), runs one untimed
 launch, then `reps` launches timed with HIP events on the current stream,
 and prints one line per variant.  `stream` times a plain device read of a
 8 GiB buffer (torch sum) and a 2 GiB copy, as a reference for the
@@ -91,6 +92,16 @@ def run(dims, names, reps=3, mass=0.1):
             continue
         if name == "overlap_sign_24":
             out.append(_run_overlap(reps))
+            torch.cuda.empty_cache()
+            continue
+        if name in ("wilson_f32", "wilson_f64"):
+            wp = bri.F32 if name == "wilson_f32" else bri.F64
+            Uw = bri.bri_pack_links(dims, Ud, wp)
+            x = bri.bri_pack_spinor(dims, psi, wp)
+            y = torch.empty_like(x)
+            ms = _time(lambda: bri.bri_apply_wilson(dims, Uw, x, mass, out=y), reps)
+            out.append({"variant": name, "ms": ms, "alg_GBs": V * 60 * CB[wp] / ms / 1e6})
+            del Uw, x, y
             torch.cuda.empty_cache()
             continue
         if name in PROD:

@@ -103,6 +103,37 @@ def test_wilson_full_size_sampled(bri):
     assert rel(g, want) < TOL[1]
 
 
+def test_wilson_t_chunks_with_ragged_tail(bri):
+    """Enough work for the t walk to run in chunks of 8 (32^3 x 12, twelve
+    right-hand sides): chunks [0, 8) and [8, 12), so the carried backward hop
+    crosses a chunk start and the last chunk is short; FP64, D and D^dag, on
+    sampled sites including every t slice next to a chunk edge."""
+    dims = (32, 32, 32, 12)
+    mass = 0.1
+    log("wilson 32^3x12 12 rhs chunks")
+    u = synth.gauge_links(dims, 0.3, 8707)
+    psi = synth.gaussian_spinor(dims, 8708, nrhs=12)
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    x = bri.bri_pack_spinor(dims, dev(psi), bri.F64)
+    got = soa_to_canon(dims, bri.bri_apply_wilson(dims, U, x, mass))
+    gdg = soa_to_canon(dims, bri.bri_apply_wilson(dims, U, x, mass, dagger=True))
+    rng = np.random.default_rng(8709)
+    ts = np.array([0, 7, 8, 11, 3, 9])
+    sites = np.stack([rng.integers(0, 32, 12), rng.integers(0, 32, 12), rng.integers(0, 32, 12),
+                      np.repeat(ts, 2)], axis=1)
+    for r in range(12):
+        want = ultralocal.apply_at(u, psi[r], mass, ultralocal.WILSON, sites)
+        g = np.stack([got[r, t, z, y, xx] for xx, y, z, t in sites])
+        assert rel(g, want) < TOL[0], r
+    # D^dag at the same sites from gamma5 D gamma5 of the oracle (whole-lattice
+    # adjoint would be slow at this size)
+    g5 = gamma5()
+    psi5 = np.einsum("st,...tc->...sc", g5, psi[0])
+    want = np.einsum("st,...tc->...sc", g5, ultralocal.apply_at(u, psi5, mass, ultralocal.WILSON, sites))
+    g = np.stack([gdg[0, t, z, y, xx] for xx, y, z, t in sites])
+    assert rel(g, want) < TOL[0]
+
+
 def test_wilson_rejects_bad_arguments(bri):
     import torch
     dims = (4, 4, 4, 4)
