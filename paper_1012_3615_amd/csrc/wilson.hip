@@ -106,6 +106,51 @@ __device__ __forceinline__ void wilson_hop(int hop, const Geom &g, const int c[4
     }
 }
 
+// acc += -1/2 (1 - s gamma_mu) W v with v the neighbour spinor and W the
+// link (forward hop) or its adjoint taken here (backward hop), both in
+// registers; the same arithmetic as wilson_hop.
+template <bool DAG, typename A>
+__device__ __forceinline__ void hop_core(int mu, bool fwd, const cx<A> (&v)[4][3], const cx<A> (&w)[3][3],
+                                         cx<A> (&acc)[4][3]) {
+    const A s = (fwd != DAG) ? (A)1 : (A)-1;
+    cx<A> h[2][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        cx<A> t0, t1;
+        b_mul(mu, v[2][b], v[3][b], t0, t1);
+        h[0][b] = caxpy(-s, t0, v[0][b]);
+        h[1][b] = caxpy(-s, t1, v[1][b]);
+    }
+    const A half = (A)0.5;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<A> y0, y1;
+        if (fwd) {
+            y0 = cmul(w[a][0], h[0][0]);
+            y1 = cmul(w[a][0], h[1][0]);
+#pragma unroll
+            for (int b = 1; b < 3; ++b) {
+                y0 = cmac(y0, w[a][b], h[0][b]);
+                y1 = cmac(y1, w[a][b], h[1][b]);
+            }
+        } else {
+            y0 = cmul(cconj(w[0][a]), h[0][0]);
+            y1 = cmul(cconj(w[0][a]), h[1][0]);
+#pragma unroll
+            for (int b = 1; b < 3; ++b) {
+                y0 = cmacc(y0, w[b][a], h[0][b]);
+                y1 = cmacc(y1, w[b][a], h[1][b]);
+            }
+        }
+        acc[0][a] = caxpy(-half, y0, acc[0][a]);
+        acc[1][a] = caxpy(-half, y1, acc[1][a]);
+        cx<A> t2, t3;
+        bdag_mul(mu, y0, y1, t2, t3);
+        acc[2][a] = caxpy(half * s, t2, acc[2][a]);
+        acc[3][a] = caxpy(half * s, t3, acc[3][a]);
+    }
+}
+
 // The t hops from registers: U_mu(x - t)^dag h with h the backward projection
 // of psi(x - t) is what the forward t hop of the site below has at hand (its
 // link and its spinor), so a thread owns one (x, y, z) and walks a chunk of t
@@ -229,6 +274,117 @@ __global__ __launch_bounds__(256) void k_wilson(Geom g, const T *__restrict__ U,
     }
 }
 
+// The same walk over t for lattices with Lx a multiple of 32 and Ly of 8:
+// a workgroup owns a 32 x 8 (x, y) tile at one z, and at every step stages
+// the tile's spinors (from the registers of their threads) and its 80-site
+// x/y halo (from memory) in LDS, so the x and y hops read their neighbours
+// there instead of fetching them again through the caches.
+constexpr int WTX = 32, WTY = 8, WHALO = 2 * WTX + 2 * WTY;
+
+template <typename T, typename A, bool DAG>
+__global__ __launch_bounds__(256) void k_wilson_tile(Geom g, const T *__restrict__ U, const T *__restrict__ in,
+                                                     T *__restrict__ out, A diag, int tchunk) {
+    __shared__ cx<A> lds[12][WTY + 2][WTX + 2];
+    const int lx = g.L[0], ly = g.L[1], lt = g.L[3];
+    const int ntx = lx / WTX, nty = ly / WTY;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * WTX, y0 = ((tile / ntx) % nty) * WTY, z = tile / (ntx * nty);
+    const int tx = threadIdx.x % WTX, ty = threadIdx.x / WTX;
+    const int v3 = g.stride[3];
+    const int s3 = (x0 + tx) + lx * ((y0 + ty) + ly * z);
+    const int t0 = blockIdx.y * tchunk;
+    const int t1 = min(t0 + tchunk, lt);
+    const size_t V = (size_t)g.V;
+    const T *q = in + (size_t)blockIdx.z * 12 * V;
+    T *o = out + (size_t)blockIdx.z * 12 * V;
+    const T *Ut = U + (size_t)3 * 9 * V;
+    const A sf = DAG ? (A)-1 : (A)1;
+
+    cx<A> carry[2][3], cur[4][3];
+    {
+        const int sb = s3 + (t0 == 0 ? lt - 1 : t0 - 1) * v3;
+        cx<A> v[4][3], h[2][3], w[3][3];
+        load_spinor(q + sb, V, v);
+        project_t(v, -sf, h);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(Ut + (size_t)e * V + sb);
+        mul_dag(w, h, carry);
+    }
+    load_spinor(q + s3 + t0 * v3, V, cur);
+
+#pragma unroll 1
+    for (int t = t0; t < t1; ++t) {
+        const int site = s3 + t * v3;
+        __syncthreads();  // the previous step's readers of the tile are done
+#pragma unroll
+        for (int c = 0; c < 12; ++c) lds[c][ty + 1][tx + 1] = cur[c / 3][c % 3];
+        for (int i = threadIdx.x; i < 12 * WHALO; i += 256) {
+            const int c = i / WHALO, h = i % WHALO;
+            int hx, hy;
+            if (h < WTX) { hx = h + 1; hy = 0; }
+            else if (h < 2 * WTX) { hx = h - WTX + 1; hy = WTY + 1; }
+            else if (h < 2 * WTX + WTY) { hx = 0; hy = h - 2 * WTX + 1; }
+            else { hx = WTX + 1; hy = h - 2 * WTX - WTY + 1; }
+            const int gx = (x0 + hx - 1 + lx) % lx, gy = (y0 + hy - 1 + ly) % ly;
+            lds[c][hy][hx] = ldc<A>(q + (size_t)c * V + gx + lx * (gy + ly * z) + (size_t)t * v3);
+        }
+        __syncthreads();
+        int c4[4];
+        coords(g, site, c4);
+        cx<A> acc[4][3], hb[2][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[s][a] = cscale(diag, cur[s][a]);
+        project_t(cur, -sf, hb);
+#pragma unroll 1
+        for (int hop = 0; hop < 4; ++hop) {
+            const int mu = hop >> 1;
+            const bool fwd = (hop & 1) == 0;
+            const int d = fwd ? 1 : -1;
+            const int hx = tx + 1 + (mu == 0 ? d : 0), hy = ty + 1 + (mu == 1 ? d : 0);
+            cx<A> v[4][3], w[3][3];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) v[c / 3][c % 3] = lds[c][hy][hx];
+            int ls = site;
+            if (!fwd) {
+                const int L = g.L[mu], str = g.stride[mu];
+                const int cm = mu == 0 ? c4[0] : c4[1];
+                ls = cm == 0 ? site + (L - 1) * str : site - str;
+            }
+            const T *p = U + (size_t)mu * 9 * V + ls;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + (size_t)e * V);
+            hop_core<DAG>(mu, fwd, v, w, acc);
+        }
+#pragma unroll 1
+        for (int hop = 4; hop < 6; ++hop) wilson_hop<DAG>(hop, g, c4, site, V, U, q, acc);
+        const int sn = s3 + (t == lt - 1 ? 0 : t + 1) * v3;
+        load_spinor(q + sn, V, cur);
+        cx<A> w[3][3], h[2][3], y[2][3];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(Ut + (size_t)e * V + site);
+        project_t(cur, sf, h);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            y[0][a] = cmul(w[a][0], h[0][0]);
+            y[1][a] = cmul(w[a][0], h[1][0]);
+#pragma unroll
+            for (int b = 1; b < 3; ++b) {
+                y[0][a] = cmac(y[0][a], w[a][b], h[0][b]);
+                y[1][a] = cmac(y[1][a], w[a][b], h[1][b]);
+            }
+        }
+        reconstruct_t(y, sf, acc);
+        reconstruct_t(carry, -sf, acc);
+        mul_dag(w, hb, carry);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) st(o + (size_t)(3 * s + a) * V + site, acc[s][a]);
+    }
+}
+
 template <typename T, typename A>
 hipError_t launch(const Geom &g, const void *U, const void *in, void *out, double diag, int nrhs, bool dag,
                   hipStream_t st) {
@@ -238,6 +394,16 @@ hipError_t launch(const Geom &g, const void *U, const void *in, void *out, doubl
     int tchunk = 8;
     while (tchunk > 1 && (long long)((v3 + 255) / 256) * ((lt + tchunk - 1) / tchunk) * nrhs < 1024) tchunk /= 2;
     const dim3 grid((v3 + 255) / 256, (lt + tchunk - 1) / tchunk, nrhs), block(256);
+    if (g.L[0] % WTX == 0 && g.L[1] % WTY == 0) {
+        // v3 / 256 tiles of 32 x 8 sites, the same grid
+        if (dag)
+            k_wilson_tile<T, A, true><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag,
+                                                              tchunk);
+        else
+            k_wilson_tile<T, A, false><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag,
+                                                               tchunk);
+        return hipGetLastError();
+    }
     if (dag)
         k_wilson<T, A, true><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag, tchunk);
     else
