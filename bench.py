@@ -303,6 +303,54 @@ def wilson_comparison(torch, bri, u, x32, brillouin_ms, dev, steps=50):
     return out
 
 
+def wilson_brillouin_iterations(torch, bri, dev, tol=1e-10, k=200):
+    """Inversion cost of the two operators at matched low end (Sec. 6 and its
+    footnote: at a fixed pion mass the smallest eigenvalues of D^dag D are
+    about equal, the largest near 2.5^2 for Brillouin and 7.5^2 for Wilson,
+    so CG should need about a third of the iterations).  On the 16^3 x 32
+    links (eps 0.3, seed 2001) the Wilson mass is tuned so that the smallest
+    Ritz value of D_W^dag D_W (k Lanczos steps from a Gaussian start, seed
+    2003) matches that of D_B^dag D_B at m_B; then plain FP64 CGNE to 1e-10
+    from a Gaussian source (seed 2002) with each operator.  Wilson runs
+    through the generic-class table: the same solver and transporter store,
+    so the iteration counts compare the operators, not the kernels."""
+    import numpy as np
+    import synth
+    dims = (16, 16, 16, 32)
+    U = bri.bri_pack_links(dims, torch.from_numpy(synth.gauge_links(dims, EPS, 2001)).to(dev), bri.F64)
+    W = bri.bri_build_transporters(dims, U, bri.F64, 80)
+    ops = {"brillouin": bri.Operator(W), "wilson": bri.Operator(W, coef=bri.TABLE_WILSON)}
+    b = bri.bri_pack_spinor(dims, torch.from_numpy(synth.gaussian_spinor(dims, 2002, 1)).to(dev), bri.F64)
+    v0 = bri.bri_pack_spinor(dims, torch.from_numpy(synth.gaussian_spinor(dims, 2003, 1)).to(dev), bri.F64)
+
+    def extremes(op, m):
+        a, bb, _ = bri.bri_lanczos(dims, op, m, k, v0)
+        r = bri.bri_ritz_values(a, bb)
+        return float(r[0]), float(r[-1])
+
+    def cgne(op, m):
+        _, info = bri.bri_solve_cgne_op(dims, op, b, m, bri.solve_params(tol=tol, inner_prec=bri.F64))
+        return int(info["iterations"]), float(info["true_residual"][0])
+
+    out = {}
+    for m_b in (0.05, 0.2):
+        lo_b, hi_b = extremes(ops["brillouin"], m_b)
+        m_w = m_b
+        for _ in range(4):  # sqrt(lambda_min) grows about one for one with m
+            lo_w, _ = extremes(ops["wilson"], m_w)
+            m_w += float(np.sqrt(lo_b) - np.sqrt(lo_w))
+        lo_w, hi_w = extremes(ops["wilson"], m_w)
+        it_b, res_b = cgne(ops["brillouin"], m_b)
+        it_w, res_w = cgne(ops["wilson"], m_w)
+        out[f"m_B={m_b}"] = {
+            "m_W": m_w, "lambda_min_B": lo_b, "lambda_min_W": lo_w, "lambda_max_B": hi_b, "lambda_max_W": hi_w,
+            "condition_B": hi_b / lo_b, "condition_W": hi_w / lo_w,
+            "cgne_iterations_B": it_b, "cgne_iterations_W": it_w, "iterations_B_over_W": it_b / it_w,
+            "sqrt_condition_ratio": float(np.sqrt((hi_b / lo_b) / (hi_w / lo_w))),
+            "true_residual_B": res_b, "true_residual_W": res_w}
+    return out
+
+
 def gradient_timing(torch, bri, dev):
     """FP64 link gradient of S = Re<chi, D psi> at 16^3 x 32 (the gradient
     lattice), as the autograd Function runs it: forward = transporter build
@@ -639,6 +687,7 @@ def main():
     if not a.no_extras:
         res["variants_16x16x16x32"] = variants_16_32(torch, bri, dev)
         res["gradient_16x16x16x32"] = gradient_timing(torch, bri, dev)
+        res["wilson_vs_brillouin_cgne_16x16x16x32"] = wilson_brillouin_iterations(torch, bri, dev)
     if not a.no_extras and not a.no_solve:
         res["solve_24x24x24x48"] = solve_24x48(torch, bri, dev)
     if not a.no_extras and not a.no_solve:
