@@ -45,70 +45,17 @@ __device__ __forceinline__ void bdag_mul(int mu, cx<A> u0, cx<A> u1, cx<A> &o2, 
     else { o2 = u0; o3 = u1; }
 }
 
-// acc += -1/2 (1 - s gamma_mu) W psi(y) for hop = 2 mu + (0: forward, 1:
-// backward): W = U_mu(x), y = x + mu for the forward hop, W = U_mu(x-mu)^dag,
-// y = x - mu for the backward one; s = +1 forward, -1 backward (negated for
-// D^dag).  Everything lane-dependent is computed from the run-time hop, so
-// the compiler cannot hoist the addresses of all eight hops out of the loop.
-template <bool DAG, typename T, typename A>
-__device__ __forceinline__ void wilson_hop(int hop, const Geom &g, const int c[4], int site, size_t V,
-                                           const T *__restrict__ U, const T *__restrict__ q,
-                                           cx<A> (&acc)[4][3]) {
-    const int mu = hop >> 1;
-    const bool fwd = (hop & 1) == 0;
-    const int L = g.L[mu], str = g.stride[mu];
-    const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
-    const int y = fwd ? (cm == L - 1 ? site - (L - 1) * str : site + str)
-                      : (cm == 0 ? site + (L - 1) * str : site - str);
-    const A s = (fwd != DAG) ? (A)1 : (A)-1;
-    const T *qy = q + y;
-    cx<A> h[2][3];
+template <typename T, typename A>
+__device__ __forceinline__ void load_spinor(const T *__restrict__ p, size_t V, cx<A> (&v)[4][3]) {
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const cx<A> u0 = ldc<A>(qy + (size_t)(0 + b) * V), u1 = ldc<A>(qy + (size_t)(3 + b) * V);
-        const cx<A> l0 = ldc<A>(qy + (size_t)(6 + b) * V), l1 = ldc<A>(qy + (size_t)(9 + b) * V);
-        cx<A> t0, t1;
-        b_mul(mu, l0, l1, t0, t1);
-        h[0][b] = caxpy(-s, t0, u0);
-        h[1][b] = caxpy(-s, t1, u1);
-    }
-    const T *p = U + (size_t)mu * 9 * V + (fwd ? site : y);
-    cx<A> w[3][3];
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + (size_t)e * V);
-    const A half = (A)0.5;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cx<A> y0, y1;
-        if (fwd) {
-            y0 = cmul(w[a][0], h[0][0]);
-            y1 = cmul(w[a][0], h[1][0]);
-#pragma unroll
-            for (int b = 1; b < 3; ++b) {
-                y0 = cmac(y0, w[a][b], h[0][b]);
-                y1 = cmac(y1, w[a][b], h[1][b]);
-            }
-        } else {
-            y0 = cmul(cconj(w[0][a]), h[0][0]);
-            y1 = cmul(cconj(w[0][a]), h[1][0]);
-#pragma unroll
-            for (int b = 1; b < 3; ++b) {
-                y0 = cmacc(y0, w[b][a], h[0][b]);
-                y1 = cmacc(y1, w[b][a], h[1][b]);
-            }
-        }
-        acc[0][a] = caxpy(-half, y0, acc[0][a]);
-        acc[1][a] = caxpy(-half, y1, acc[1][a]);
-        cx<A> t2, t3;
-        bdag_mul(mu, y0, y1, t2, t3);
-        acc[2][a] = caxpy(half * s, t2, acc[2][a]);
-        acc[3][a] = caxpy(half * s, t3, acc[3][a]);
-    }
+        for (int a = 0; a < 3; ++a) v[s][a] = ldc<A>(p + (size_t)(3 * s + a) * V);
 }
 
 // acc += -1/2 (1 - s gamma_mu) W v with v the neighbour spinor and W the
 // link (forward hop) or its adjoint taken here (backward hop), both in
-// registers; the same arithmetic as wilson_hop.
+// registers; s = +1 forward, -1 backward (negated for D^dag).
 template <bool DAG, typename A>
 __device__ __forceinline__ void hop_core(int mu, bool fwd, const cx<A> (&v)[4][3], const cx<A> (&w)[3][3],
                                          cx<A> (&acc)[4][3]) {
@@ -151,6 +98,28 @@ __device__ __forceinline__ void hop_core(int mu, bool fwd, const cx<A> (&v)[4][3
     }
 }
 
+// The hop 2 mu + (0: forward, 1: backward) of one site with its operands
+// from memory: W = U_mu(x), y = x + mu forward, W = U_mu(x-mu)^dag, y = x - mu
+// backward.  Everything lane-dependent is computed from the run-time hop, so
+// the compiler cannot hoist the addresses of all the hops out of the loop.
+template <bool DAG, typename T, typename A>
+__device__ __forceinline__ void wilson_hop(int hop, const Geom &g, const int c[4], int site, size_t V,
+                                           const T *__restrict__ U, const T *__restrict__ q,
+                                           cx<A> (&acc)[4][3]) {
+    const int mu = hop >> 1;
+    const bool fwd = (hop & 1) == 0;
+    const int L = g.L[mu], str = g.stride[mu];
+    const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
+    const int y = fwd ? (cm == L - 1 ? site - (L - 1) * str : site + str)
+                      : (cm == 0 ? site + (L - 1) * str : site - str);
+    cx<A> v[4][3], w[3][3];
+    load_spinor(q + y, V, v);
+    const T *p = U + (size_t)mu * 9 * V + (fwd ? site : y);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + (size_t)e * V);
+    hop_core<DAG>(mu, fwd, v, w, acc);
+}
+
 // The t hops from registers: U_mu(x - t)^dag h with h the backward projection
 // of psi(x - t) is what the forward t hop of the site below has at hand (its
 // link and its spinor), so a thread owns one (x, y, z) and walks a chunk of t
@@ -158,13 +127,6 @@ __device__ __forceinline__ void hop_core(int mu, bool fwd, const cx<A> (&v)[4][3
 // to the next step.  The x, y and z hops read their neighbours through the
 // caches (the threads of those neighbours read the same data at about the
 // same step).
-template <typename T, typename A>
-__device__ __forceinline__ void load_spinor(const T *__restrict__ p, size_t V, cx<A> (&v)[4][3]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) v[s][a] = ldc<A>(p + (size_t)(3 * s + a) * V);
-}
 
 // (1 - s gamma_t) psi has upper part h = psi_u - s psi_l (B_t = 1)
 template <typename A>
