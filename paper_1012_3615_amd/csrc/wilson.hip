@@ -243,15 +243,18 @@ __global__ __launch_bounds__(256) void k_wilson(Geom g, const T *__restrict__ U,
 // there instead of fetching them again through the caches.
 constexpr int WTX = 32, WTY = 8, WHALO = 2 * WTX + 2 * WTY;
 
-template <typename T, typename A, bool DAG>
-__global__ __launch_bounds__(256) void k_wilson_tile(Geom g, const T *__restrict__ U, const T *__restrict__ in,
-                                                     T *__restrict__ out, A diag, int tchunk) {
-    __shared__ cx<A> lds[12][WTY + 2][WTX + 2];
+template <typename T, typename A, bool DAG, int WTZ>
+__global__ __launch_bounds__(256 * WTZ) void k_wilson_tile(Geom g, const T *__restrict__ U,
+                                                           const T *__restrict__ in, T *__restrict__ out, A diag,
+                                                           int tchunk) {
+    __shared__ cx<A> lds_all[WTZ][12][WTY + 2][WTX + 2];
     const int lx = g.L[0], ly = g.L[1], lt = g.L[3];
     const int ntx = lx / WTX, nty = ly / WTY;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
-    const int x0 = (tile % ntx) * WTX, y0 = ((tile / ntx) % nty) * WTY, z = tile / (ntx * nty);
-    const int tx = threadIdx.x % WTX, ty = threadIdx.x / WTX;
+    const int tz = threadIdx.x / 256, tid = threadIdx.x % 256;
+    const int x0 = (tile % ntx) * WTX, y0 = ((tile / ntx) % nty) * WTY, z = (tile / (ntx * nty)) * WTZ + tz;
+    const int tx = tid % WTX, ty = tid / WTX;
+    auto &lds = lds_all[tz];
     const int v3 = g.stride[3];
     const int s3 = (x0 + tx) + lx * ((y0 + ty) + ly * z);
     const int t0 = blockIdx.y * tchunk;
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(256) void k_wilson_tile(Geom g, const T *__restrict
         __syncthreads();  // the previous step's readers of the tile are done
 #pragma unroll
         for (int c = 0; c < 12; ++c) lds[c][ty + 1][tx + 1] = cur[c / 3][c % 3];
-        for (int i = threadIdx.x; i < 12 * WHALO; i += 256) {
+        for (int i = tid; i < 12 * WHALO; i += 256) {
             const int c = i / WHALO, h = i % WHALO;
             int hx, hy;
             if (h < WTX) { hx = h + 1; hy = 0; }
@@ -319,8 +322,23 @@ __global__ __launch_bounds__(256) void k_wilson_tile(Geom g, const T *__restrict
             for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + (size_t)e * V);
             hop_core<DAG>(mu, fwd, v, w, acc);
         }
+        // z hops: with two slices per workgroup the neighbour inside it
+        // comes from the other slice's LDS tile
 #pragma unroll 1
-        for (int hop = 4; hop < 6; ++hop) wilson_hop<DAG>(hop, g, c4, site, V, U, q, acc);
+        for (int hop = 4; hop < 6; ++hop) {
+            const bool fwd = hop == 4;
+            if (WTZ == 2 && (fwd ? tz == 0 : tz == 1)) {
+                cx<A> v[4][3], w[3][3];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) v[c / 3][c % 3] = lds_all[1 - tz][c][ty + 1][tx + 1];
+                const T *p = U + (size_t)2 * 9 * V + (fwd ? site : site - g.stride[2]);
+#pragma unroll
+                for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = ld<A>(p + (size_t)e * V);
+                hop_core<DAG>(2, fwd, v, w, acc);
+            } else {
+                wilson_hop<DAG>(hop, g, c4, site, V, U, q, acc);
+            }
+        }
         const int sn = s3 + (t == lt - 1 ? 0 : t + 1) * v3;
         load_spinor(q + sn, V, cur);
         cx<A> w[3][3], h[2][3], y[2][3];
@@ -357,13 +375,24 @@ hipError_t launch(const Geom &g, const void *U, const void *in, void *out, doubl
     while (tchunk > 1 && (long long)((v3 + 255) / 256) * ((lt + tchunk - 1) / tchunk) * nrhs < 1024) tchunk /= 2;
     const dim3 grid((v3 + 255) / 256, (lt + tchunk - 1) / tchunk, nrhs), block(256);
     if (g.L[0] % WTX == 0 && g.L[1] % WTY == 0) {
+        if (g.L[2] % 2 == 0) {
+            // v3 / 512 workgroups of two 32 x 8 tiles at z and z + 1
+            const dim3 grid2(v3 / 512, grid.y, grid.z), block2(512);
+            if (dag)
+                k_wilson_tile<T, A, true, 2><<<grid2, block2, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out,
+                                                                       (A)diag, tchunk);
+            else
+                k_wilson_tile<T, A, false, 2><<<grid2, block2, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out,
+                                                                        (A)diag, tchunk);
+            return hipGetLastError();
+        }
         // v3 / 256 tiles of 32 x 8 sites, the same grid
         if (dag)
-            k_wilson_tile<T, A, true><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag,
-                                                              tchunk);
+            k_wilson_tile<T, A, true, 1><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag,
+                                                                 tchunk);
         else
-            k_wilson_tile<T, A, false><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag,
-                                                               tchunk);
+            k_wilson_tile<T, A, false, 1><<<grid, block, 0, st>>>(g, (const T *)U, (const T *)in, (T *)out, (A)diag,
+                                                                  tchunk);
         return hipGetLastError();
     }
     if (dag)

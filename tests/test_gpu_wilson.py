@@ -31,9 +31,10 @@ def bri():
 # L = 2 in a direction (forward and backward neighbour coincide), odd
 # extents, a volume that is not a multiple of the 256-site workgroup; Lx a
 # multiple of 32 and Ly of 8 take the LDS-tiled kernel (one tile in y, so
-# the y halo wraps onto the tile itself; two tiles in x and y)
+# the y halo wraps onto the tile itself; two tiles in x and y), with two z
+# slices per workgroup where Lz is even and one where it is odd
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 5, 3, 4), (2, 3, 2, 5), (16, 6, 2, 2), (32, 8, 2, 3),
-                                  (64, 16, 2, 2)])
+                                  (64, 16, 2, 2), (32, 8, 3, 2)])
 def test_wilson_matches_oracle(bri, dims):
     mass = 0.1
     u = synth.gauge_links(dims, 0.4, 8701)
