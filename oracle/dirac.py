@@ -87,6 +87,27 @@ def apply_dag(U, psi, mass):
     return out
 
 
+def apply_dag_at(U, psi, mass, sites):
+    """(D^dag psi)(x) only at the sampled sites (N, 4) = (x, y, z, t), from
+    D^dag(x,y) = D(y,x)^dag: the term of offset n is C(n)^dag W(x-n, x)^dag
+    psi(x-n), with W(x-n, x) enumerated from the links around x-n.  Returns
+    shape (N, 4, 3)."""
+    dims = (psi.shape[3], psi.shape[2], psi.shape[1], psi.shape[0])
+    get = make_site_getter(sites, dims)
+    lam, rho = operator_weights(mass)
+    out = np.conj(lam[(0, 0, 0, 0)]) * get(psi, (0, 0, 0, 0))
+    for n in all_offsets():
+        back = tuple(-v for v in n)
+
+        def get_back(field, d, back=back):
+            return get(field, tuple(d[mu] + back[mu] for mu in range(4)))
+
+        w_from = transporter(U, n, get_back)  # W(x-n, x) at every sampled x
+        cd = dag(coefficient_matrix(lam, rho, n))
+        out = out + _spin(cd, _colour(dag(w_from), get(psi, back)))
+    return out
+
+
 def apply_gamma5_sandwich(U, psi, mass):
     """gamma5 D gamma5 psi (used to check gamma5-hermiticity, Sec. 1)."""
     g5 = gamma5()

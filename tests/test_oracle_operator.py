@@ -181,3 +181,16 @@ def test_pointwise_apply_matches_whole_lattice(links_small):
     pt = dirac.apply_at(links_small, psi, MASS, sites)
     for i, (x, y, z, t) in enumerate(sites):
         assert np.allclose(pt[i], full[t, z, y, x], atol=1e-13)
+
+
+def test_pointwise_apply_dag_matches_whole_lattice(links_small):
+    """The sampled-site D^dag (from D(y,x)^dag, links around x - n) equals the
+    whole-lattice D^dag, which the gamma5-hermiticity pin ties to D."""
+    psi = synth.gaussian_spinor(DIMS_SMALL, seed=22)
+    full = dirac.apply_dag(links_small, psi, MASS)
+    sites = np.array([[0, 0, 0, 0], [2, 1, 0, 2], [1, 2, 2, 1], [2, 2, 2, 2], [0, 2, 1, 2]])
+    pt = dirac.apply_dag_at(links_small, psi, MASS, sites)
+    for i, (x, y, z, t) in enumerate(sites):
+        assert np.allclose(pt[i], full[t, z, y, x], atol=1e-13)
+    # and it is not the sampled D: the two differ on random links
+    assert not np.allclose(pt, dirac.apply_at(links_small, psi, MASS, sites), atol=1e-3)
