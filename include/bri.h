@@ -82,10 +82,11 @@ typedef enum {
 /* Message for the last failing call on this thread ("" if none). */
 const char *bri_last_error(void);
 /* ABI revision of this header (incremented on incompatible change; 3 added
- * the coefficient table to bri_operator and to the gradient calls).  bri_abi_version() returns the
+ * the coefficient table to bri_operator and to the gradient calls, 5
+ * replaced the per-precision kernel choice by per-shape configurations).  bri_abi_version() returns the
  * revision the library was built with; a caller compares it to
  * BRI_ABI_VERSION. */
-#define BRI_ABI_VERSION 4
+#define BRI_ABI_VERSION 5
 int32_t bri_abi_version(void);
 
 /* ---- sizes (bytes) of the SoA buffers ----------------------------------- */
@@ -152,38 +153,49 @@ bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W_or_U, bri_prec
 bri_status bri_apply_wilson(bri_dims d, const void *U_soa, bri_prec prec, double mass, const void *in,
                             void *out, int32_t nrhs, int32_t dagger, void *stream);
 
-/* Choose the number of right-hand sides held per thread in the fused
- * multi-RHS apply (1, 2, 3, 4, 6 or 12; 0 restores the built-in default of 2)
- * for the given precisions.  Used by the autotuner; host-side state, not
- * thread-safe against concurrent applies. */
-bri_status bri_set_rhs_block(bri_prec w_prec, bri_prec s_prec, int32_t rhs_per_thread);
-int32_t bri_get_rhs_block(bri_prec w_prec, bri_prec s_prec);
-
-/* Choose the stored-variant kernel for the given precisions.  Codes:
- *   1  LDS tiles, shape chosen from Lx (default): each workgroup stages the
- *      spinor of its x-y tile plus a one-site halo layer by layer in LDS;
- *      for Lx > 16 a 32x8 tile (24x8 or 48x4 when Lx is a multiple of 24 or
- *      48 but not of 32; 32x16 for FP32 or FP64 transporters (80 offsets)
- *      with spinors of the same precision, one right-hand side per thread,
- *      when Lx is a multiple of 32 and Ly of 16) with the
- *      next transporter prefetched and each layer's offsets unrolled; for
- *      Lx <= 16 a 16x16 tile (one right-hand side per thread; 16x4 with
- *      unrolled offsets for FP32 when Lx = 16) or 16x8 (several);
+/* Launch configuration of the stored apply, per shape.  A shape is
+ * (extents, w_prec, s_prec, n_offsets, nrhs).  Kernel codes:
+ *   1  built-in selection (the default for every shape): LDS tiles whose
+ *      shape follows Lx; each workgroup stages the spinor of its x-y tile
+ *      plus a one-site halo layer by layer in LDS.  For Lx > 16 a 32x8 tile
+ *      (24x8 or 48x4 when Lx is a multiple of 24 or 48 but not of 32; 32x16
+ *      for FP32 or FP64 transporters (80 offsets) with spinors of the same
+ *      precision and one right-hand side, when Lx is a multiple of 32 and Ly
+ *      of 16) with the next transporter prefetched and each layer's offsets
+ *      unrolled; for Lx <= 16 a 16x16 tile (one right-hand side per thread;
+ *      16x4 with unrolled offsets for FP32 when Lx = 16) or 16x8 (several);
  *   2..5   LDS tiles of 32x8, 16x16, 64x4 or 16x8 sites;
  *   6, 7   tiles 32x8, 16x16 with transporter prefetch;
  *   8      tile 32x8 with prefetch and each layer's offsets unrolled;
  *   9, 10  tiles 32x8, 16x8 with the offsets unrolled, no prefetch;
- *   11, 12 tiles 24x8, 48x4 with prefetch and unrolled offsets (chosen by
- *          code 1 when Lx is a multiple of 24 or 48 but not of 32);
+ *   11, 12 tiles 24x8, 48x4 with prefetch and unrolled offsets;
  *   13, 14 tiles 32x16, 16x4 with prefetch and unrolled offsets, one
  *          right-hand side per thread;
  *   0      direct neighbour gathers through the caches.
- * A tile kernel holds 1-4 right-hand sides per thread (bri_set_rhs_block,
- * clamped to what the shape supports).  All add the 81 terms of a site in
- * the same order (offset index 0..80), so their results agree bit for bit.
- * Host-side state, not thread-safe against concurrent applies. */
-bri_status bri_set_apply_kernel(bri_prec w_prec, bri_prec s_prec, int32_t kernel);
-int32_t bri_get_apply_kernel(bri_prec w_prec, bri_prec s_prec);
+ * rhs_per_thread (1, 2, 3, 4, 6 or 12; the built-in value is 2) is clamped to
+ * what the kernel holds: tiles 1-4 right-hand sides per thread (16x16, 64x4,
+ * 32x16, 16x4: 1; 32x8, 24x8 and 48x4 with prefetch: 1, 2), the gather form
+ * any of the six values.  All kernels add the 81 terms of a site in the same
+ * order (offset index 0..80), so their results agree bit for bit.
+ *
+ * bri_set_apply_config installs (kernel, rhs_per_thread) for exactly the
+ * given shape: every later apply of that shape (bri_apply, bri_apply_dag,
+ * bri_apply_op without the two-row form or clover term, and the applies
+ * inside the solver, Lanczos and the sign function) launches it, and every
+ * other shape keeps its own entry or the built-in selection.  kernel = -1
+ * removes the entry.  At most 256 shapes carry an entry (BRI_E_ARG beyond).
+ * The table is host-side library state shared by all threads, guarded by a
+ * lock.  This is what the autotuner (paper_1012_3615_amd/autotune.py) uses. */
+bri_status bri_set_apply_config(bri_dims d, bri_prec w_prec, bri_prec s_prec, int32_t n_offsets, int32_t nrhs,
+                                int32_t kernel, int32_t rhs_per_thread);
+/* The configuration an apply of this shape launches: the kernel code (code 1
+ * resolved to the tile it picks, so never 1) and the right-hand sides per
+ * thread after clamping.  Outputs are host pointers. */
+bri_status bri_get_apply_config(bri_dims d, bri_prec w_prec, bri_prec s_prec, int32_t n_offsets, int32_t nrhs,
+                                int32_t *kernel, int32_t *rhs_per_thread);
+/* Remove every installed configuration (all shapes back to the built-in
+ * selection). */
+void bri_clear_apply_configs(void);
 
 /* ---- solver: CG on the normal equations D^dag D x = D^dag b ----------------
  * The paper inverts D for propagators (Sec. 6.4, BiCGstab to 1e-7); here the

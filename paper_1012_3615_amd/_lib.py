@@ -40,7 +40,7 @@ class bri_solve_stats(ctypes.Structure):
 
 
 # BRI_ABI_VERSION of include/bri.h that the structures below mirror
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class bri_operator(ctypes.Structure):
@@ -76,10 +76,9 @@ PROTOTYPES = {
     "bri_apply": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
     "bri_apply_dag": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
     "bri_apply_wilson": (_i32, [_D, _vp, _i32, _dbl, _vp, _vp, _i32, _i32, _vp]),
-    "bri_set_rhs_block": (_i32, [_i32, _i32, _i32]),
-    "bri_get_rhs_block": (_i32, [_i32, _i32]),
-    "bri_set_apply_kernel": (_i32, [_i32, _i32, _i32]),
-    "bri_get_apply_kernel": (_i32, [_i32, _i32]),
+    "bri_set_apply_config": (_i32, [_D, _i32, _i32, _i32, _i32, _i32, _i32]),
+    "bri_get_apply_config": (_i32, [_D, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "bri_clear_apply_configs": (None, []),
     "bri_solve_workspace_bytes": (_sz, [_D, ctypes.POINTER(bri_solve_params), _i32]),
     "bri_solve_cgne": (_i32, [_D, ctypes.POINTER(bri_solve_params), _vp, _vp, _dbl, _vp, _vp,
                               _i32, _vp, _sz, ctypes.POINTER(bri_solve_stats), _vp]),

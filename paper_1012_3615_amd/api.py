@@ -204,20 +204,24 @@ def bri_apply_wilson(dims, U, psi, mass, dagger=False, out=None):
     return out
 
 
-def bri_set_rhs_block(w_prec, s_prec, rhs_per_thread):
-    _check(_lib_handle.bri_set_rhs_block(w_prec, s_prec, rhs_per_thread), "bri_set_rhs_block")
+def bri_set_apply_config(dims, w_prec, s_prec, n_offsets, nrhs, kernel, rhs_per_thread=2):
+    """Install (kernel, rhs_per_thread) for applies of exactly this shape;
+    kernel = -1 removes the entry (the shape returns to the built-in choice)."""
+    _check(_lib_handle.bri_set_apply_config(_dims(dims), w_prec, s_prec, n_offsets, nrhs, kernel,
+                                            rhs_per_thread), "bri_set_apply_config")
 
 
-def bri_get_rhs_block(w_prec, s_prec):
-    return _lib_handle.bri_get_rhs_block(w_prec, s_prec)
+def bri_get_apply_config(dims, w_prec, s_prec, n_offsets, nrhs):
+    """(kernel code, right-hand sides per thread) that an apply of this shape
+    launches (the built-in code 1 resolved to its tile)."""
+    k, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib_handle.bri_get_apply_config(_dims(dims), w_prec, s_prec, n_offsets, nrhs, ctypes.byref(k),
+                                            ctypes.byref(r)), "bri_get_apply_config")
+    return k.value, r.value
 
 
-def bri_set_apply_kernel(w_prec, s_prec, kernel):
-    _check(_lib_handle.bri_set_apply_kernel(w_prec, s_prec, kernel), "bri_set_apply_kernel")
-
-
-def bri_get_apply_kernel(w_prec, s_prec):
-    return _lib_handle.bri_get_apply_kernel(w_prec, s_prec)
+def bri_clear_apply_configs():
+    _lib_handle.bri_clear_apply_configs()
 
 
 # ------------------------------------------------------------------ solver

@@ -2,25 +2,26 @@
 
 For a lattice, precision pair, transporter store and number of right-hand
 sides it times every launch configuration the library offers (LDS tiles of
-32x8 or 16x8 sites with 1-4 right-hand sides per thread, tiles of 16x16 or
-64x4 sites with one, or the register-blocked gather form with 1, 2, 3, 4, 6
-or 12 right-hand sides per thread)
-with HIP events on the current stream, installs the fastest through
-bri_set_apply_kernel / bri_set_rhs_block, and caches the choice in a JSON
-file keyed by (extents, w_prec, s_prec, n_offsets, nrhs, device name).
+32x8 or 16x8 sites with 1-4 right-hand sides per thread, tiles of 16x16,
+64x4, 32x16 or 16x4 sites with one, or the register-blocked gather form with
+1, 2, 3, 4, 6 or 12 right-hand sides per thread) with HIP events on the
+current stream, and installs the fastest through bri_set_apply_config for
+exactly that shape (extents, w_prec, s_prec, n_offsets, nrhs): applies of
+every other shape keep their own choice or the built-in one.
 
-The installed choice is library state per precision pair, not per shape: it
-governs every later apply with those precisions, whatever the lattice or
-number of right-hand sides, until reset() restores the built-in selection.
+Choices are cached in a JSON file keyed by the shape, the device name and a
+hash of the library file, so an entry timed against another build of the
+kernels is never installed without being re-timed.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
 import torch
 
-from . import api
+from . import _lib, api
 
 CACHE = os.environ.get("BRI_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "bri_autotune.json"))
@@ -33,10 +34,25 @@ TILE_RBLK = {2: (1, 2, 3, 4), 3: (1,), 4: (1,), 5: (1, 2, 3, 4), 6: (1, 2), 7: (
              9: (1, 2, 3), 10: (2, 3, 4), 11: (1, 2), 12: (1, 2), 13: (1,), 14: (1,)}
 RBLKS = (1, 2, 3, 4, 6, 12)
 
+_lib_digest = None
+
+
+def library_digest():
+    """sha256 (first 16 hex digits) of the loaded libbri.so and its ABI revision."""
+    global _lib_digest
+    if _lib_digest is None:
+        h = hashlib.sha256()
+        with open(_lib.LIB_PATH, "rb") as f:
+            for chunk in iter(lambda: f.read(1 << 22), b""):
+                h.update(chunk)
+        _lib_digest = f"abi{_lib.ABI_VERSION}-{h.hexdigest()[:16]}"
+    return _lib_digest
+
 
 def _key(dims, w_prec, s_prec, n_offsets, nrhs):
     dev = torch.cuda.get_device_name()
-    return f"{'x'.join(map(str, dims))}|w{w_prec}|s{s_prec}|o{n_offsets}|r{nrhs}|{dev}"
+    return (f"{'x'.join(map(str, dims))}|w{w_prec}|s{s_prec}|o{n_offsets}|r{nrhs}|{dev}|"
+            f"{library_digest()}")
 
 
 def _load():
@@ -74,34 +90,32 @@ def candidates(dims, nrhs, s_prec=api.F32):
     return out
 
 
-def _install(w_prec, s_prec, kernel, rblk):
-    api.bri_set_apply_kernel(w_prec, s_prec, kernel)
-    api.bri_set_rhs_block(w_prec, s_prec, rblk)
+def install(dims, w_prec, s_prec, n_offsets, nrhs, kernel, rblk):
+    api.bri_set_apply_config(dims, w_prec, s_prec, n_offsets, nrhs, kernel, rblk)
 
 
-def reset(w_prec, s_prec):
-    """Restore the built-in selection (kernel code 1, two right-hand sides
-    per thread where the tile holds several) for one precision pair."""
-    _install(w_prec, s_prec, 1, 0)
+def reset(dims, w_prec, s_prec, n_offsets, nrhs):
+    """Return one shape to the built-in selection."""
+    api.bri_set_apply_config(dims, w_prec, s_prec, n_offsets, nrhs, -1, 0)
 
 
 def tune(dims, W, psi, mass=0.1, reps=5, use_cache=True):
-    """Pick and install the fastest configuration for apply(W, psi); it stays
-    installed for the precision pair of (W, psi) until reset().
-    Returns (name, ms, table of all timings)."""
+    """Pick and install the fastest configuration for apply(W, psi), for this
+    shape only.  Returns (name, ms, table of all timings, from_cache); with a
+    cached entry nothing is timed and the table is the one stored with it."""
     w_prec, s_prec = api.prec_of(W), api.prec_of(psi)
     n_off, nrhs = W.shape[0], psi.shape[0]
     key = _key(dims, w_prec, s_prec, n_off, nrhs)
     cache = _load() if use_cache else {}
     if key in cache:
         e = cache[key]
-        _install(w_prec, s_prec, e["kernel"], e["rblk"])
-        return e["name"], e["ms"], e.get("table", {})
+        install(dims, w_prec, s_prec, n_off, nrhs, e["kernel"], e["rblk"])
+        return e["name"], e["ms"], e.get("table", {}), True
     out = torch.empty_like(psi)
     table = {}
     best = None
     for name, kernel, rblk in candidates(dims, nrhs, s_prec):
-        _install(w_prec, s_prec, kernel, rblk)
+        install(dims, w_prec, s_prec, n_off, nrhs, kernel, rblk)
         api.bri_apply(dims, W, psi, mass, out=out)
         torch.cuda.synchronize()
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -115,8 +129,8 @@ def tune(dims, W, psi, mass=0.1, reps=5, use_cache=True):
         if best is None or ms < best[3]:
             best = (name, kernel, rblk, ms)
     name, kernel, rblk, ms = best
-    _install(w_prec, s_prec, kernel, rblk)
-    cache[key] = {"name": name, "kernel": kernel, "rblk": rblk, "ms": ms, "table": table}
+    install(dims, w_prec, s_prec, n_off, nrhs, kernel, rblk)
     if use_cache:
+        cache[key] = {"name": name, "kernel": kernel, "rblk": rblk, "ms": ms, "table": table}
         _store(cache)
-    return name, ms, table
+    return name, ms, table, False

@@ -2,7 +2,9 @@
 // argument validation, precision dispatch and error reporting.
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/bri.h"
 #include "common.h"
@@ -51,12 +53,22 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 }
 
 namespace {
-// rhs-per-thread setting of the fused multi-RHS apply, per (w_prec, s_prec)
-int g_rhs_block[3][3] = {{2, 2, 2}, {2, 2, 2}, {2, 2, 2}};
-// apply kernel per (w_prec, s_prec): 0 = register-blocked gather, 1 = LDS tiles
-// with the tile shape chosen from Lx, 2..5 = LDS tiles 32x8, 16x16, 64x4, 16x8,
-// 6, 7 = tiles 32x8, 16x16 with transporter prefetch
-int g_apply_kernel[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};
+// Launch configurations installed for particular shapes (the autotuner's
+// choices).  A shape is (extents, w_prec, s_prec, n_offsets, nrhs); an apply
+// of any other shape takes the built-in selection.  Guarded by a mutex: an
+// apply looks its shape up once per call.
+struct ApplyConfig {
+    int32_t L[4];
+    int wp, sp, noff, nrhs, kernel, rblk;
+};
+constexpr size_t kMaxConfigs = 256;
+std::mutex g_cfg_mu;
+std::vector<ApplyConfig> g_cfg;
+
+bool same_shape(const ApplyConfig &c, const Geom &g, int wp, int sp, int noff, int nrhs) {
+    return c.L[0] == g.L[0] && c.L[1] == g.L[1] && c.L[2] == g.L[2] && c.L[3] == g.L[3] && c.wp == wp &&
+           c.sp == sp && c.noff == noff && c.nrhs == nrhs;
+}
 
 int snap_rblk(int want, int nrhs) {
     static const int allowed[] = {12, 6, 4, 3, 2, 1};  // snapped down to one of these
@@ -66,6 +78,59 @@ int snap_rblk(int want, int nrhs) {
     return 1;
 }
 }  // namespace
+
+// The kernel code (never 1) and right-hand sides per thread that an apply of
+// this shape launches, from the requested code and blocking (code 1 and
+// blocking 2 are the built-in selection).
+void resolve_apply_config(const Geom &g, int wp, int sp, int noff, int nrhs, int kernel, int want_rblk,
+                          int *kernel_out, int *rblk_out) {
+    int rblk = nrhs == 1 ? 1 : snap_rblk(want_rblk, nrhs);
+    if (kernel >= 1) {
+        // LDS tiles hold 1..4 right-hand sides per thread (shapes 16x16, 64x4: 1)
+        if (kernel == 3 || kernel == 4 || kernel == 7 || kernel == 13 || kernel == 14) rblk = 1;
+        if ((kernel == 6 || kernel == 8 || kernel == 11 || kernel == 12) && rblk > 2) rblk = 2;
+        if (kernel == 9 && rblk > 3) rblk = 3;
+        if (kernel == 10 && rblk < 2) rblk = 2;
+        if (rblk > 4) rblk = 4;
+        if (wp == BRI_F64 && rblk > 2 && kernel != 5 && kernel != 10 && !(kernel == 1 && g.L[0] <= 16))
+            rblk = 2;  // LDS of a 32x8 tile
+    }
+    if (kernel == 1) {
+        // built-in shapes: transporter prefetch where it is instantiated; the
+        // tile width follows Lx so that no lanes idle (24 and 48 wide tiles
+        // for extents that are multiples of those but not of 32)
+        const int lx = g.L[0];
+        if (lx == 16 && rblk == 1 && wp == BRI_F32 && sp == BRI_F32)
+            kernel = 14;  // 16x4 with unrolled offsets: four times the workgroups of 16x16 on small lattices
+        else if (lx <= 16)
+            kernel = rblk == 1 ? 7 : 10;
+        else if (rblk <= 2 && lx % 32 != 0 && lx % 48 == 0)
+            kernel = 12;
+        else if (rblk <= 2 && lx % 32 != 0 && lx % 24 == 0)
+            kernel = 11;
+        else if (noff == 80 && wp == sp && wp != BRI_F16 && rblk == 1 && lx % 32 == 0 && g.L[1] % 16 == 0)
+            kernel = 13;  // 32x16 (halo 1.2x a tile's sites instead of 1.33x): faster for FP32 and FP64 W80
+        else
+            kernel = rblk <= 2 ? 8 : rblk == 3 ? 9 : 2;
+    }
+    *kernel_out = kernel;
+    *rblk_out = rblk;
+}
+
+// the configuration installed for this shape, else the built-in one
+void lookup_apply_config(const Geom &g, int wp, int sp, int noff, int nrhs, int *kernel, int *rblk) {
+    int k = 1, r = 2;
+    {
+        std::lock_guard<std::mutex> lock(g_cfg_mu);
+        for (const ApplyConfig &c : g_cfg)
+            if (same_shape(c, g, wp, sp, noff, nrhs)) {
+                k = c.kernel;
+                r = c.rblk;
+                break;
+            }
+    }
+    resolve_apply_config(g, wp, sp, noff, nrhs, k, r, kernel, rblk);
+}
 
 bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int32_t noff,
                       bri_prec sp, double mass, const void *in, void *out, int32_t nrhs,
@@ -86,18 +151,8 @@ bri_status apply_impl(bri_dims d, bri_variant v, const void *W, bri_prec wp, int
         const bool combo = (wp == BRI_F64 && sp == BRI_F64) || (wp == BRI_F32 && sp == BRI_F32) ||
                            (wp == BRI_F16 && (sp == BRI_F32 || sp == BRI_F16));
         if (!combo) return fail(BRI_E_UNSUPPORTED, "unsupported (w_prec, s_prec) combination");
-        const int kernel = g_apply_kernel[wp][sp];
-        int rblk = nrhs == 1 ? 1 : snap_rblk(g_rhs_block[wp][sp], nrhs);
-        if (kernel >= 1) {
-            // LDS tiles hold 1..4 right-hand sides per thread (shapes 16x16, 64x4: 1)
-            if (kernel == 3 || kernel == 4 || kernel == 7 || kernel == 13 || kernel == 14) rblk = 1;
-            if ((kernel == 6 || kernel == 8 || kernel == 11 || kernel == 12) && rblk > 2) rblk = 2;
-            if (kernel == 9 && rblk > 3) rblk = 3;
-            if (kernel == 10 && rblk < 2) rblk = 2;
-            if (rblk > 4) rblk = 4;
-            if (wp == BRI_F64 && rblk > 2 && kernel != 5 && kernel != 10 && !(kernel == 1 && g.L[0] <= 16))
-                rblk = 2;  // LDS of a 32x8 tile
-        }
+        int kernel, rblk;
+        lookup_apply_config(g, (int)wp, (int)sp, noff, nrhs, &kernel, &rblk);
         return hip_check(apply_stored(g, noff, (int)wp, (int)sp, kernel, rblk, W, in, out, diag, nrhs,
                                       dag, st, table),
                          "apply (stored)");
@@ -238,32 +293,54 @@ bri_status bri_apply_wilson(bri_dims d, const void *U, bri_prec prec, double mas
                      "apply (Wilson)");
 }
 
-bri_status bri_set_rhs_block(bri_prec wp, bri_prec sp, int32_t r) {
+bri_status bri_set_apply_config(bri_dims d, bri_prec wp, bri_prec sp, int32_t noff, int32_t nrhs, int32_t kernel,
+                                int32_t rblk) {
     g_last_error.clear();
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    if (r == 0) r = 2;
-    if (r != 1 && r != 2 && r != 3 && r != 4 && r != 6 && r != 12)
+    if (noff != 40 && noff != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
+    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
+    if (kernel < -1 || kernel > 14) return fail(BRI_E_ARG, "kernel must be in 0..14 (or -1 to remove)");
+    if (kernel >= 0 && rblk != 1 && rblk != 2 && rblk != 3 && rblk != 4 && rblk != 6 && rblk != 12)
         return fail(BRI_E_ARG, "rhs_per_thread must be 1, 2, 3, 4, 6 or 12");
-    g_rhs_block[wp][sp] = r;
+    std::lock_guard<std::mutex> lock(g_cfg_mu);
+    for (size_t i = 0; i < g_cfg.size(); ++i)
+        if (same_shape(g_cfg[i], g, wp, sp, noff, nrhs)) {
+            if (kernel < 0) {
+                g_cfg.erase(g_cfg.begin() + (long)i);
+            } else {
+                g_cfg[i].kernel = kernel;
+                g_cfg[i].rblk = rblk;
+            }
+            return BRI_OK;
+        }
+    if (kernel < 0) return BRI_OK;
+    if (g_cfg.size() >= kMaxConfigs)
+        return fail(BRI_E_ARG, "at most %zu shapes can carry an installed configuration", kMaxConfigs);
+    g_cfg.push_back(ApplyConfig{{g.L[0], g.L[1], g.L[2], g.L[3]}, (int)wp, (int)sp, noff, nrhs, kernel, rblk});
     return BRI_OK;
 }
 
-bri_status bri_set_apply_kernel(bri_prec wp, bri_prec sp, int32_t kernel) {
+bri_status bri_get_apply_config(bri_dims d, bri_prec wp, bri_prec sp, int32_t noff, int32_t nrhs, int32_t *kernel,
+                                int32_t *rblk) {
     g_last_error.clear();
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
     if (!prec_ok(wp) || !prec_ok(sp)) return fail(BRI_E_ARG, "invalid precision");
-    if (kernel < 0 || kernel > 14) return fail(BRI_E_ARG, "kernel must be in 0..14");
-    g_apply_kernel[wp][sp] = kernel;
+    if (noff != 40 && noff != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
+    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
+    if (!kernel || !rblk) return fail(BRI_E_ARG, "null output pointer");
+    int k, r;
+    lookup_apply_config(g, (int)wp, (int)sp, noff, nrhs, &k, &r);
+    *kernel = k;
+    *rblk = r;
     return BRI_OK;
 }
 
-int32_t bri_get_apply_kernel(bri_prec wp, bri_prec sp) {
-    if (!prec_ok(wp) || !prec_ok(sp)) return -1;
-    return g_apply_kernel[wp][sp];
-}
-
-int32_t bri_get_rhs_block(bri_prec wp, bri_prec sp) {
-    if (!prec_ok(wp) || !prec_ok(sp)) return 0;
-    return g_rhs_block[wp][sp];
+void bri_clear_apply_configs(void) {
+    std::lock_guard<std::mutex> lock(g_cfg_mu);
+    g_cfg.clear();
 }
 
 }  // extern "C"

@@ -50,13 +50,13 @@ hipError_t gather(const Geom &g, const void *W, const void *in, void *out, doubl
     return hipGetLastError();
 }
 
-// kernel: 0 gather (rblk in 1,2,3,4,6,12); 1 tiles with the shape chosen from
-// Lx; 2..5 tiles 32x8, 16x16, 64x4, 16x8; 6, 7 tiles 32x8 and 16x16 with the
+// kernel: 0 gather (rblk in 1,2,3,4,6,12); 2..5 tiles 32x8, 16x16, 64x4, 16x8; 6, 7 tiles 32x8 and 16x16 with the
 // next transporter prefetched; 8 tile 32x8 with prefetch and the offsets of a
 // layer unrolled at compile time (rblk 1, 2); 9, 10 tiles 32x8 (rblk 1-3) and
 // 16x8 (rblk 2-4) with the offsets unrolled, no prefetch; 11, 12 tiles 24x8 and 48x4 with prefetch and
 // unrolled offsets (rblk 1, 2); 13, 14 tiles 32x16 and 16x4 with prefetch and unrolled offsets (rblk 1).  Tiles hold rblk in 1..4 right-hand sides per thread (16x16 and 64x4: 1;
-// 32x8, 24x8 and 48x4 with prefetch: 1, 2).
+// 32x8, 24x8 and 48x4 with prefetch: 1, 2).  The built-in choice (code 1)
+// is resolved to one of these on the host before the launch.
 template <int NOFF, typename WS, typename SS, typename A>
 hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void *in, void *out,
                   double diag, int nrhs, bool dag, hipStream_t st, const double *table) {
@@ -70,25 +70,6 @@ hipError_t stored(const Geom &g, int kernel, int rblk, const void *W, const void
             case 12: return gather<NOFF, WS, SS, A, 12>(g, W, in, out, diag, nrhs, dag, st, table);
             default: return hipErrorInvalidValue;
         }
-    }
-    if (kernel == 1) {
-        // default shapes: transporter prefetch where it is instantiated; the
-        // tile width follows Lx so that no lanes idle (24 and 48 wide tiles
-        // for extents that are multiples of those but not of 32)
-        const int lx = g.L[0];
-        if (lx == 16 && rblk == 1 && std::is_same<WS, float2>::value && std::is_same<SS, float2>::value)
-            kernel = 14;  // 16x4 with unrolled offsets: four times the workgroups of 16x16 on small lattices
-        else if (lx <= 16)
-            kernel = rblk == 1 ? 7 : 10;
-        else if (rblk <= 2 && lx % 32 != 0 && lx % 48 == 0)
-            kernel = 12;
-        else if (rblk <= 2 && lx % 32 != 0 && lx % 24 == 0)
-            kernel = 11;
-        else if (NOFF == 80 && std::is_same<WS, SS>::value && !std::is_same<WS, __half2>::value && rblk == 1 &&
-                 lx % 32 == 0 && g.L[1] % 16 == 0)
-            kernel = 13;  // 32x16 (halo 1.2x a tile's sites instead of 1.33x): faster for FP32 and FP64 W80
-        else
-            kernel = rblk <= 2 ? 8 : rblk == 3 ? 9 : 2;
     }
     switch (kernel * 16 + rblk) {
         case 2 * 16 + 1: return tiled<NOFF, WS, SS, A, 32, 8, 1>(g, W, in, out, diag, nrhs, dag, st, nullptr, table);

@@ -121,14 +121,11 @@ def run(dims, names, reps=3, mass=0.1):
         else:
             Wv = bri.bri_pack_links(dims, Ud, wp)
             byts = V * (36 * CB[wp] + nrhs * 2 * 12 * CB[sp])
-        old = (bri.bri_get_apply_kernel(wp, sp), bri.bri_get_rhs_block(wp, sp))
-        bri.bri_set_apply_kernel(wp, sp, kernel)
-        bri.bri_set_rhs_block(wp, sp, rblk)
+        bri.bri_set_apply_config(dims, wp, sp, noff, nrhs, kernel, rblk)
         y = torch.empty_like(x)
         fn = bri.bri_apply_dag if name.endswith("_dag") else bri.bri_apply
         ms = _time(lambda: fn(dims, Wv, x, mass, variant=variant, out=y), reps)
-        bri.bri_set_apply_kernel(wp, sp, old[0])
-        bri.bri_set_rhs_block(wp, sp, old[1])
+        bri.bri_set_apply_config(dims, wp, sp, noff, nrhs, -1, 0)
         out.append({"variant": name, "ms": ms, "alg_GBs": byts / ms / 1e6,
                     "nominal_TFs": 35376 * V * nrhs / ms / 1e9})
         del Wv, x, y

@@ -22,43 +22,52 @@ def test_all_configurations_bitwise_equal(dims, wp, sp, noff):
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     W = bri.bri_build_transporters(dims, U, wp, noff)
     x = bri.bri_pack_spinor(dims, dev(psi), sp)
-    old = (bri.bri_get_apply_kernel(wp, sp), bri.bri_get_rhs_block(wp, sp))
     outs = {}
     try:
-        for name, kernel, rblk in autotune.candidates(dims, 12, sp) + [("default", 1, 1)]:
+        for name, kernel, rblk in autotune.candidates(dims, 12, sp) + [("default", -1, 0)]:
             log(f"config {name} dims={dims} w={wp} s={sp} noff={noff}")
-            bri.bri_set_apply_kernel(wp, sp, kernel)
-            bri.bri_set_rhs_block(wp, sp, rblk)
+            bri.bri_set_apply_config(dims, wp, sp, noff, 12, kernel, rblk)
             outs[name] = (bri.bri_apply(dims, W, x, 0.1).cpu(), bri.bri_apply_dag(dims, W, x, 0.1).cpu())
     finally:
-        bri.bri_set_apply_kernel(wp, sp, old[0])
-        bri.bri_set_rhs_block(wp, sp, old[1])
+        bri.bri_clear_apply_configs()
     ref = outs["default"]
     for name, (o, od) in outs.items():
         assert torch.equal(o, ref[0]) and torch.equal(od, ref[1]), name
 
 
 def test_autotuner_installs_a_configuration(tmp_path, monkeypatch):
+    """A 12-RHS tune installs its choice for that shape only: a later 1-RHS
+    apply on the same lattice and precisions still launches its built-in
+    kernel (bit for bit the result from before the tune), with no reset."""
+    import torch
     import paper_1012_3615_amd as bri
     from paper_1012_3615_amd import autotune
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
-    dims = (8, 8, 8, 8)
+    bri.bri_clear_apply_configs()
+    dims = (32, 16, 4, 4)
     u = synth.gauge_links(dims, 0.3, 63)
     psi = synth.gaussian_spinor(dims, 64, nrhs=12)
-    log("autotune 8^4 12 rhs")
+    log("autotune 32x16x4x4 12 rhs")
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     W = bri.bri_build_transporters(dims, U, bri.F32, 80)
     x = bri.bri_pack_spinor(dims, dev(psi), bri.F32)
-    old = (bri.bri_get_apply_kernel(1, 1), bri.bri_get_rhs_block(1, 1))
+    x1 = x[3:4].contiguous()
+    builtin_1 = bri.bri_get_apply_config(dims, 1, 1, 80, 1)
+    assert builtin_1 == (13, 1)
+    before = bri.bri_apply(dims, W, x1, 0.1).clone()
     try:
-        name, ms, table = autotune.tune(dims, W, x)
-        assert name in table and ms == min(table.values())
+        name, ms, table, cached = autotune.tune(dims, W, x)
+        assert not cached and name in table and ms == min(table.values())
         again = autotune.tune(dims, W, x)          # served from the cache
-        assert again[0] == name
-        kernel = bri.bri_get_apply_kernel(1, 1)
-        assert name.startswith(autotune.TILES.get(kernel, "gather"))
-        autotune.reset(1, 1)
-        assert (bri.bri_get_apply_kernel(1, 1), bri.bri_get_rhs_block(1, 1)) == (1, 2)
+        assert again[0] == name and again[3]
+        kernel, rblk = bri.bri_get_apply_config(dims, 1, 1, 80, 12)
+        assert name.startswith(autotune.TILES.get(kernel, "gather")), (name, kernel, rblk)
+        # the single right-hand side shape is untouched by the tune
+        assert bri.bri_get_apply_config(dims, 1, 1, 80, 1) == builtin_1
+        log("autotune: 1-RHS apply after the 12-RHS tune")
+        assert torch.equal(bri.bri_apply(dims, W, x1, 0.1), before)
+        # a cache entry made with another library build is not used
+        monkeypatch.setattr(autotune, "_lib_digest", "abi0-otherbuild")
+        assert not autotune.tune(dims, W, x, reps=1)[3]
     finally:
-        bri.bri_set_apply_kernel(1, 1, old[0])
-        bri.bri_set_rhs_block(1, 1, old[1])
+        bri.bri_clear_apply_configs()

@@ -77,14 +77,12 @@ def test_table_every_kernel_configuration(bri):
             op = bri.Operator(bri.bri_build_transporters(dims, U, bri.F64, noff), coef=t)
             for kernel, rblk in ((0, 3), (0, 1), (2, 2), (3, 1), (5, 3), (8, 2), (9, 3), (10, 2), (11, 1), (12, 2)):
                 log(f"generic class kernel {kernel} rblk {rblk} noff {noff}")
-                bri.bri_set_apply_kernel(bri.F64, bri.F64, kernel)
-                bri.bri_set_rhs_block(bri.F64, bri.F64, rblk)
+                bri.bri_set_apply_config(dims, bri.F64, bri.F64, noff, 3, kernel, rblk)
                 got = soa_to_canon(dims, bri.bri_apply_op(dims, op, x, mass))
                 for r in range(3):
                     assert rel(got[r], want[r]) <= TOL[0], (kernel, rblk, noff, r)
     finally:
-        bri.bri_set_apply_kernel(bri.F64, bri.F64, 1)
-        bri.bri_set_rhs_block(bri.F64, bri.F64, 0)
+        bri.bri_clear_apply_configs()
 
 
 @pytest.mark.parametrize("dims", [(8, 4, 4, 4), (32, 4, 2, 2)])
