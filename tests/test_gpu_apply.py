@@ -24,8 +24,13 @@ TOL = {("f64", "f64"): 1e-12, ("f32", "f32"): 1e-5, ("f16", "f32"): 5e-3, ("f16"
 PREC = {"f64": 0, "f32": 1, "f16": 2}
 
 # lattices: the 4^4 case, ragged volumes (not multiples of the 256-thread
-# block), extent-2 directions (x+1 == x-1), and a multi-block case
-LATTICES = [(4, 4, 4, 4), (5, 3, 2, 6), (2, 2, 2, 2), (6, 4, 4, 8), (16, 6, 2, 2)]
+# block), extent-2 directions (x+1 == x-1), a multi-block case, and two
+# lattices with Lx a multiple of 32 and Ly of 16, where the FP32 and FP64
+# 80-offset apply with one right-hand side takes the 32x16 tile that the
+# benchmark times at 32^3 x 64 (one tile per (z, t); the second with z and t
+# of extent 2, so the tile's z and t neighbours wrap onto one slice)
+LATTICES = [(4, 4, 4, 4), (5, 3, 2, 6), (2, 2, 2, 2), (6, 4, 4, 8), (16, 6, 2, 2), (32, 16, 3, 4),
+            (32, 16, 2, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -82,6 +87,8 @@ def test_apply_stored_matches_oracle(bri, dims, wp, sp, noff):
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     W = bri.bri_build_transporters(dims, U, PREC[wp], noff)
     x = bri.bri_pack_spinor(dims, dev(psi), PREC[sp])
+    if dims[0] % 32 == 0 and dims[1] % 16 == 0 and noff == 80 and wp == sp and wp != "f16":
+        assert bri.bri_get_apply_config(dims, PREC[wp], PREC[sp], noff, 1) == (13, 1)
     out = bri.bri_apply(dims, W, x, 0.1)
     outd = bri.bri_apply_dag(dims, W, x, 0.1)
     tol = TOL[(wp, sp)]
@@ -129,18 +136,51 @@ def test_multi_rhs_point_sources(bri, wp, sp, rblk):
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     W = bri.bri_build_transporters(dims, U, PREC[wp], 80)
     x = bri.bri_pack_spinor(dims, dev(src), PREC[sp])
-    old = bri.bri_get_rhs_block(PREC[wp], PREC[sp])
     try:
-        bri.bri_set_rhs_block(PREC[wp], PREC[sp], rblk)
+        bri.bri_set_apply_config(dims, PREC[wp], PREC[sp], 80, 12, 1, rblk)
         out = bri.bri_apply(dims, W, x, 0.1)
     finally:
-        bri.bri_set_rhs_block(PREC[wp], PREC[sp], old)
+        bri.bri_clear_apply_configs()
     got = soa_to_canon(dims, out)
     for r in range(12):
         check(got[r], ref[r], TOL[(wp, sp)], f"rhs {r}")
     # blocking does not change the arithmetic of a column
     one = soa_to_canon(dims, bri.bri_apply(dims, W, x[5:6].contiguous(), 0.1))
     assert np.array_equal(one[0], got[5])
+
+
+@pytest.mark.parametrize("wp,sp", [("f64", "f64"), ("f32", "f32"), ("f16", "f32")])
+@pytest.mark.parametrize("kind", ["point", "gaussian"])
+def test_multi_rhs_default_launch_lx32(bri, wp, sp, kind):
+    """Twelve right-hand sides in one fused launch with the built-in selection
+    at Lx = 32 (the 32x8 tile with prefetch and unrolled offsets, two
+    right-hand sides per thread: the configuration the autotuner picks for
+    the 12-source apply at 32^3 x 64), D and D^dag, every column element by
+    element against the oracle.  The point sources sit on a tile corner
+    (x = 31, y = 7), so their 81-point images wrap across tile and lattice
+    edges; the Gaussian fields load every tile."""
+    dims = (32, 8, 2, 3)
+    u = synth.gauge_links(dims, 0.3, 4001)
+    if kind == "point":
+        src = synth.point_sources(dims, site=(31, 7, 1, 2))
+    else:
+        src = synth.gaussian_spinor(dims, 4012, nrhs=12)
+    key = ("lx32", kind, dims)
+    if key not in _cache:
+        _cache[key] = (np.stack([dirac.apply(u, src[r], 0.1) for r in range(12)]),
+                       np.stack([dirac.apply_dag(u, src[r], 0.1) for r in range(12)]))
+    ref, refd = _cache[key]
+    log(f"multi-rhs default launch Lx=32 W={wp} psi={sp} {kind}")
+    bri.bri_clear_apply_configs()
+    assert bri.bri_get_apply_config(dims, PREC[wp], PREC[sp], 80, 12) == (8, 2)
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    W = bri.bri_build_transporters(dims, U, PREC[wp], 80)
+    x = bri.bri_pack_spinor(dims, dev(src), PREC[sp])
+    got = soa_to_canon(dims, bri.bri_apply(dims, W, x, 0.1))
+    gotd = soa_to_canon(dims, bri.bri_apply_dag(dims, W, x, 0.1))
+    for r in range(12):
+        check(got[r], ref[r], TOL[(wp, sp)], f"D rhs {r}")
+        check(gotd[r], refd[r], TOL[(wp, sp)], f"D^dag rhs {r}")
 
 
 def test_multi_rhs_ragged_count(bri):
@@ -152,12 +192,12 @@ def test_multi_rhs_ragged_count(bri):
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     W = bri.bri_build_transporters(dims, U, bri.F32, 80)
     x = bri.bri_pack_spinor(dims, dev(psi), bri.F32)
-    old = bri.bri_get_rhs_block(bri.F32, bri.F32)
     try:
-        bri.bri_set_rhs_block(bri.F32, bri.F32, 4)
+        bri.bri_set_apply_config(dims, bri.F32, bri.F32, 80, 7, 1, 4)
+        assert bri.bri_get_apply_config(dims, bri.F32, bri.F32, 80, 7) == (10, 4)
         out = soa_to_canon(dims, bri.bri_apply(dims, W, x, 0.1))
     finally:
-        bri.bri_set_rhs_block(bri.F32, bri.F32, old)
+        bri.bri_clear_apply_configs()
     for r in range(7):
         check(out[r], dirac.apply(u, psi[r], 0.1), 1e-5, f"rhs {r}")
 

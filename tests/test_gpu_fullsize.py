@@ -1,8 +1,11 @@
 """Parity at the full benchmark sizes, in the launch configuration the
-benchmark times (stored transporters, LDS-tiled kernel, one right-hand side),
-on outputs the oracle computes site by site: 256 random sites of 32^3 x 64
-and 24^3 x 48, for every stored precision and both transporter stores, and
-for the recompute variant."""
+benchmark times (stored transporters, LDS-tiled kernel, one right-hand side;
+at 32^3 x 64 the 32x16 tile for FP32 and FP64 with 80 offsets), on outputs
+the oracle computes site by site: 256 random sites plus three corners of
+32^3 x 64 and 24^3 x 48, for every stored precision and both transporter
+stores, D and D^dag (the oracle's D^dag from D(y,x)^dag), and for the
+recompute variant.  Each case is checked in the 2-norm over the sampled
+outputs and element by element against the largest sampled element."""
 import numpy as np
 import pytest
 
@@ -29,7 +32,8 @@ def inputs(dims, eps, seed):
                             [0, dims[1] - 1, 0, dims[3] - 1]])
         sites = np.concatenate([sites, corners])
         ref = dirac.apply_at(u, psi[0], 0.1, sites)
-        _inputs[key] = (u, psi, sites, ref)
+        refd = dirac.apply_dag_at(u, psi[0], 0.1, sites)
+        _inputs[key] = (u, psi, sites, ref, refd)
     return _inputs[key]
 
 
@@ -38,23 +42,33 @@ def sampled(bri, dims, out, sites):
     return np.stack([got[t, z, y, x] for x, y, z, t in sites])
 
 
+def check(got, ref, tol, what):
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    emax = float(np.abs(got - ref).max() / np.abs(ref).max())
+    assert err <= tol and emax <= tol, f"{what}: rel {err:.3e} max-elem {emax:.3e} > {tol}"
+
+
 @pytest.mark.parametrize("dims,eps,seed", [((32, 32, 32, 64), 0.3, 4001), ((24, 24, 24, 48), 0.4, 3001)])
 def test_fullsize_sampled_parity(dims, eps, seed):
     import torch
     import paper_1012_3615_amd as bri
-    u, psi, sites, ref = inputs(dims, eps, seed)
+    u, psi, sites, ref, refd = inputs(dims, eps, seed)
+    bri.bri_clear_apply_configs()
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     for wp, sp, noff in [(1, 1, 80), (1, 1, 40), (0, 0, 80), (2, 1, 80), (2, 2, 80)]:
-        log(f"fullsize {dims} w={wp} s={sp} noff={noff}")
+        log(f"fullsize {dims} w={wp} s={sp} noff={noff} kernel={bri.bri_get_apply_config(dims, wp, sp, noff, 1)}")
         W = bri.bri_build_transporters(dims, U, wp, noff)
         x = bri.bri_pack_spinor(dims, dev(psi), sp)
-        got = sampled(bri, dims, bri.bri_apply(dims, W, x, 0.1), sites)
-        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        assert err <= TOL[(wp, sp)], (wp, sp, noff, err)
+        check(sampled(bri, dims, bri.bri_apply(dims, W, x, 0.1), sites), ref, TOL[(wp, sp)],
+              f"D w={wp} s={sp} noff={noff}")
+        check(sampled(bri, dims, bri.bri_apply_dag(dims, W, x, 0.1), sites), refd, TOL[(wp, sp)],
+              f"D^dag w={wp} s={sp} noff={noff}")
         del W, x
         torch.cuda.empty_cache()
     log(f"fullsize {dims} recompute f32")
     U32 = bri.bri_pack_links(dims, dev(u), bri.F32)
     x = bri.bri_pack_spinor(dims, dev(psi), bri.F32)
-    got = sampled(bri, dims, bri.bri_apply(dims, U32, x, 0.1, variant=bri.RECOMPUTE), sites)
-    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+    check(sampled(bri, dims, bri.bri_apply(dims, U32, x, 0.1, variant=bri.RECOMPUTE), sites), ref, 1e-5,
+          "recompute D")
+    check(sampled(bri, dims, bri.bri_apply_dag(dims, U32, x, 0.1, variant=bri.RECOMPUTE), sites), refd, 1e-5,
+          "recompute D^dag")
