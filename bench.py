@@ -13,7 +13,7 @@ Printed (one JSON line): applications/s, the roofline of the apply kernel
 events on the library's stream), the CPU oracle timed on a bounded sample of
 the same workload, and side measurements of the other variants.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--cpu-full]
 """
 import argparse
 import hashlib
@@ -104,13 +104,22 @@ def batch_ms(torch, fn, steps, warmup, out=None):
     return s.elapsed_time(e) / (3 * steps)
 
 
-def cpu_baseline(u, psi, got, target_s=15.0):
-    """The CPU oracle as it stands (plain numpy, FP64), on sampled sites of the
-    same 32^3 x 64 workload, scaled to applications/s of the whole lattice;
-    also the relative error of the timed GPU output `got` (canonical layout)
-    at 64 random sites.  Returns (baseline dict, spot error)."""
+def cpu_baseline(u, psi, got, full=False):
+    """The CPU oracle as it stands (plain numpy, FP64): the whole-field apply
+    (oracle.dirac.apply: np.roll shifts, path-enumerated transporters, the
+    direct 81-point sum) on seeded lattices of 4^4 and 8^4 (and 16^3 x 32 with
+    full=True, about a minute per application), one warm-up then the median of
+    three, with the BLAS thread pool open to every host core.  The value is
+    the per-site rate of the largest lattice timed, in applications/s of the
+    32^3 x 64 lattice.  The threads the oracle actually used are measured as
+    process CPU time over wall time (numpy's per-site 3x3 products and
+    einsum loops run on one thread whatever the BLAS setting).  Also the
+    relative error of the timed GPU output `got` (canonical layout) at 64
+    random sites against the pointwise oracle.  Returns (baseline dict, spot
+    error)."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
+    from threadpoolctl import threadpool_info, threadpool_limits
+    import synth
     from oracle import dirac
     V = int(np.prod(DIMS))
     rs = np.random.default_rng(5)
@@ -118,20 +127,36 @@ def cpu_baseline(u, psi, got, target_s=15.0):
     ref = dirac.apply_at(u, psi, MASS, spot)
     gs = np.stack([got[t, z, y, x] for x, y, z, t in spot])
     spot_err = float(np.linalg.norm(gs - ref) / np.linalg.norm(ref))
-    rng = np.random.default_rng(99)
-    with threadpool_limits(limits=1):
-        probe = np.stack([rng.integers(0, L, 256) for L in DIMS], axis=1)
-        t0 = time.perf_counter()
-        dirac.apply_at(u, psi, MASS, probe)
-        dt0 = time.perf_counter() - t0
-        n = int(min(1 << 16, max(256, 256 * target_s / max(dt0, 1e-3))))
-        sites = np.stack([rng.integers(0, L, n) for L in DIMS], axis=1)
-        t0 = time.perf_counter()
-        dirac.apply_at(u, psi, MASS, sites)
-        dt = time.perf_counter() - t0
-    return {"value": (n / dt) / V, "unit": "applies/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} random sites of the 32^3x64 lattice via the pointwise oracle "
-                      f"(FP64 numpy, single thread), {dt:.1f} s, scaled by sites/V"}, spot_err
+    ncpu = os.cpu_count() or 1
+    sizes = [(4, 4, 4, 4), (8, 8, 8, 8)] + ([(16, 16, 16, 32)] if full else [])
+    per_size = {}
+    with threadpool_limits(limits=ncpu):
+        blas = sorted({(p.get("internal_api"), p.get("num_threads")) for p in threadpool_info()})
+        for dims in sizes:
+            uu = synth.gauge_links(dims, EPS, SEED_U)
+            pp = synth.gaussian_spinor(dims, SEED_PSI, nrhs=1)[0]
+            dirac.apply(uu, pp, MASS)  # warm-up
+            walls, cpus = [], []
+            for _ in range(3):
+                t0, c0 = time.perf_counter(), time.process_time()
+                dirac.apply(uu, pp, MASS)
+                walls.append(time.perf_counter() - t0)
+                cpus.append(time.process_time() - c0)
+            wall = float(np.median(walls))
+            vs = int(np.prod(dims))
+            per_size["x".join(map(str, dims))] = {
+                "median_s": wall, "applies_s": 1.0 / wall, "sites_per_s": vs / wall,
+                "gflops": FLOPS_PER_SITE * vs / wall / 1e9, "cpu_over_wall": float(sum(cpus) / sum(walls))}
+    last = per_size["x".join(map(str, sizes[-1]))]
+    used = max(1, int(round(max(e["cpu_over_wall"] for e in per_size.values()))))
+    return {"value": last["sites_per_s"] / V, "unit": "applies/s", "cores": used, "kind": "oracle",
+            "sample": (f"whole-field FP64 numpy oracle (oracle.dirac.apply) on "
+                       f"{', '.join('x'.join(map(str, d)) for d in sizes)} lattices (links exp(i {EPS} H)), "
+                       f"warm-up then median of 3 each; value = the per-site rate at "
+                       f"{'x'.join(map(str, sizes[-1]))} scaled to the 32x32x32x64 volume"),
+            "host_cpu_count": ncpu, "blas_threads": [list(b) for b in blas],
+            "threads_used": f"process CPU time / wall time = {max(e['cpu_over_wall'] for e in per_size.values()):.2f}",
+            "sizes": per_size}, spot_err
 
 
 def traffic_from_profile(launch_bytes_alg):
@@ -276,14 +301,15 @@ def variants_16_32(torch, bri, dev, steps=100):
     return out
 
 
-def wilson_comparison(torch, bri, u, x32, brillouin_ms, dev, steps=50):
+def wilson_comparison(torch, bri, u, x32, W, dev, steps=50):
     """The Wilson operator (the paper's comparison operator, applied from the
     links, half-spinor hops) on the same 32^3 x 64 links and spinor, FP32
     and FP64, one right-hand side; `steps` applications captured in a HIP
     graph and timed on its replays.  The ratio of the headline Brillouin
     launch to the FP32 Wilson launch is the cost of one D_B application in
     Wilson applications on this GPU (the paper's conjecture: near 1 where
-    both are bound by memory traffic).  Algorithmic bytes per site: the four
+    both are bound by memory traffic); both sides are timed the same way, on
+    graph replays (the Brillouin side with 20 applications per replay).  Algorithmic bytes per site: the four
     links of the site plus the spinor read and written (each neighbour
     spinor and backward link counted once, at its own site)."""
     import numpy as np
@@ -299,7 +325,10 @@ def wilson_comparison(torch, bri, u, x32, brillouin_ms, dev, steps=50):
                                  "alg_GBs": bps * V / (ms * 1e-3) / 1e9,
                                  "hbm_frac": bps * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del U, x, y
-    out["brillouin_f32_over_wilson_f32"] = brillouin_ms / out["wilson_f32"]["ms"]
+    yb = torch.empty_like(x32)
+    b_ms = batch_ms(torch, lambda: bri.bri_apply(DIMS, W, x32, MASS, out=yb), 20, 5, out=yb)
+    out["brillouin_f32_graph_ms"] = b_ms
+    out["brillouin_f32_over_wilson_f32"] = b_ms / out["wilson_f32"]["ms"]
     return out
 
 
@@ -542,6 +571,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the whole-field oracle at 16^3x32 (about four minutes)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     a = ap.parse_args()
@@ -664,24 +695,26 @@ def main():
         from paper_1012_3615_amd import autotune
         src = synth.point_sources(DIMS)
         x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F32)
-        name, _, table = autotune.tune(DIMS, W, x12, MASS, reps=3)
+        # (timed in this run, not read from a cache; the choice is installed
+        # for the 12-RHS shape only and stays for the solves below)
+        name, _, table, cached = autotune.tune(DIMS, W, x12, MASS, reps=3, use_cache=False)
         bench_variant("stored_w80_f32_12rhs", W, x12, 80, 8, 8, steps=5)
         extras["stored_w80_f32_12rhs"]["autotuned"] = name
         extras["stored_w80_f32_12rhs"]["autotune_ms"] = table
-        autotune.reset(bri.F32, bri.F32)  # the tuned choice would govern every later FP32 apply
+        extras["stored_w80_f32_12rhs"]["autotune_from_cache"] = cached
         del x12
         x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F64)
         W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
-        name, _, _ = autotune.tune(DIMS, W64, x12, MASS, reps=2)
+        name, _, _, cached = autotune.tune(DIMS, W64, x12, MASS, reps=2, use_cache=False)
         bench_variant("stored_w80_f64_12rhs", W64, x12, 80, 16, 16, steps=3)
         extras["stored_w80_f64_12rhs"]["autotuned"] = name
-        autotune.reset(bri.F64, bri.F64)
+        extras["stored_w80_f64_12rhs"]["autotune_from_cache"] = cached
         del x12, W64, src
         torch.cuda.empty_cache()
         res["extras"] = extras
 
     if not a.no_extras:
-        res["wilson_32x32x32x64"] = wilson_comparison(torch, bri, u, x32, per_ms, dev)
+        res["wilson_32x32x32x64"] = wilson_comparison(torch, bri, u, x32, W, dev)
     if not a.no_extras and not a.no_solve:
         res["solve_12rhs"] = solve_comparison(torch, bri, U64, dev)
     if not a.no_extras:
@@ -698,7 +731,7 @@ def main():
         res["overlap_kernel_24x24x24x48"] = overlap_kernel(torch, bri, dev)
 
     if not a.no_cpu_baseline:
-        res["cpu_baseline"], res["spot_parity_rel_err"] = cpu_baseline(u, psi[0], got)
+        res["cpu_baseline"], res["spot_parity_rel_err"] = cpu_baseline(u, psi[0], got, full=a.cpu_full)
     else:
         res["cpu_baseline"], res["spot_parity_rel_err"] = None, None
     print(json.dumps(res), flush=True)
