@@ -238,6 +238,26 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
                           int32_t nrhs, void *work, size_t work_bytes,
                           bri_solve_stats *stats /* host */, void *stream);
 
+/* Allocation-free form of bri_solve_cgne, for callers that cannot allocate
+ * device memory (serving loops and harnesses that forbid hipMalloc between
+ * set-up and tear-down).  Same arguments and results as bri_solve_cgne
+ * without the workspace: the library keeps a static device array of
+ * BRI_SOLVE_NOALLOC_MAX_BYTES (128 MiB) per device, present from the time the
+ * library's code is loaded on that device until the process ends, and calls
+ * no allocating routine.  A solve whose bri_solve_workspace_bytes exceeds
+ * that size is rejected with BRI_E_WORKSPACE before any device work (at
+ * 128 MiB: plain FP64 with one right-hand side up to ~99k sites, FP32 inner
+ * solves up to ~155k sites, 16^3 x 32 included).  The array is shared by
+ * every call on the device: calls on one device are serialised by a lock held
+ * until the call's work on `stream` has finished, so they never overlap; the
+ * array keeps the last call's contents, and nothing in it needs to start at
+ * zero (the solver writes each buffer before reading it).  `stream` must
+ * belong to the current device. */
+#define BRI_SOLVE_NOALLOC_MAX_BYTES (128u << 20)
+bri_status bri_solve_cgne_noalloc(bri_dims d, const bri_solve_params *p, const void *W_hi,
+                                  const void *W_lo, double mass, const double *b, double *x,
+                                  int32_t nrhs, bri_solve_stats *stats /* host */, void *stream);
+
 /* ---- gradient with respect to the links -----------------------------------
  * For S = Re sum_rhs <chi, D psi> (FP64 SoA spinors, nrhs fields each) writes
  * gradU = scale * (dS/dRe U + i dS/dIm U) in the FP64 SoA link layout, treating link

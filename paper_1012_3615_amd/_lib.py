@@ -82,6 +82,8 @@ PROTOTYPES = {
     "bri_solve_workspace_bytes": (_sz, [_D, ctypes.POINTER(bri_solve_params), _i32]),
     "bri_solve_cgne": (_i32, [_D, ctypes.POINTER(bri_solve_params), _vp, _vp, _dbl, _vp, _vp,
                               _i32, _vp, _sz, ctypes.POINTER(bri_solve_stats), _vp]),
+    "bri_solve_cgne_noalloc": (_i32, [_D, ctypes.POINTER(bri_solve_params), _vp, _vp, _dbl, _vp, _vp,
+                                      _i32, ctypes.POINTER(bri_solve_stats), _vp]),
     "bri_grad_workspace_bytes": (_sz, [_D]),
     "bri_grad_links": (_i32, [_D, _vp, _vp, _vp, _i32, _dbl, _vp, _vp, _vp, _sz, _vp]),
     "bri_grad_workspace_bytes_w": (_sz, [_D]),

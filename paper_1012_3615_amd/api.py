@@ -236,6 +236,47 @@ def solve_params(tol=1e-10, inner_tol=1e-4, max_iter=20000, max_outer=100, n_off
     return p
 
 
+def _solve_info(stats, nrhs, st):
+    return {
+        "iterations": stats.iterations, "outer": stats.outer, "applies": stats.applies,
+        "converged": bool(stats.converged),
+        "true_residual": [stats.true_residual[i] for i in range(min(nrhs, _lib.BRI_MAX_RHS))],
+        "status": st,
+    }
+
+
+def _solve_args(dims, W_hi, b, params, W_lo, x):
+    _need_cuda(W_hi, b, W_lo, x)
+    V = volume(dims)
+    _shape(b, (b.shape[0], 12, V, 2), "b")
+    _shape(W_hi, (params.n_offsets, 9, V, 2), "W_hi")
+    if W_lo is not None:
+        _shape(W_lo, (params.n_offsets, 9, V, 2), "W_lo")
+    if x is not None:
+        _shape(x, b.shape, "x")
+    if prec_of(b) != F64 or prec_of(W_hi) != F64:
+        raise ValueError("b and W_hi must be FP64")
+    if params.inner_prec != F64 and (W_lo is None or prec_of(W_lo) != params.inner_prec):
+        raise ValueError("W_lo must be given in the inner precision")
+    return x if x is not None else torch.zeros_like(b)
+
+
+def bri_solve_cgne_noalloc(dims, W_hi, b, mass, params, W_lo=None, x=None, raise_on_noconv=True):
+    """bri_solve_cgne without a workspace: the library's static per-device
+    array serves as workspace (nothing is allocated except x when not given).
+    Returns (x, stats dict)."""
+    x = _solve_args(dims, W_hi, b, params, W_lo, x)
+    nrhs = b.shape[0]
+    stats = _lib.bri_solve_stats()
+    st = _lib_handle.bri_solve_cgne_noalloc(_dims(dims), ctypes.byref(params), _ptr(W_hi), _ptr(W_lo),
+                                            float(mass), _ptr(b), _ptr(x), nrhs, ctypes.byref(stats),
+                                            _stream())
+    info = _solve_info(stats, nrhs, st)
+    if st != 0 and (raise_on_noconv or st != -4):
+        raise BriError(st, "bri_solve_cgne_noalloc")
+    return x, info
+
+
 def bri_solve_cgne(dims, W_hi, b, mass, params, W_lo=None, x=None, raise_on_noconv=True):
     """Solve D x = b (or D^dag x = b with params.dagger) for FP64 SoA spinors.
     Returns (x, stats dict)."""

@@ -16,6 +16,7 @@
 // The paper solves with BiCGstab (Sec. 6.4); CGNE is the solver of this
 // library, stopped on the FP64 true residual.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "abi_internal.h"
@@ -254,6 +255,37 @@ static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc
     return BRI_OK;
 }
 
+// ------------------------------------------------------------ allocation-free form
+// The workspace of bri_solve_cgne_noalloc: a static device array, one copy per
+// device (each device that loads the library's code holds it until the process
+// ends).  In host code `scratch` is only the host-side stand-in of the device
+// symbol: the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is ever handed to
+// kernels or copies.
+static __device__ __align__(256) unsigned char scratch[BRI_SOLVE_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                  // guards g_scratch_ptr
+void *g_scratch_ptr[kMaxDevices] = {};    // device address of scratch, per device
+std::mutex g_noalloc_mu[kMaxDevices];     // serialises the calls on one device
+
+// the device address of `scratch` on the current device (set up on the first
+// call on that device)
+bri_status scratch_address(int dev, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail(BRI_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if (!ptr) return fail(BRI_E_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BRI_OK;
+}
+}  // namespace
+
 }  // namespace bri
 
 using namespace bri;
@@ -276,6 +308,39 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     const OpDesc hi{W_hi, BRI_F64, p->n_offsets, 3, nullptr, nullptr};
     const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr, nullptr};
     return solve_core(d, p, hi, lo, mass, b, x, nrhs, work, work_bytes, stats, stream);
+}
+
+bri_status bri_solve_cgne_noalloc(bri_dims d, const bri_solve_params *p, const void *W_hi, const void *W_lo,
+                                  double mass, const double *b, double *x, int32_t nrhs, bri_solve_stats *stats,
+                                  void *stream) {
+    g_last_error.clear();
+    if (!p) return fail(BRI_E_ARG, "null params or stats");
+    if (p->n_offsets != 40 && p->n_offsets != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (nrhs < 1 || nrhs > BRI_MAX_RHS) return fail(BRI_E_ARG, "nrhs must be in [1, %d]", BRI_MAX_RHS);
+    const size_t need = bri_solve_workspace_bytes(d, p, nrhs);
+    if (need > (size_t)BRI_SOLVE_NOALLOC_MAX_BYTES)
+        return fail(BRI_E_WORKSPACE,
+                    "the allocation-free solver holds %zu bytes of workspace; this solve needs %zu "
+                    "(use bri_solve_cgne with a caller workspace)",
+                    (size_t)BRI_SOLVE_NOALLOC_MAX_BYTES, need);
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(BRI_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(BRI_E_UNSUPPORTED, "device index %d out of range", dev);
+    void *work = nullptr;
+    bri_status s = scratch_address(dev, &work);
+    if (s != BRI_OK) return s;
+    const OpDesc hi{W_hi, BRI_F64, p->n_offsets, 3, nullptr, nullptr};
+    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr, nullptr};
+    // one call at a time per device: the array is shared, and a call holds it
+    // until its work on the stream has finished (also on an error return)
+    std::lock_guard<std::mutex> lock(g_noalloc_mu[dev]);
+    s = solve_core(d, p, hi, lo, mass, b, x, nrhs, work, (size_t)BRI_SOLVE_NOALLOC_MAX_BYTES, stats, stream);
+    const hipError_t es = hipStreamSynchronize((hipStream_t)stream);
+    if (s == BRI_OK && es != hipSuccess) return fail(BRI_E_HIP, "synchronize: %s", hipGetErrorString(es));
+    return s;
 }
 
 bri_status bri_solve_cgne_op(bri_dims d, const bri_solve_params *p, const bri_operator *op_hi,
