@@ -31,6 +31,14 @@ EPS = 0.3
 SEED_U, SEED_PSI = 4001, 4002
 HBM_PEAK_GBS = 8000.0
 FLOPS_PER_SITE = 35376           # nominal flops per site and right-hand side
+FP64_PEAK_TFS = 78.6
+# transporter build: FP64 links read once (4 x 9 x 16 B) + FP32 80-offset store
+# written once (80 x 9 x 8 B); 104 FP64 3x3 complex products (216 flops each)
+BUILD_BYTES_PER_SITE = 4 * 9 * 16 + 80 * 9 * 8
+BUILD_FLOPS_PER_SITE = 104 * 216
+# link gradient with the transporters given: links, FP64 40-offset
+# transporters, chi and psi read once, the gradient written once
+GRAD_BYTES_PER_SITE = 4 * 9 * 16 + 40 * 9 * 16 + 2 * 12 * 16 + 4 * 9 * 16
 # the headline kernel and the launcher that picks its tile shape
 KERNEL_SOURCES = ["paper_1012_3615_amd/csrc/common.h", "paper_1012_3615_amd/csrc/stencil.h",
                   "paper_1012_3615_amd/csrc/apply_tiled.h", "paper_1012_3615_amd/csrc/apply_launch.h"]
@@ -405,7 +413,40 @@ def gradient_timing(torch, bri, dev):
     _, pf = timed_launches(torch, fwd, 5, 2)
     _, pb = timed_launches(torch, bwd, 5, 2)
     tf, tb = float(np.mean(pf)), float(np.mean(pb))
-    return {"forward_ms": tf, "backward_ms": tb, "backward_over_forward": tb / tf}
+    # the link gradient alone (bri_grad_links_w, FP64 40-offset transporters
+    # given): it must read the links, the transporters, chi and psi once and
+    # write the gradient once
+    V = bri.volume(dims)
+    W40 = bri.bri_build_transporters(dims, U, bri.F64, 40)
+    _, pg = timed_launches(torch, lambda: bri.bri_grad_links(dims, U, chi, psi, W40=W40), 5, 2)
+    tg = float(np.mean(pg))
+    gbps = GRAD_BYTES_PER_SITE * V / (tg * 1e-3) / 1e9
+    return {"forward_ms": tf, "backward_ms": tb, "backward_over_forward": tb / tf,
+            "grad_links_w": {"ms": tg, "alg_bytes_per_site": GRAD_BYTES_PER_SITE, "alg_GBs": gbps,
+                             "hbm_frac": gbps / HBM_PEAK_GBS, "bound": "hbm",
+                             "kernels": "k_grad_level (4 launches) + k_grad_gather"}}
+
+
+def build_roofline(torch, bri, U64, steps=3):
+    """The transporter build at 32^3 x 64 into the FP32 80-offset store (the
+    headline's transporters), timed with HIP events on the library's stream.
+    Algorithmic bytes per site: the FP64 links read once and the FP32 store
+    written once; flops: the 104 FP64 3x3 complex products of the hop-order
+    recursion over the 40 canonical offsets (12 two-hop x 2, 16 three-hop
+    x 3, 8 four-hop x 4; the 1-hop transporters are the links)."""
+    import numpy as np
+    V = bri.volume(DIMS)
+    W = bri.bri_build_transporters(DIMS, U64, bri.F32, 80)
+    _, p = timed_launches(torch, lambda: bri.bri_build_transporters(DIMS, U64, bri.F32, 80, out=W), steps, 1)
+    ms = float(np.mean(p))
+    del W
+    gbps = BUILD_BYTES_PER_SITE * V / (ms * 1e-3) / 1e9
+    tfs = BUILD_FLOPS_PER_SITE * V / (ms * 1e-3) / 1e12
+    return {"ms": ms, "alg_bytes_per_site": BUILD_BYTES_PER_SITE, "alg_GBs": gbps, "hbm_frac": gbps / HBM_PEAK_GBS,
+            "flops_per_site": BUILD_FLOPS_PER_SITE, "fp64_TFs": tfs, "fp64_frac": tfs / FP64_PEAK_TFS,
+            "bound": "hbm", "roofline_ms": max(BUILD_BYTES_PER_SITE * V / HBM_PEAK_GBS / 1e6,
+                                               BUILD_FLOPS_PER_SITE * V / FP64_PEAK_TFS / 1e9),
+            "kernels": "k_build_level<1..4> (one launch per hop count)"}
 
 
 def production_operator(torch, bri, U64, dev, psi, tol=1e-10):
@@ -644,7 +685,7 @@ def main():
                      # the same time priced at the minimum bytes of any stored scheme (W40)
                      "frac_vs_w40_min": bytes_per_site(40, 8, 8) * V / (per_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "gflops": FLOPS_PER_SITE * V / (per_ms * 1e-3) / 1e9,
-        "build_transporters_ms": build_ms,
+        "build_transporters_ms": build_ms,  # first build, host clock (includes the first launches)
         "input_generation_s": gen_s,
     }
 
@@ -714,6 +755,7 @@ def main():
         res["extras"] = extras
 
     if not a.no_extras:
+        res["build_transporters_32x32x32x64"] = build_roofline(torch, bri, U64)
         res["wilson_32x32x32x64"] = wilson_comparison(torch, bri, u, x32, W, dev)
     if not a.no_extras and not a.no_solve:
         res["solve_12rhs"] = solve_comparison(torch, bri, U64, dev)

@@ -7,7 +7,9 @@
 Each variant builds its inputs (links exp(i 0.3 H), seed 4001; Gaussian
 spinors; the 12 point sources for the 12-RHS variant; for the production
 operator forms prod*: one APE step, back-projected transporters whole or as
-two rows, and the clover term; overlap_sign_24: sign(gamma5 D) at 24^3 x 48
+two rows, and the clover term; build_w80_f32: the transporter build into
+the FP32 80-offset store; grad_w40: the link gradient with the FP64
+40-offset transporters given; overlap_sign_24: sign(gamma5 D) at 24^3 x 48
 to 1e-10 for the smeared, projected kernel at mass -1; wilson_f32/_f64: the
 Wilson comparison operator from the links), runs one untimed
 launch, then `reps` launches timed with HIP events on the current stream,
@@ -89,6 +91,23 @@ def run(dims, names, reps=3, mass=0.1):
             ms = _time(lambda: b.copy_(a), reps)
             out.append({"variant": "copy_2GiB", "ms": ms, "GBs": 2 * a.numel() / ms / 1e6})
             del a, b
+            continue
+        if name == "build_w80_f32":
+            W = bri.bri_build_transporters(dims, U64, bri.F32, 80)
+            ms = _time(lambda: bri.bri_build_transporters(dims, U64, bri.F32, 80, out=W), reps)
+            out.append({"variant": name, "ms": ms, "alg_GBs": V * (576 + 5760) / ms / 1e6,
+                        "fp64_TFs": V * 104 * 216 / ms / 1e9})
+            del W
+            torch.cuda.empty_cache()
+            continue
+        if name == "grad_w40":
+            W40 = bri.bri_build_transporters(dims, U64, bri.F64, 40)
+            chi = bri.bri_pack_spinor(dims, psi, bri.F64)
+            x = bri.bri_pack_spinor(dims, psi.conj(), bri.F64)
+            ms = _time(lambda: bri.bri_grad_links(dims, U64, chi, x, W40=W40), reps)
+            out.append({"variant": name, "ms": ms, "alg_GBs": V * (576 + 5760 + 384 + 576) / ms / 1e6})
+            del W40, chi, x
+            torch.cuda.empty_cache()
             continue
         if name == "overlap_sign_24":
             out.append(_run_overlap(reps))

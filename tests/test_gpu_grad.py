@@ -4,8 +4,10 @@ the oracle's explicit path-enumeration adjoint and central finite
 differences (h = 1e-6).
 
 Tolerances: AD vs oracle gradient 1e-12 (relative, 2-norm); AD vs central
-differences 1e-6 relative to the largest gradient entry (FD truncation is
-O(h^2) and the rounding of S is ~1e-16 |S| / h)."""
+differences 1e-6 relative to the largest gradient entry checked (FD
+truncation is O(h^2) and the rounding of S is ~1e-16 |S| / h; for S2 the
+source is confined to a 3^4 block so that |S2| stays O(1e3) and its rounding
+and the solver's 1e-14 residual stay below that bound)."""
 import math
 
 import numpy as np
@@ -144,30 +146,85 @@ def test_normal_solve_gradient_matches_oracle(torch, ag):
     assert rel(F.grad.cpu().numpy()[0], 2.0 * Xo) < 1e-10
 
 
-def test_normal_solve_central_differences_8_4(torch, ag):
-    dims, mass, h = (8, 8, 8, 8), 0.2, 1e-6
-    u = synth.gauge_links(dims, 0.3, 5301)
-    phi = synth.gaussian_spinor(dims, 5302, nrhs=1)
-    log("S2 gradient FD 8^4")
+def _local_source(dims, centre, seed):
+    """phi Gaussian on the 3^4 block around `centre`, zero elsewhere: S2 is then
+    O(|phi|^2) ~ 1e3 whatever the volume, so its rounding and the solver's
+    residual stay far below 1e-6 of the gradient entries near the block."""
+    phi = np.zeros((1,) + synth.lattice_shape(dims) + (4, 3), dtype=np.complex128)
+    g = synth.gaussian_spinor(dims, seed, nrhs=1)
+    for d in np.array(np.meshgrid(*[np.arange(-1, 2)] * 4, indexing="ij")).reshape(4, -1).T:
+        x, y, z, t = ((np.array(centre) + d) % np.array(dims)).tolist()
+        phi[0, t, z, y, x] = g[0, t, z, y, x]
+    return phi
+
+
+def _s2_checks(torch, ag, dims, mass, seed, n_links, with_oracle):
+    """AD of S2 = phi^dag (D^dag D)^{-1} phi against (a) central differences
+    of the GPU's S2 (h = 1e-6, real and imaginary parts of link entries next
+    to the source, solves to 1e-14) and, with_oracle, (b) the closed form
+    dS2/dU = d/dU Re<chi, D(U) psi> at fixed chi = -2 D X, psi = X, evaluated
+    by the pointwise oracle with X from the GPU solve (local central
+    differences of the bilinear form over the sites whose stencil holds the
+    link, summed with math.fsum)."""
+    u = synth.gauge_links(dims, 0.3, seed)
+    centre = tuple(int(L // 2) for L in dims)
+    phi = _local_source(dims, centre, seed + 1)
     U = torch.from_numpy(u).cuda().requires_grad_(True)
     F = torch.from_numpy(phi).cuda()
-    S2 = torch.real(torch.vdot(F.reshape(-1), ag.normal_solve(U, F, mass).reshape(-1)))
+    X = ag.normal_solve(U, F, mass, tol=1e-14)
+    S2 = torch.real(torch.vdot(F.reshape(-1), X.reshape(-1)))
     S2.backward()
     gU = U.grad.cpu().numpy()
+    Xh = X.detach().cpu().numpy()[0]
+    h = 1e-6
 
     def S2_of(uu):
-        X = ag.normal_solve(torch.from_numpy(uu).cuda(), F, mass, tol=1e-14)
-        return float(torch.real(torch.vdot(F.reshape(-1), X.reshape(-1))))
+        Xp = ag.normal_solve(torch.from_numpy(uu).cuda(), F, mass, tol=1e-14)
+        return float(torch.real(torch.vdot(F.reshape(-1), Xp.reshape(-1))))
 
-    rng = np.random.default_rng(6)
-    gmax = np.abs(gU).max()
-    for _ in range(3):
-        idx = tuple(int(rng.integers(s)) for s in u.shape)
-        up, um = u.copy(), u.copy()
-        up[idx] += h
-        um[idx] -= h
-        fd = (S2_of(up) - S2_of(um)) / (2 * h)
-        assert abs(fd - gU[idx].real) <= 1e-5 * gmax, (idx, fd, gU[idx].real)
+    rng = np.random.default_rng(seed + 7)
+    near = [(int(rng.integers(4)), tuple(int((c + rng.integers(-1, 2)) % L) for c, L in zip(centre, dims)),
+             int(rng.integers(3)), int(rng.integers(3))) for _ in range(n_links)]
+    idxs = [(mu, y[3], y[2], y[1], y[0], a, b) for mu, y, a, b in near]
+    gmax = max(abs(gU[i]) for i in idxs)
+    assert gmax > 1e-3  # the sampled entries carry the gradient
+    for idx in idxs:
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            up, um = u.copy(), u.copy()
+            up[idx] += unit * h
+            um[idx] -= unit * h
+            fd = (S2_of(up) - S2_of(um)) / (2 * h)
+            an = gU[idx].real if part == "re" else gU[idx].imag
+            assert abs(fd - an) <= 1e-6 * gmax, (idx, part, fd, an, gmax)
+    if not with_oracle:
+        return
+    off = np.array(np.meshgrid(*[np.arange(-2, 3)] * 4, indexing="ij")).reshape(4, -1).T
+    for (mu, y, a, b), idx in zip(near, idxs):
+        sites = (np.array(y)[None, :] + off) % np.array(dims)[None, :]
+        chi = -2.0 * dirac.apply_at(u, Xh, mass, sites)  # fixed: the derivative acts on D(U) only
+
+        def S_local(uu):
+            return math.fsum(np.real(np.conj(chi) * dirac.apply_at(uu, Xh, mass, sites)).ravel())
+
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            up, um = u.copy(), u.copy()
+            up[idx] += unit * h
+            um[idx] -= unit * h
+            ref = (S_local(up) - S_local(um)) / (2 * h)
+            an = gU[idx].real if part == "re" else gU[idx].imag
+            assert abs(ref - an) <= 1e-6 * gmax, ("closed form", idx, part, ref, an, gmax)
+
+
+def test_normal_solve_central_differences_8_4(torch, ag):
+    log("S2 gradient FD 8^4")
+    _s2_checks(torch, ag, (8, 8, 8, 8), 0.2, 5301, 3, with_oracle=True)
+
+
+def test_normal_solve_gradient_16_32(torch, ag):
+    """S2 at 16^3 x 32 (the second gradient lattice): central differences of
+    the GPU's S2 and the oracle's closed form, real and imaginary parts."""
+    log("S2 gradient FD and closed form 16^3x32")
+    _s2_checks(torch, ag, (16, 16, 16, 32), 0.2, 5311, 2, with_oracle=True)
 
 
 def test_torch_gradcheck_tiny(torch, ag):
