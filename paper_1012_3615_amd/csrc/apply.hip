@@ -16,17 +16,19 @@ namespace bri {
 
 // ---------------------------------------------------------------- launchers
 namespace {
-constexpr int kBlock = 256;
 
 template <typename LS, typename SS, typename A>
 hipError_t launch_recompute(const Geom &g, const void *U, const void *in, void *out, double diag,
                             int nrhs, bool dag, hipStream_t st) {
-    dim3 grid((g.V + 15) / 16, nrhs);  // 16 sites x 16 orthants per workgroup
+    // element planes are addressed with 32-bit byte offsets
+    if ((size_t)g.V * sizeof(LS) >= ((size_t)1 << 32) || (size_t)g.V * sizeof(SS) >= ((size_t)1 << 32))
+        return hipErrorInvalidValue;
+    dim3 grid((g.V + 15) / 16, nrhs);  // 16 sites x 16 threads per workgroup
     if (dag)
-        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, true>), grid, dim3(kBlock), 0, st, g,
+        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, true>), grid, dim3(256), 0, st, g,
                            (const LS *)U, (const SS *)in, (SS *)out, (A)diag);
     else
-        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, false>), grid, dim3(kBlock), 0, st, g,
+        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, false>), grid, dim3(256), 0, st, g,
                            (const LS *)U, (const SS *)in, (SS *)out, (A)diag);
     return hipGetLastError();
 }
