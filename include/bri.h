@@ -113,9 +113,10 @@ bri_status bri_unpack_links(bri_dims d, const void *U_soa, bri_prec p, double *U
  * obtained in hop order from the (k-1)-hop ones at the same site,
  *   W(x, x+n) = (1/k) sum_{mu in supp n} W(x, x+n-s_mu mu) V_mu(x+n-s_mu mu),
  * V_mu(y) = U_mu(y) for s_mu = +1 and U_mu(y-mu)^dag for s_mu = -1, which is
- * the average over all k! paths.  work: FP64 scratch of
- * bri_build_workspace_bytes(d, w_prec, n_offsets) bytes (0 is allowed when
- * that query returns 0). */
+ * the average over all k! paths.  All 80 transporters of a site are built in
+ * one kernel, each once, in FP64, and cast to w_prec on store; no scratch is
+ * needed: bri_build_workspace_bytes returns 0 and work may be NULL (the
+ * argument is kept for the SU(3) forms of bri_build_transporters_ex). */
 size_t bri_build_workspace_bytes(bri_dims d, bri_prec w_prec, int32_t n_offsets);
 bri_status bri_build_transporters(bri_dims d, const double *U_soa, void *W, bri_prec w_prec,
                                   int32_t n_offsets, void *work, size_t work_bytes, void *stream);

@@ -195,10 +195,10 @@ size_t bri_transporter_bytes(bri_dims d, bri_prec p, int32_t noff) {
 }
 
 size_t bri_build_workspace_bytes(bri_dims d, bri_prec p, int32_t noff) {
-    Geom g;
-    if (!dims_ok(d, &g) || !prec_ok(p) || (noff != 40 && noff != 80)) return 0;
-    if (p == BRI_F64 && noff == 40) return 0;
-    return (size_t)g.V * 9 * 40 * 16;
+    (void)d;
+    (void)p;
+    (void)noff;
+    return 0;  // the fused build keeps its lower levels on chip
 }
 
 bri_status bri_pack_links(bri_dims d, const double *U, void *soa, bri_prec p, void *stream) {
@@ -251,16 +251,9 @@ bri_status bri_build_transporters(bri_dims d, const double *U, void *W, bri_prec
     if (!prec_ok(wp)) return fail(BRI_E_ARG, "invalid precision");
     if (noff != 40 && noff != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
     if (!aligned(U) || !aligned(W)) return fail(BRI_E_ARG, "null or misaligned pointer");
-    const size_t need = bri_build_workspace_bytes(d, wp, noff);
-    hipStream_t st = (hipStream_t)stream;
-    if (need == 0) {
-        return hip_check(build_w40_f64(g, (const double2 *)U, (double2 *)W, st), "build transporters");
-    }
-    if (!aligned(work) || work_bytes < need)
-        return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", need);
-    if (overlap(work, need, W, bri_transporter_bytes(d, wp, noff)))
-        return fail(BRI_E_ARG, "workspace overlaps the transporter store");
-    return hip_check(build_cast(g, (const double2 *)U, (double2 *)work, W, (int)wp, noff, st), "build transporters");
+    (void)work;
+    (void)work_bytes;
+    return hip_check(build_fused(g, (const double2 *)U, W, (int)wp, noff, (hipStream_t)stream), "build transporters");
 }
 
 bri_status bri_apply(bri_dims d, bri_variant v, const void *W, bri_prec wp, int32_t noff,

@@ -89,7 +89,10 @@ size_t bri_transporter_bytes_ex(bri_dims d, bri_prec p, int32_t noff, bri_wform 
 size_t bri_build_workspace_bytes_ex(bri_dims d, bri_prec p, int32_t noff, bri_wform form) {
     Geom g;
     if (!dims_ok(d, &g) || !prec_ok(p) || (noff != 40 && noff != 80)) return 0;
-    if (form == BRI_W_AVERAGE || form == BRI_W_SU3) return bri_build_workspace_bytes(d, p, noff);
+    if (form == BRI_W_AVERAGE) return bri_build_workspace_bytes(d, p, noff);
+    // the SU(3) form projects the FP64 40-offset store, which is the output
+    // itself only for FP64 with 40 offsets
+    if (form == BRI_W_SU3) return (p == BRI_F64 && noff == 40) ? 0 : (size_t)g.V * 9 * 40 * 16;
     if (form == BRI_W_SU3_2ROW) return (size_t)g.V * 9 * 40 * 16;
     return 0;
 }

@@ -8,140 +8,17 @@
 //            = U_mu(x+n)^dag     if s_mu = -1,
 // (grouping the k! paths by their last direction gives k groups of (k-1)!
 // paths, each of which is the (k-1)-hop average times the last link).
-// Levels are built in separate launches (1, 2, 3, 4 hops), one thread per
-// (site, offset), in FP64, into the 40-offset store (offsets whose last non-zero component is +1); the other
-// orientation of a lower-level transporter is read through
-// W(x, x+m) = W(x+m, x)^dag.
+// k_build_fused builds all 80 transporters of a site in one kernel, each
+// once, in FP64, with the lower levels kept on chip; k_convert turns the
+// FP64 40-offset store into another store (the SU(3) forms project that
+// store first).
+#include "apply_recompute.h"
 #include "common.h"
 #include "kernels.h"
 
 namespace bri {
 
 namespace {
-
-__device__ __forceinline__ void load_mat(const double2 *p, size_t V, bool dagger, cx<double> m[3][3]) {
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        cx<double> v = ldc<double>(p + e * V);
-        if (dagger)
-            m[e % 3][e / 3] = cconj(v);
-        else
-            m[e / 3][e % 3] = v;
-    }
-}
-
-// The canonical offsets (i > 40) of each hop count: 4, 12, 16, 8 of them.
-struct CanonLevels {
-    signed char idx[5][16];
-    int count[5];
-};
-constexpr CanonLevels make_canon() {
-    CanonLevels t{};
-    for (int i = 41; i < 81; ++i) {
-        const int k = off_k(i);
-        t.idx[k][t.count[k]++] = (signed char)i;
-    }
-    return t;
-}
-constexpr CanonLevels kCanon = make_canon();
-__constant__ CanonLevels c_canon = make_canon();
-
-// One thread per (site, canonical offset of the level): the offsets of a
-// block of sites are consecutive blocks on one XCD, so the lower-level
-// transporters and links they share are read through its L2.  The offset
-// is uniform in a block; its code is selected by a uniform branch, so the
-// offset arithmetic stays compile-time.
-// Wout (optional): the target store (precision WT, 40 or 80 offsets), written
-// as soon as a transporter is final (the cast fused into the build: own plane
-// at x and, for 80 offsets, the adjoint at x+n under -n).  keep_stage = false
-// skips the FP64 stage write (the last level, whose stage nothing reads).
-template <int K, typename WT>
-__global__ __launch_bounds__(256) void k_build_level(Geom g, const double2 *__restrict__ U,
-                                                     double2 *__restrict__ W40, WT *__restrict__ Wout, int noff,
-                                                     bool keep_stage) {
-    constexpr int cnt = kCanon.count[K];
-    const int lin = xcd_block(blockIdx.x, gridDim.x);
-    const int site = (lin / cnt) * blockDim.x + threadIdx.x;
-    if (site >= g.V) return;
-    const int target = c_canon.idx[K][lin % cnt];
-    const size_t V = (size_t)g.V;
-    int c[4];
-    coords(g, site, c);
-    const Nbr nb = make_nbr(g, c);
-
-    static_for<41, 81>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (off_k(i) == K) {
-            if (i != target) return;
-            constexpr int n[4] = {off_n(i, 0), off_n(i, 1), off_n(i, 2), off_n(i, 3)};
-            cx<double> acc[3][3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) acc[a][b] = cmake(0.0, 0.0);
-            static_for<0, 4>([&](auto M) {
-                constexpr int mu = decltype(M)::value;
-                if constexpr (n[mu] != 0) {
-                    // last link L(n, mu)
-                    constexpr int sm = n[mu];
-                    int dl[4] = {n[0], n[1], n[2], n[3]};
-                    if (sm > 0) dl[mu] -= 1;
-                    const int yl = nb.at(dl[0], dl[1], dl[2], dl[3]);
-                    cx<double> l[3][3];
-                    load_mat(U + (size_t)mu * 9 * V + yl, V, sm < 0, l);
-                    if constexpr (K == 1) {
-#pragma unroll
-                        for (int a = 0; a < 3; ++a)
-#pragma unroll
-                            for (int b = 0; b < 3; ++b) acc[a][b] = cadd(acc[a][b], l[a][b]);
-                    } else {
-                        // predecessor m = n - s_mu mu
-                        constexpr int m0 = mu == 0 ? 0 : n[0], m1 = mu == 1 ? 0 : n[1],
-                                      m2 = mu == 2 ? 0 : n[2], m3 = mu == 3 ? 0 : n[3];
-                        constexpr int im = off_index(m0, m1, m2, m3);
-                        cx<double> p[3][3];
-                        if constexpr (is_canonical(im)) {
-                            load_mat(W40 + (size_t)plane40(im) * 9 * V + site, V, false, p);
-                        } else {
-                            const int ym = nb.at(m0, m1, m2, m3);
-                            load_mat(W40 + (size_t)plane40(80 - im) * 9 * V + ym, V, true, p);
-                        }
-#pragma unroll
-                        for (int a = 0; a < 3; ++a)
-#pragma unroll
-                            for (int b = 0; b < 3; ++b) {
-                                cx<double> t = acc[a][b];
-                                t = cmac(t, p[a][0], l[0][b]);
-                                t = cmac(t, p[a][1], l[1][b]);
-                                acc[a][b] = cmac(t, p[a][2], l[2][b]);
-                            }
-                    }
-                }
-            });
-            constexpr double inv = 1.0 / K;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) acc[a][b] = cscale(inv, acc[a][b]);
-            if (keep_stage) {
-                double2 *o = W40 + (size_t)plane40(i) * 9 * V + site;
-#pragma unroll
-                for (int e = 0; e < 9; ++e) st(o + e * V, acc[e / 3][e % 3]);
-            }
-            if (Wout) {
-                WT *o = Wout + (size_t)(noff == 80 ? i - 1 : plane40(i)) * 9 * V + site;
-#pragma unroll
-                for (int e = 0; e < 9; ++e) st(o + e * V, acc[e / 3][e % 3]);
-                if (noff == 80) {
-                    const int y = nb.at(n[0], n[1], n[2], n[3]);
-                    WT *ob = Wout + (size_t)(80 - i) * 9 * V + y;  // plane of offset 80 - i (< 40)
-#pragma unroll
-                    for (int e = 0; e < 9; ++e) st(ob + e * V, cconj(acc[e % 3][e / 3]));
-                }
-            }
-        }
-    });
-}
 
 // W40 (FP64) -> target store (precision WT, 40 or 80 offsets).  One thread
 // per (site x, canonical offset n): it reads W(x, x+n) once and writes it to
@@ -181,32 +58,167 @@ __global__ __launch_bounds__(256) void k_convert(Geom g, const double2 *__restri
 constexpr int kBlock = 256;
 }  // namespace
 
+// ---------------------------------------------------------------- fused build
+// All transporters of a site in one kernel, the way k_apply_recompute builds
+// them: 16 consecutive sites x 16 threads per workgroup, every one of the 80
+// transporters of a site built once by the hop-order recursion (k! W
+// carried, two- and three-hop ones shared through LDS, one support per wave),
+// in FP64, and written to the store as soon as it is built (the 40-offset
+// store keeps the offsets whose last non-zero component is +1).  No FP64
+// stage goes through HBM: the kernel reads the links (through the caches)
+// and writes the store.
 namespace {
+template <typename WT, int NOFF>
+__device__ __forceinline__ void store_w(WT *__restrict__ W, size_t V, int site, bool valid, const int (&n)[4],
+                                        double inv_fact, const cx<double> s[3][3]) {
+    const int i = (n[0] + 1) + 3 * (n[1] + 1) + 9 * (n[2] + 1) + 27 * (n[3] + 1);
+    if (!valid || (NOFF == 40 && i < 41)) return;
+    const int plane = NOFF == 80 ? (i < 40 ? i : i - 1) : i - 41;
+    WT *o = W + (size_t)plane * 9 * V + site;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) st(o + e * V, cscale(inv_fact, s[e / 3][e % 3]));
+}
+
+template <int P, typename WT, int NOFF>
+__device__ __forceinline__ void build_l2(const double2 *U, WT *W, size_t V, const NbrParts &q, int bits, int sl,
+                                         int site, bool valid, cx<double> (*w2)[9][16]) {
+    constexpr int MU = pair_lo(P), NU = pair_hi(P);
+    int n[4] = {0, 0, 0, 0};
+    n[MU] = (bits & 1) ? -1 : 1;
+    n[NU] = (bits & 2) ? -1 : 1;
+    cx<double> w[3][3], p[3][3], l[3][3];
+    zero33(w);
+    {
+        int m[4] = {0, 0, 0, 0};
+        m[NU] = n[NU];
+        last_link<NU, double2, double>(U, V, q, m, p);
+        last_link<MU, double2, double>(U, V, q, n, l);
+        mat_mul_acc(w, p, l);
+    }
+    {
+        int m[4] = {0, 0, 0, 0};
+        m[MU] = n[MU];
+        last_link<MU, double2, double>(U, V, q, m, p);
+        last_link<NU, double2, double>(U, V, q, n, l);
+        mat_mul_acc(w, p, l);
+    }
+    lds_put<double, 16>(w2, 4 * P + bits, sl, w);
+    store_w<WT, NOFF>(W, V, site, valid, n, 0.5, w);
+}
+
+template <int Q, typename WT, int NOFF>
+__device__ __forceinline__ void build_l3(const double2 *U, WT *W, size_t V, const NbrParts &q, int bits, int sl,
+                                         int site, bool valid, cx<double> (*w2)[9][16], cx<double> (*w3)[9][16]) {
+    constexpr int D0 = Q == 0 ? 1 : 0, D1 = Q <= 1 ? 2 : 1, D2 = Q <= 2 ? 3 : 2;
+    int n[4] = {0, 0, 0, 0};
+    n[D0] = (bits & 1) ? -1 : 1;
+    n[D1] = (bits & 2) ? -1 : 1;
+    n[D2] = (bits & 4) ? -1 : 1;
+    const int b0 = bits & 1, b1 = (bits >> 1) & 1, b2 = (bits >> 2) & 1;
+    cx<double> w[3][3], p[3][3], l[3][3];
+    zero33(w);
+    lds_get<double, 16>(w2, 4 * pair_index(D1, D2) + b1 + 2 * b2, sl, p);
+    last_link<D0, double2, double>(U, V, q, n, l);
+    mat_mul_acc(w, p, l);
+    lds_get<double, 16>(w2, 4 * pair_index(D0, D2) + b0 + 2 * b2, sl, p);
+    last_link<D1, double2, double>(U, V, q, n, l);
+    mat_mul_acc(w, p, l);
+    lds_get<double, 16>(w2, 4 * pair_index(D0, D1) + b0 + 2 * b1, sl, p);
+    last_link<D2, double2, double>(U, V, q, n, l);
+    mat_mul_acc(w, p, l);
+    lds_put<double, 16>(w3, 8 * Q + bits, sl, w);
+    store_w<WT, NOFF>(W, V, site, valid, n, 1.0 / 6.0, w);
+}
+
+template <typename WT, int NOFF>
+__global__ __launch_bounds__(256) void k_build_fused(Geom g, const double2 *__restrict__ U, WT *__restrict__ W) {
+    constexpr int S = 16;
+    __shared__ cx<double> w2[24][9][S];
+    __shared__ cx<double> w3[32][9][S];
+    const int sl = threadIdx.x % S;
+    const int role = (threadIdx.x / S) % 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s0 = blk * S + sl;
+    const bool valid = s0 < g.V;
+    const int site = valid ? s0 : 0;
+    const size_t V = (size_t)g.V;
+    int c[4];
+    coords(g, site, c);
+    const NbrParts q = make_parts(g, c);
+
+    // two hops and the links
+    static_for<0, 4>([&](auto P) {
+        if (wave == decltype(P)::value) build_l2<decltype(P)::value, WT, NOFF>(U, W, V, q, role, sl, site, valid, w2);
+    });
+    if (wave == 0) build_l2<4, WT, NOFF>(U, W, V, q, role, sl, site, valid, w2);
+    if (wave == 1) build_l2<5, WT, NOFF>(U, W, V, q, role, sl, site, valid, w2);
+    if (wave >= 2) {
+        // links: wave 2 the x and y directions, wave 3 z and t; role bit 0 the sign
+        const int sgn = (role & 1) ? -1 : 1;
+        static_for<0, 4>([&](auto M) {
+            constexpr int MU = decltype(M)::value;
+            if (wave == 2 + MU / 2 && (role >> 1) == MU % 2) {
+                int n[4] = {0, 0, 0, 0};
+                n[MU] = sgn;
+                cx<double> w[3][3];
+                last_link<MU, double2, double>(U, V, q, n, w);
+                store_w<WT, NOFF>(W, V, site, valid, n, 1.0, w);
+            }
+        });
+    }
+    __syncthreads();
+    // three hops
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        const int bits = 4 * half + role;
+        static_for<0, 4>([&](auto Q) {
+            if (wave == decltype(Q)::value)
+                build_l3<decltype(Q)::value, WT, NOFF>(U, W, V, q, bits, sl, site, valid, w2, w3);
+        });
+    }
+    __syncthreads();
+    // four hops
+    {
+        const int bits = 4 * wave + role;
+        int n[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) n[mu] = ((bits >> mu) & 1) ? -1 : 1;
+        cx<double> w[3][3], p[3][3], l[3][3];
+        zero33(w);
+        static_for<0, 4>([&](auto M) {
+            constexpr int MU = decltype(M)::value;
+            const int low = bits & ((1 << MU) - 1), high = bits >> (MU + 1);
+            lds_get<double, 16>(w3, 8 * MU + (low | (high << MU)), sl, p);
+            last_link<MU, double2, double>(U, V, q, n, l);
+            mat_mul_acc(w, p, l);
+        });
+        store_w<WT, NOFF>(W, V, site, valid, n, 1.0 / 24.0, w);
+    }
+}
+
 template <typename WT>
-hipError_t build_levels(const Geom &g, const double2 *U, double2 *W40, WT *Wout, int noff, hipStream_t st) {
-    const unsigned nb = (g.V + kBlock - 1) / kBlock;
-    const bool last_stage = Wout == nullptr;  // the 4-hop stage is read only when it is the output
-    hipLaunchKernelGGL((k_build_level<1, WT>), dim3(nb * kCanon.count[1]), dim3(kBlock), 0, st, g, U, W40, Wout,
-                       noff, true);
-    hipLaunchKernelGGL((k_build_level<2, WT>), dim3(nb * kCanon.count[2]), dim3(kBlock), 0, st, g, U, W40, Wout,
-                       noff, true);
-    hipLaunchKernelGGL((k_build_level<3, WT>), dim3(nb * kCanon.count[3]), dim3(kBlock), 0, st, g, U, W40, Wout,
-                       noff, true);
-    hipLaunchKernelGGL((k_build_level<4, WT>), dim3(nb * kCanon.count[4]), dim3(kBlock), 0, st, g, U, W40, Wout,
-                       noff, last_stage);
+hipError_t build_fused_t(const Geom &g, const double2 *U, void *W, int noff, hipStream_t st) {
+    // the link planes are addressed with 32-bit byte offsets
+    if ((size_t)g.V * sizeof(double2) >= ((size_t)1 << 32)) return hipErrorInvalidValue;
+    dim3 grid((g.V + 15) / 16);
+    if (noff == 80)
+        hipLaunchKernelGGL((k_build_fused<WT, 80>), grid, dim3(256), 0, st, g, U, (WT *)W);
+    else
+        hipLaunchKernelGGL((k_build_fused<WT, 40>), grid, dim3(256), 0, st, g, U, (WT *)W);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st) {
-    return build_levels<double2>(g, U, W40, nullptr, 40, st);
+hipError_t build_fused(const Geom &g, const double2 *U, void *W, int wp, int noff, hipStream_t st) {
+    if (wp == 0) return build_fused_t<double2>(g, U, W, noff, st);
+    if (wp == 1) return build_fused_t<float2>(g, U, W, noff, st);
+    if (wp == 2) return build_fused_t<__half2>(g, U, W, noff, st);
+    return hipErrorInvalidValue;
 }
 
-hipError_t build_cast(const Geom &g, const double2 *U, double2 *stage, void *W, int wp, int noff, hipStream_t st) {
-    if (wp == 0) return build_levels<double2>(g, U, stage, (double2 *)W, noff, st);
-    if (wp == 1) return build_levels<float2>(g, U, stage, (float2 *)W, noff, st);
-    if (wp == 2) return build_levels<__half2>(g, U, stage, (__half2 *)W, noff, st);
-    return hipErrorInvalidValue;
+hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st) {
+    return build_fused(g, U, W40, 0, 40, st);
 }
 
 hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st) {

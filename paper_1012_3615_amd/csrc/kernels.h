@@ -40,12 +40,13 @@ hipError_t apply_recompute(const Geom &g, int up, int sp, const void *U, const v
 hipError_t apply_wilson(const Geom &g, int prec, const void *U, const void *in, void *out, double diag,
                         int nrhs, bool dag, hipStream_t st);
 
-// build.hip: FP64 40-offset store, then conversion
+// build.hip: the FP64 40-offset store (the fused build), and its conversion
+// to another store
 hipError_t build_w40_f64(const Geom &g, const double2 *U, double2 *W40, hipStream_t st);
 hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int noff, hipStream_t st);
-// the same in one pass: levels 1-3 staged in FP64 (stage: 40-offset FP64
-// store), every transporter cast into W as soon as it is built
-hipError_t build_cast(const Geom &g, const double2 *U, double2 *stage, void *W, int wp, int noff, hipStream_t st);
+// all transporters of a site in one kernel (no FP64 stage in HBM), into the
+// store of precision wp with 40 or 80 offsets
+hipError_t build_fused(const Geom &g, const double2 *U, void *W, int wp, int noff, hipStream_t st);
 
 // production.hip
 hipError_t project_su3_soa(const double2 *A, double2 *Y, int64_t n, hipStream_t st);
