@@ -446,7 +446,7 @@ def build_roofline(torch, bri, U64, steps=3):
             "flops_per_site": BUILD_FLOPS_PER_SITE, "fp64_TFs": tfs, "fp64_frac": tfs / FP64_PEAK_TFS,
             "bound": "hbm", "roofline_ms": max(BUILD_BYTES_PER_SITE * V / HBM_PEAK_GBS / 1e6,
                                                BUILD_FLOPS_PER_SITE * V / FP64_PEAK_TFS / 1e9),
-            "kernels": "k_build_level<1..4> (one launch per hop count)"}
+            "kernels": "k_build_fused<float2, 80> (one launch)"}
 
 
 def production_operator(torch, bri, U64, dev, psi, tol=1e-10):
