@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_apply_stored(Geom g, const WS *__restri
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) st(o + (3 * s + a) * V, acc[r][s][a]);
+            for (int a = 0; a < 3; ++a) stnt(o + (3 * s + a) * V, acc[r][s][a]);
     }
 }
 

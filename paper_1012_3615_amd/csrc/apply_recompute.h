@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_apply_recompute(Geom g, const LS *__res
             cx<A> sum = cmake<A>(red[0][comp][ss][0], red[0][comp][ss][1]);
 #pragma unroll
             for (int o = 1; o < 16; ++o) sum = cadd(sum, cmake<A>(red[o][comp][ss][0], red[o][comp][ss][1]));
-            st(out + comp * V + st_site, caxpy(diag, ld_plane<A>(in + (size_t)comp * V, st_site), sum));
+            stnt(out + comp * V + st_site, caxpy(diag, ld_plane<A>(in + (size_t)comp * V, st_site), sum));
         }
     }
 }

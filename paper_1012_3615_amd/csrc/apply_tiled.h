@@ -226,7 +226,7 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) st(out + (size_t)r * 12 * V + (3 * s + a) * V + site, acc[r][s][a]);
+                for (int a = 0; a < 3; ++a) stnt(out + (size_t)r * 12 * V + (3 * s + a) * V + site, acc[r][s][a]);
         }
     }
 }

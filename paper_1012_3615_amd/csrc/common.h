@@ -118,6 +118,24 @@ template <typename A>
 __device__ __forceinline__ void st(__half2 *p, cx<A> v) {
     *p = __floats2half2_rn((float)v.re, (float)v.im);
 }
+// streaming stores (data written once per launch and not read again by it:
+// operator outputs), so the output stream does not take L2 capacity from
+// the spinor halos the tile kernels re-read
+template <typename A>
+__device__ __forceinline__ void stnt(double2 *p, cx<A> v) {
+    const f64x2 t = {(double)v.re, (double)v.im};
+    __builtin_nontemporal_store(t, reinterpret_cast<f64x2 *>(p));
+}
+template <typename A>
+__device__ __forceinline__ void stnt(float2 *p, cx<A> v) {
+    const f32x2 t = {(float)v.re, (float)v.im};
+    __builtin_nontemporal_store(t, reinterpret_cast<f32x2 *>(p));
+}
+template <typename A>
+__device__ __forceinline__ void stnt(__half2 *p, cx<A> v) {
+    __half2 h = __floats2half2_rn((float)v.re, (float)v.im);
+    __builtin_nontemporal_store(*reinterpret_cast<unsigned int *>(&h), reinterpret_cast<unsigned int *>(p));
+}
 
 // ------------------------------------------------------------------ geometry
 struct Geom {

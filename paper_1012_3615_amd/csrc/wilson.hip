@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_wilson(Geom g, const T *__restrict__ U,
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) st(o + (size_t)(3 * s + a) * V + site, acc[s][a]);
+            for (int a = 0; a < 3; ++a) stnt(o + (size_t)(3 * s + a) * V + site, acc[s][a]);
     }
 }
 
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256 * WTZ) void k_wilson_tile(Geom g, const T *__re
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) st(o + (size_t)(3 * s + a) * V + site, acc[s][a]);
+            for (int a = 0; a < 3; ++a) stnt(o + (size_t)(3 * s + a) * V + site, acc[s][a]);
     }
 }
 
