@@ -83,10 +83,11 @@ typedef enum {
 const char *bri_last_error(void);
 /* ABI revision of this header (incremented on incompatible change; 3 added
  * the coefficient table to bri_operator and to the gradient calls, 5
- * replaced the per-precision kernel choice by per-shape configurations).  bri_abi_version() returns the
+ * replaced the per-precision kernel choice by per-shape configurations, 6
+ * added the matrix-core apply and bri_solve_params.inner_mfma).  bri_abi_version() returns the
  * revision the library was built with; a caller compares it to
  * BRI_ABI_VERSION. */
-#define BRI_ABI_VERSION 5
+#define BRI_ABI_VERSION 6
 int32_t bri_abi_version(void);
 
 /* ---- sizes (bytes) of the SoA buffers ----------------------------------- */
@@ -153,6 +154,44 @@ bri_status bri_apply_dag(bri_dims d, bri_variant v, const void *W_or_U, bri_prec
  * 16-byte aligned (BRI_E_ARG otherwise).  Enqueued on stream, asynchronous. */
 bri_status bri_apply_wilson(bri_dims d, const void *U_soa, bri_prec prec, double mass, const void *in,
                             void *out, int32_t nrhs, int32_t dagger, void *stream);
+
+/* ---- matrix-core apply for blocks of right-hand sides (Eq. def_pref)
+ * The operator of bri_apply (80 offsets, c_SW = 0, any member of the generic
+ * class of Sec. 8) evaluated with the matrix cores: the spin matrix
+ * lambda_k + rho_k sum_mu n_mu gamma_mu is split into five colour sums,
+ *   X_0 = sum_n lambda_k W(x,x+n) psi(x+n),  X_mu = sum_n rho_k n_mu W(x,x+n) psi(x+n),
+ * and D psi = (lambda_0 + m) psi + X_0 + sum_mu gamma_mu X_mu.  The five sums
+ * of a site are one matrix product with FP16 operands (transporters times
+ * lambda_k or rho_k normalised to at most 1; psi scaled by a power of two per
+ * right-hand side) and FP32 accumulation; the gamma matrices, the diagonal term
+ * (from psi in FP32) and the output are FP32.  Relative error per output
+ * component is about 1e-3 of the field's scale: an operator for inner solves
+ * and other FP16-transporter work, not a replacement of the FP32 apply.
+ *
+ * bri_pack_w_mfma: the transporter store of this apply, written from a store
+ *   of bri_build_transporters (W: [n_offsets][9][V] complex in w_prec,
+ *   n_offsets 40 or 80).  W_mfma: device, BRI_MFMA_W_BYTES_PER_SITE bytes per
+ *   site, caller-allocated: per site the 80 offsets in the order of the
+ *   80-offset store, each a row-major 3x3 matrix of FP16 complex numbers
+ *   (real part first).  W and W_mfma must not overlap.
+ * bri_spinor_bound2: bound2[r] = (largest |real or imaginary part| of psi_r)^2
+ *   for r < nrhs (device doubles; psi FP32 SoA [nrhs][12][V] complex).
+ * bri_apply_mfma: out = D in (dagger = 0) or D^dag in (dagger = 1); in, out
+ *   FP32 SoA [nrhs][12][V] complex, nrhs in [1, 65535] (blocks of 12 per
+ *   workgroup; a partial block pads with zeros); bound2: device, nrhs doubles,
+ *   bound2[r] >= the largest squared real or imaginary part of in_r
+ *   (bri_spinor_bound2, or a squared 2-norm; any upper bound works, a loose
+ *   one costs nothing); coef: NULL for the Brillouin column of Tab. rholambda
+ *   or 9 host doubles lambda_0..4, rho_1..4.  in and out must not overlap;
+ *   pointers 16-byte aligned (BRI_E_ARG otherwise).  Enqueued on stream,
+ *   asynchronous; no allocation. */
+#define BRI_MFMA_W_BYTES_PER_SITE 2880
+bri_status bri_pack_w_mfma(bri_dims d, const void *W, bri_prec w_prec, int32_t n_offsets, void *W_mfma,
+                           void *stream);
+bri_status bri_spinor_bound2(bri_dims d, int32_t nrhs, const float *psi, double *bound2, void *stream);
+bri_status bri_apply_mfma(bri_dims d, const void *W_mfma, double mass, const float *in, float *out,
+                          int32_t nrhs, int32_t dagger, const double *coef, const double *bound2,
+                          void *stream);
 
 /* Launch configuration of the stored apply, per shape.  A shape is
  * (extents, w_prec, s_prec, n_offsets, nrhs).  Kernel codes:
@@ -222,6 +261,9 @@ typedef struct {
     int32_t check_every;     /* iterations between host convergence checks (>=1) */
     int32_t use_initial_guess; /* 0: x is zeroed first                           */
     int32_t dagger;          /* 1: solve D^dag x = b (CG on D D^dag) instead     */
+    int32_t inner_mfma;      /* 1: inner applies on the matrix cores              */
+                             /*    (bri_apply_mfma): inner_prec BRI_F16 and W_lo  */
+                             /*    from bri_pack_w_mfma                            */
 } bri_solve_params;
 
 #define BRI_MAX_RHS 64

@@ -23,6 +23,7 @@ class bri_solve_params(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("use_initial_guess", ctypes.c_int32),
         ("dagger", ctypes.c_int32),
+        ("inner_mfma", ctypes.c_int32),
     ]
 
 
@@ -40,7 +41,7 @@ class bri_solve_stats(ctypes.Structure):
 
 
 # BRI_ABI_VERSION of include/bri.h that the structures below mirror
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class bri_operator(ctypes.Structure):
@@ -76,6 +77,9 @@ PROTOTYPES = {
     "bri_apply": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
     "bri_apply_dag": (_i32, [_D, _i32, _vp, _i32, _i32, _i32, _dbl, _vp, _vp, _i32, _vp]),
     "bri_apply_wilson": (_i32, [_D, _vp, _i32, _dbl, _vp, _vp, _i32, _i32, _vp]),
+    "bri_pack_w_mfma": (_i32, [_D, _vp, _i32, _i32, _vp, _vp]),
+    "bri_spinor_bound2": (_i32, [_D, _i32, _vp, _vp, _vp]),
+    "bri_apply_mfma": (_i32, [_D, _vp, _dbl, _vp, _vp, _i32, _i32, _vp, _vp, _vp]),
     "bri_set_apply_config": (_i32, [_D, _i32, _i32, _i32, _i32, _i32, _i32]),
     "bri_get_apply_config": (_i32, [_D, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "bri_clear_apply_configs": (None, []),

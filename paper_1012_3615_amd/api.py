@@ -7,6 +7,7 @@ real tensors whose last axis holds (re, im):
     spinors       [nrhs, 12, V, 2]     component = 3*spin + colour
     links         [4, 9, V, 2]         element   = 3*a + b
     transporters  [n_offsets, 9, V, 2]   (two-row SU(3) form: [n_offsets, 6, V, 2])
+    matrix-core transporter store  [V, 80, 9, 2] float16 (site-major)
     clover term   [2, 18, V, 2]
 
 with dtype float64 (F64), float32 (F32) or float16 (F16).  Canonical fields
@@ -204,6 +205,69 @@ def bri_apply_wilson(dims, U, psi, mass, dagger=False, out=None):
     return out
 
 
+def _coef_arg(coef):
+    if coef is None:
+        return None, None
+    coef = tuple(float(c) for c in coef)
+    if len(coef) != 9:
+        raise ValueError("a coefficient table has nine entries (lambda_0..4, rho_1..4)")
+    arr = (ctypes.c_double * 9)(*coef)
+    return arr, ctypes.addressof(arr)
+
+
+def bri_pack_w_mfma(dims, W, out=None):
+    """The site-major FP16 transporter store of the matrix-core apply
+    ([V, 80, 9, 2] float16) from a 40- or 80-offset store W of any precision."""
+    _need_cuda(W, out)
+    V = volume(dims)
+    _shape(W, (W.shape[0], 9, V, 2), "transporters")
+    if out is None:
+        out = torch.empty((V, 80, 9, 2), dtype=torch.float16, device=W.device)
+    _shape(out, (V, 80, 9, 2), "matrix-core store")
+    if out.dtype != torch.float16:
+        raise ValueError("the matrix-core store is float16")
+    _check(_lib_handle.bri_pack_w_mfma(_dims(dims), _ptr(W), prec_of(W), W.shape[0], _ptr(out), _stream()),
+           "bri_pack_w_mfma")
+    return out
+
+
+def bri_spinor_bound2(dims, psi, out=None):
+    """Per right-hand side the square of the largest |real or imaginary part|
+    of an FP32 spinor field (float64 tensor [nrhs])."""
+    _need_cuda(psi, out)
+    _shape(psi, (psi.shape[0], 12, volume(dims), 2), "spinor")
+    if psi.dtype != torch.float32:
+        raise ValueError("bri_spinor_bound2 takes an FP32 field")
+    if out is None:
+        out = torch.empty(psi.shape[0], dtype=torch.float64, device=psi.device)
+    _check(_lib_handle.bri_spinor_bound2(_dims(dims), psi.shape[0], _ptr(psi), _ptr(out), _stream()),
+           "bri_spinor_bound2")
+    return out
+
+
+def bri_apply_mfma(dims, Wm, psi, mass, dagger=False, coef=None, bound2=None, out=None):
+    """out = D psi (or D^dag psi) on the matrix cores: Wm from bri_pack_w_mfma,
+    psi and out FP32; bound2 (float64 [nrhs], device) bounds the squared
+    components of psi, computed here when not given."""
+    _need_cuda(Wm, psi, out, bound2)
+    V = volume(dims)
+    _shape(Wm, (V, 80, 9, 2), "matrix-core store")
+    _shape(psi, (psi.shape[0], 12, V, 2), "spinor")
+    if psi.dtype != torch.float32 or Wm.dtype != torch.float16:
+        raise ValueError("the matrix-core apply takes an FP16 store and FP32 fields")
+    if bound2 is None:
+        bound2 = bri_spinor_bound2(dims, psi)
+    _shape(bound2, (psi.shape[0],), "bound2")
+    if out is None:
+        out = torch.empty_like(psi)
+    elif out.shape != psi.shape or out.dtype != psi.dtype:
+        raise ValueError("out must match the input spinor's shape and dtype")
+    _keep, cptr = _coef_arg(coef)
+    _check(_lib_handle.bri_apply_mfma(_dims(dims), _ptr(Wm), float(mass), _ptr(psi), _ptr(out), psi.shape[0],
+                                      int(bool(dagger)), cptr, _ptr(bound2), _stream()), "bri_apply_mfma")
+    return out
+
+
 def bri_set_apply_config(dims, w_prec, s_prec, n_offsets, nrhs, kernel, rhs_per_thread=2):
     """Install (kernel, rhs_per_thread) for applies of exactly this shape;
     kernel = -1 removes the entry (the shape returns to the built-in choice)."""
@@ -226,8 +290,11 @@ def bri_clear_apply_configs():
 
 # ------------------------------------------------------------------ solver
 def solve_params(tol=1e-10, inner_tol=1e-4, max_iter=20000, max_outer=100, n_offsets=80,
-                 inner_prec=F64, check_every=8, use_initial_guess=False, dagger=False):
+                 inner_prec=F64, check_every=8, use_initial_guess=False, dagger=False, inner_mfma=False):
+    """inner_mfma: inner applies on the matrix cores (inner_prec F16, W_lo
+    from bri_pack_w_mfma)."""
     p = _lib.bri_solve_params()
+    p.inner_mfma = int(bool(inner_mfma))
     p.tol, p.inner_tol = tol, inner_tol
     p.max_iter, p.max_outer = max_iter, max_outer
     p.n_offsets, p.inner_prec = n_offsets, inner_prec
@@ -251,7 +318,7 @@ def _solve_args(dims, W_hi, b, params, W_lo, x):
     _shape(b, (b.shape[0], 12, V, 2), "b")
     _shape(W_hi, (params.n_offsets, 9, V, 2), "W_hi")
     if W_lo is not None:
-        _shape(W_lo, (params.n_offsets, 9, V, 2), "W_lo")
+        _shape(W_lo, (V, 80, 9, 2) if params.inner_mfma else (params.n_offsets, 9, V, 2), "W_lo")
     if x is not None:
         _shape(x, b.shape, "x")
     if prec_of(b) != F64 or prec_of(W_hi) != F64:
@@ -285,7 +352,7 @@ def bri_solve_cgne(dims, W_hi, b, mass, params, W_lo=None, x=None, raise_on_noco
     _shape(b, (b.shape[0], 12, V, 2), "b")
     _shape(W_hi, (params.n_offsets, 9, V, 2), "W_hi")
     if W_lo is not None:
-        _shape(W_lo, (params.n_offsets, 9, V, 2), "W_lo")
+        _shape(W_lo, (V, 80, 9, 2) if params.inner_mfma else (params.n_offsets, 9, V, 2), "W_lo")
     if x is not None:
         _shape(x, b.shape, "x")
     if prec_of(b) != F64 or prec_of(W_hi) != F64:

@@ -25,7 +25,7 @@ ARCH = os.environ.get("BRI_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.hip", "abi_prod.hip", "apply.hip", "apply_f64.hip", "apply_f32.hip", "apply_f16.hip", "apply_f16h.hip",
            "apply_prod_f64.hip", "apply_prod_f32.hip", "apply_prod_f16.hip", "apply_prod_f16h.hip",
-           "build.hip", "production.hip", "overlap.hip", "pack.hip", "blas.hip", "solve.hip", "grad.hip", "wilson.hip"]
+           "build.hip", "production.hip", "overlap.hip", "pack.hip", "blas.hip", "solve.hip", "grad.hip", "wilson.hip", "mfma.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -35,6 +35,7 @@ struct OpDesc {
     int rows;
     const void *clover;
     const double *coef;
+    bool mfma = false;  // W is the matrix-core store (bri_pack_w_mfma); FP32 fields
 };
 bri_status op_from_public(const bri_operator *op, OpDesc *out);
 bri_status apply_op(bri_dims d, const OpDesc &op, bri_prec sp, double mass, const void *in, void *out,

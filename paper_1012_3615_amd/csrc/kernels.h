@@ -48,6 +48,16 @@ hipError_t convert_w40(const Geom &g, const double2 *W40, void *W, int wp, int n
 // store of precision wp with 40 or 80 offsets
 hipError_t build_fused(const Geom &g, const double2 *U, void *W, int wp, int noff, hipStream_t st);
 
+// mfma.hip: the site-major FP16 store of the matrix-core apply (V x 2880 B
+// from a 40- or 80-offset store of precision wp), per-right-hand-side bounds
+// of an FP32 field, and the apply itself (FP32 fields, up to 12 right-hand
+// sides per workgroup; bound2 per right-hand side with stride bstride; tlen
+// <= 0 picks the t-chunk)
+hipError_t pack_w_mfma(const Geom &g, const void *W, int wp, int noff, void *Wm, hipStream_t st);
+hipError_t spinor_bound2(const Geom &g, int nrhs, const float2 *in, double *bound2, hipStream_t st);
+hipError_t apply_mfma(const Geom &g, const void *Wm, const float2 *in, float2 *out, int nrhs, double diag,
+                      const double *table, bool dag, const double *bound2, int bstride, int tlen, hipStream_t st);
+
 // production.hip
 hipError_t project_su3_soa(const double2 *A, double2 *Y, int64_t n, hipStream_t st);
 hipError_t project_w40(const Geom &g, double2 *W40, hipStream_t st);

@@ -65,7 +65,7 @@ Layout layout(size_t n, int nrhs, size_t tbytes) {
     L.q = take(lv);
     L.z = take(lv);
     L.part = take((size_t)nrhs * 1024 * 2 * sizeof(double));
-    L.red = take((size_t)3 * nrhs * 2 * sizeof(double));
+    L.red = take((size_t)4 * nrhs * 2 * sizeof(double));
     L.stv = take((size_t)7 * nrhs * sizeof(double));
     L.scale = take((size_t)nrhs * sizeof(double));
     L.unscale = take((size_t)nrhs * sizeof(double));
@@ -115,25 +115,37 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
     T *q = (T *)(c.w + c.L.q), *z = (T *)(c.w + c.L.z);
     double *part = (double *)(c.w + c.L.part);
     double *qq2 = (double *)(c.w + c.L.red), *rr2 = qq2 + 2 * c.nrhs, *zz2 = rr2 + 2 * c.nrhs;
+    double *pp2 = zz2 + 2 * c.nrhs;
+    // the operator; the matrix-core apply takes a bound of each input column
+    // (its squared 2-norm, stride 2 in the reduction output)
+    const double diag = (op.coef ? op.coef[0] : lam_k(0)) + c.mass;
+    auto apply = [&](const T *in, T *out, bool dag, const double *in_norm2) -> bri_status {
+        if (op.mfma)
+            return hip_check(apply_mfma(c.g, op.W, (const float2 *)in, (float2 *)out, c.nrhs, diag, op.coef, dag,
+                                        in_norm2, 2, 0, c.st),
+                             "apply (matrix cores)");
+        return apply_op(c.d, op, sp, c.mass, in, out, c.nrhs, c.st, dag);
+    };
     double *stv = (double *)(c.w + c.L.stv);
     const int nb = dot_blocks(c.n);
     const size_t bytes = c.n * c.nrhs * sizeof(T);
 
     BRI_HIP(zero(c.n * c.nrhs, e, c.st), "zero");
-    BRI_TRY(apply_op(c.d, op, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
-    ++*applies;
     BRI_TRY(norm2<T>(c, r, rr2));
+    BRI_TRY(apply(r, z, !c.dag, rr2));
+    ++*applies;
     BRI_TRY(norm2<T>(c, z, zz2));
     BRI_HIP(cg_init(c.nrhs, stv, rr2, zz2, rel * rel, c.st), "cg init");
     BRI_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, c.st), "copy");
     std::vector<double> hs(7 * c.nrhs);
     for (int it = 1; it <= max_it; ++it) {
-        BRI_TRY(apply_op(c.d, op, sp, c.mass, p, q, c.nrhs, c.st, c.dag));
+        if (op.mfma) BRI_TRY(norm2<T>(c, p, pp2));
+        BRI_TRY(apply(p, q, c.dag, pp2));
         BRI_TRY(norm2<T>(c, q, qq2));
         BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
         BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
         BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
-        BRI_TRY(apply_op(c.d, op, sp, c.mass, r, z, c.nrhs, c.st, !c.dag));
+        BRI_TRY(apply(r, z, !c.dag, rr2));
         BRI_TRY(norm2<T>(c, z, zz2));
         BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
         BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
@@ -173,6 +185,11 @@ static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc
         return fail(BRI_E_ARG, "inner_tol must be in (0, 1)");
     if (hi.wp != BRI_F64) return fail(BRI_E_ARG, "the outer operator must have FP64 transporters");
     if (mixed && lo.wp != p->inner_prec) return fail(BRI_E_ARG, "inner operator precision differs from inner_prec");
+    if (p->inner_mfma != 0 && p->inner_mfma != 1) return fail(BRI_E_ARG, "inner_mfma must be 0 or 1");
+    if (p->inner_mfma && p->inner_prec != BRI_F16)
+        return fail(BRI_E_ARG, "the matrix-core inner apply needs inner_prec = BRI_F16");
+    if (p->inner_mfma && (lo.rows != 3 || lo.clover))
+        return fail(BRI_E_UNSUPPORTED, "the matrix-core inner apply has no two-row store or clover term");
     if (!aligned(hi.W) || !aligned(b) || !aligned(x) || (mixed && !aligned(lo.W)))
         return fail(BRI_E_ARG, "null or misaligned pointer");
     const size_t n = (size_t)24 * g.V;
@@ -306,7 +323,7 @@ bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_h
     if (!p) return fail(BRI_E_ARG, "null params or stats");
     if (p->n_offsets != 40 && p->n_offsets != 80) return fail(BRI_E_ARG, "n_offsets must be 40 or 80");
     const OpDesc hi{W_hi, BRI_F64, p->n_offsets, 3, nullptr, nullptr};
-    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr, nullptr};
+    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr, nullptr, p->inner_mfma == 1};
     return solve_core(d, p, hi, lo, mass, b, x, nrhs, work, work_bytes, stats, stream);
 }
 
@@ -333,7 +350,7 @@ bri_status bri_solve_cgne_noalloc(bri_dims d, const bri_solve_params *p, const v
     bri_status s = scratch_address(dev, &work);
     if (s != BRI_OK) return s;
     const OpDesc hi{W_hi, BRI_F64, p->n_offsets, 3, nullptr, nullptr};
-    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr, nullptr};
+    const OpDesc lo{W_lo, p->inner_prec, p->n_offsets, 3, nullptr, nullptr, p->inner_mfma == 1};
     // one call at a time per device: the array is shared, and a call holds it
     // until its work on the stream has finished (also on an error return)
     std::lock_guard<std::mutex> lock(g_noalloc_mu[dev]);
@@ -354,6 +371,7 @@ bri_status bri_solve_cgne_op(bri_dims d, const bri_solve_params *p, const bri_op
     if (p->inner_prec != BRI_F64) {
         s = op_from_public(op_lo, &lo);
         if (s != BRI_OK) return s;
+        lo.mfma = p->inner_mfma == 1;
         // the inner operator is the same operator at lower precision
         const double *ch = hi.coef, *cl = lo.coef;
         bool same = (ch == nullptr) == (cl == nullptr);

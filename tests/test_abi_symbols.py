@@ -60,7 +60,7 @@ def test_size_queries(lib):
     assert lib.bri_transporter_bytes(d, 1, 39) == 0
     assert lib.bri_build_workspace_bytes(d, 0, 40) == 0
     assert lib.bri_build_workspace_bytes(d, 1, 80) == 0  # the fused build needs no stage
-    assert lib.bri_abi_version() == plib.ABI_VERSION == 5
+    assert lib.bri_abi_version() == plib.ABI_VERSION == 6
     # production-operator forms: two-row SU(3) store and the clover term
     assert lib.bri_transporter_bytes_ex(d, 1, 80, 0) == V * 80 * 9 * 8
     assert lib.bri_transporter_bytes_ex(d, 1, 80, 1) == V * 80 * 9 * 8
@@ -100,6 +100,17 @@ def test_argument_errors_without_device(lib):
     assert lib.bri_apply_wilson(d, None, 2, 0.1, None, None, 1, 0, None) == -2
     assert lib.bri_apply_wilson(d, None, 1, 0.1, None, None, 1, 2, None) == -1
     assert lib.bri_build_transporters_ex(d, None, None, 1, 80, 2, None, 0, None) == -1
+    # the matrix-core apply: argument checks come before any device work
+    assert lib.bri_apply_mfma(d, None, 0.1, None, None, 12, 0, None, None, None) == -1
+    assert b"pointer" in lib.bri_last_error()
+    assert lib.bri_apply_mfma(d, None, 0.1, None, None, 0, 0, None, None, None) == -1
+    assert b"nrhs" in lib.bri_last_error()
+    assert lib.bri_apply_mfma(d, None, 0.1, None, None, 12, 3, None, None, None) == -1
+    assert b"dagger" in lib.bri_last_error()
+    assert lib.bri_pack_w_mfma(d, None, 1, 39, None, None) == -1
+    assert b"n_offsets" in lib.bri_last_error()
+    assert lib.bri_pack_w_mfma(d, None, 5, 80, None, None) == -1
+    assert lib.bri_spinor_bound2(d, 0, None, None, None) == -1
     assert lib.bri_ape_smear(d, None, None, 0.72, None) == -1
     assert lib.bri_build_clover(d, None, 1.0, None, 1, None) == -1
     d.L[0] = 1
