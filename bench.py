@@ -39,6 +39,12 @@ BUILD_FLOPS_PER_SITE = 104 * 216
 # link gradient with the transporters given: links, FP64 40-offset
 # transporters, chi and psi read once, the gradient written once
 GRAD_BYTES_PER_SITE = 4 * 9 * 16 + 40 * 9 * 16 + 2 * 12 * 16 + 4 * 9 * 16
+# matrix-core 12-RHS apply: the site-major FP16 store read once (80 x 9 x 4 B),
+# 12 FP32 spinors read and written once (2 x 12 x 12 x 8 B); per site 20
+# reduction steps x 6 v_mfma_f32_16x16x32_f16 of 16 x 16 x 32 x 2 flops each
+MFMA_BYTES_PER_SITE = 80 * 9 * 4 + 2 * 12 * 12 * 8
+MFMA_ISSUED_FLOPS_PER_SITE = 20 * 6 * 16 * 16 * 32 * 2
+FP16_PEAK_TFS = 2500.0
 # the headline kernel and the launcher that picks its tile shape
 KERNEL_SOURCES = ["paper_1012_3615_amd/csrc/common.h", "paper_1012_3615_amd/csrc/stencil.h",
                   "paper_1012_3615_amd/csrc/apply_tiled.h", "paper_1012_3615_amd/csrc/apply_launch.h"]
@@ -211,6 +217,15 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
     torch.cuda.synchronize()
     t_half = time.perf_counter() - t0
     del W16
+    # the FP16-transporter inner solve with the matrix-core apply
+    Wm = bri.bri_pack_w_mfma(DIMS, W64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = bri.solve_params(tol=tol, inner_prec=bri.F16, inner_tol=1e-2, check_every=4, inner_mfma=True)
+    _, imf = bri.bri_solve_cgne(DIMS, W64, b, MASS, p, W_lo=Wm)
+    torch.cuda.synchronize()
+    t_mfma = time.perf_counter() - t0
+    del Wm
     # plain FP64 CGNE with the twelve sources batched (one fused FP64 apply per step)
     t0 = time.perf_counter()
     p = bri.solve_params(tol=tol, inner_prec=bri.F64, check_every=4)
@@ -238,7 +253,11 @@ def solve_comparison(torch, bri, U64, dev, tol=1e-10):
             "plain_fp64_batched_s": t_batched, "plain_fp64_batched_iterations": ib["iterations"],
             "plain_fp64_batched_max_true_residual": max(ib["true_residual"][:12]),
             "ratio_mixed_over_plain_batched": t_mixed / t_batched,
-            "ratio_mixed_f16w_over_plain_batched": t_half / t_batched}
+            "ratio_mixed_f16w_over_plain_batched": t_half / t_batched,
+            "mixed_f16w_mfma_s": t_mfma, "ratio_mixed_f16w_mfma_over_plain": t_mfma / t_plain,
+            "ratio_mixed_f16w_mfma_over_plain_batched": t_mfma / t_batched,
+            "mixed_f16w_mfma_iterations": imf["iterations"], "mixed_f16w_mfma_outer": imf["outer"],
+            "mixed_f16w_mfma_max_true_residual": max(imf["true_residual"][:12])}
 
 
 def solve_24x48(torch, bri, dev, tol=1e-10):
@@ -743,7 +762,24 @@ def main():
         extras["stored_w80_f32_12rhs"]["autotuned"] = name
         extras["stored_w80_f32_12rhs"]["autotune_ms"] = table
         extras["stored_w80_f32_12rhs"]["autotune_from_cache"] = cached
-        del x12
+        # the same 12 sources on the matrix cores (FP16 operands, FP32
+        # accumulation): the site-major FP16 store packed from the FP32 W80
+        Wm = bri.bri_pack_w_mfma(DIMS, W)
+        b2 = bri.bri_spinor_bound2(DIMS, x12)
+        o12 = torch.empty_like(x12)
+        _, p = timed_launches(torch, lambda: bri.bri_apply_mfma(DIMS, Wm, x12, MASS, bound2=b2, out=o12), 5, 10)
+        ms = float(np.mean(p))
+        _, pb = timed_launches(torch, lambda: bri.bri_spinor_bound2(DIMS, x12, out=b2), 5, 3)
+        byts = MFMA_BYTES_PER_SITE * V
+        issued = MFMA_ISSUED_FLOPS_PER_SITE * V
+        extras["mfma_w80_f16_12rhs"] = {
+            "ms": ms, "applies_s": 1e3 / ms, "alg_GBs": byts / (ms * 1e-3) / 1e9,
+            "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "mfma_issued_TFs": issued / (ms * 1e-3) / 1e12,
+            "mfma_frac_fp16_dense": issued / (ms * 1e-3) / 1e12 / FP16_PEAK_TFS,
+            "bound2_ms": float(np.mean(pb)),
+            "kernel": "k_apply_mfma<3> (4x2 tile, 12 rhs per workgroup)"}
+        del Wm, b2, o12, x12
         x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F64)
         W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
         name, _, _, cached = autotune.tune(DIMS, W64, x12, MASS, reps=2, use_cache=False)

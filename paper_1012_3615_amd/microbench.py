@@ -8,7 +8,8 @@ Each variant builds its inputs (links exp(i 0.3 H), seed 4001; Gaussian
 spinors; the 12 point sources for the 12-RHS variant; for the production
 operator forms prod*: one APE step, back-projected transporters whole or as
 two rows, and the clover term; build_w80_f32: the transporter build into
-the FP32 80-offset store; grad_w40: the link gradient with the FP64
+the FP32 80-offset store; mfma12_w80_f16: the matrix-core apply of the 12
+point sources; grad_w40: the link gradient with the FP64
 40-offset transporters given; overlap_sign_24: sign(gamma5 D) at 24^3 x 48
 to 1e-10 for the smeared, projected kernel at mass -1; wilson_f32/_f64: the
 Wilson comparison operator from the links), runs one untimed
@@ -121,6 +122,23 @@ def run(dims, names, reps=3, mass=0.1):
             ms = _time(lambda: bri.bri_apply_wilson(dims, Uw, x, mass, out=y), reps)
             out.append({"variant": name, "ms": ms, "alg_GBs": V * 60 * CB[wp] / ms / 1e6})
             del Uw, x, y
+            torch.cuda.empty_cache()
+            continue
+        if name == "mfma12_w80_f16":
+            # the matrix-core apply of the 12 point sources (site-major FP16
+            # store from the FP32 80-offset store, FP32 spinors)
+            W = bri.bri_build_transporters(dims, U64, bri.F32, 80)
+            Wm = bri.bri_pack_w_mfma(dims, W)
+            del W
+            src = torch.from_numpy(synth.point_sources(dims)).to("cuda")
+            x = bri.bri_pack_spinor(dims, src, bri.F32)
+            del src
+            b2 = bri.bri_spinor_bound2(dims, x)
+            y = torch.empty_like(x)
+            ms = _time(lambda: bri.bri_apply_mfma(dims, Wm, x, mass, bound2=b2, out=y), reps)
+            out.append({"variant": name, "ms": ms, "alg_GBs": V * (80 * 9 * 4 + 2 * 12 * 12 * 8) / ms / 1e6,
+                        "mfma_issued_TFs": V * 20 * 6 * 16 * 16 * 32 * 2 / ms / 1e9})
+            del Wm, x, y, b2
             torch.cuda.empty_cache()
             continue
         if name in PROD:
