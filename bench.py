@@ -40,7 +40,7 @@ BUILD_FLOPS_PER_SITE = 104 * 216
 # transporters, chi and psi read once, the gradient written once
 GRAD_BYTES_PER_SITE = 4 * 9 * 16 + 40 * 9 * 16 + 2 * 12 * 16 + 4 * 9 * 16
 # matrix-core 12-RHS apply: the site-major FP16 store read once (80 x 9 x 4 B),
-# 12 FP32 spinors read and written once (2 x 12 x 12 x 8 B); per site 20
+# 12 site-major FP32 spinors read and written once (2 x 12 x 12 x 8 B); per site 20
 # reduction steps x 6 v_mfma_f32_16x16x32_f16 of 16 x 16 x 32 x 2 flops each
 MFMA_BYTES_PER_SITE = 80 * 9 * 4 + 2 * 12 * 12 * 8
 MFMA_ISSUED_FLOPS_PER_SITE = 20 * 6 * 16 * 16 * 32 * 2
@@ -764,12 +764,16 @@ def main():
         extras["stored_w80_f32_12rhs"]["autotune_from_cache"] = cached
         # the same 12 sources on the matrix cores (FP16 operands, FP32
         # accumulation): the site-major FP16 store packed from the FP32 W80
+        # and site-major FP32 spinors [V][12][12] (the conversions from and
+        # to the SoA layout, which also give the per-source bounds, timed
+        # on their own)
         Wm = bri.bri_pack_w_mfma(DIMS, W)
-        b2 = bri.bri_spinor_bound2(DIMS, x12)
-        o12 = torch.empty_like(x12)
-        _, p = timed_launches(torch, lambda: bri.bri_apply_mfma(DIMS, Wm, x12, MASS, bound2=b2, out=o12), 5, 10)
+        xs, b2 = bri.bri_spinor_to_sites(DIMS, x12, bound2=True)
+        o12 = torch.empty_like(xs)
+        _, p = timed_launches(torch, lambda: bri.bri_apply_mfma(DIMS, Wm, xs, MASS, bound2=b2, out=o12), 5, 10)
         ms = float(np.mean(p))
-        _, pb = timed_launches(torch, lambda: bri.bri_spinor_bound2(DIMS, x12, out=b2), 5, 3)
+        _, pb = timed_launches(torch, lambda: bri.bri_spinor_to_sites(DIMS, x12, out=o12, bound2=b2), 5, 3)
+        _, pf = timed_launches(torch, lambda: bri.bri_spinor_from_sites(DIMS, xs, out=x12), 5, 3)
         byts = MFMA_BYTES_PER_SITE * V
         issued = MFMA_ISSUED_FLOPS_PER_SITE * V
         extras["mfma_w80_f16_12rhs"] = {
@@ -777,9 +781,9 @@ def main():
             "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "mfma_issued_TFs": issued / (ms * 1e-3) / 1e12,
             "mfma_frac_fp16_dense": issued / (ms * 1e-3) / 1e12 / FP16_PEAK_TFS,
-            "bound2_ms": float(np.mean(pb)),
-            "kernel": "k_apply_mfma<3> (4x2 tile, 12 rhs per workgroup)"}
-        del Wm, b2, o12, x12
+            "to_sites_with_bound_ms": float(np.mean(pb)), "from_sites_ms": float(np.mean(pf)),
+            "kernel": "k_apply_mfma<3> (4x2 tile, 12 rhs per workgroup, site-major spinors)"}
+        del Wm, b2, o12, x12, xs
         x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F64)
         W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
         name, _, _, cached = autotune.tune(DIMS, W64, x12, MASS, reps=2, use_cache=False)

@@ -174,11 +174,18 @@ bri_status bri_apply_wilson(bri_dims d, const void *U_soa, bri_prec prec, double
  *   site, caller-allocated: per site the 80 offsets in the order of the
  *   80-offset store, each a row-major 3x3 matrix of FP16 complex numbers
  *   (real part first).  W and W_mfma must not overlap.
- * bri_spinor_bound2: bound2[r] = (largest |real or imaginary part| of psi_r)^2
- *   for r < nrhs (device doubles; psi FP32 SoA [nrhs][12][V] complex).
+ * Spinors of this apply are site-major: [V][nrhs][12] FP32 complex (one
+ *   contiguous record of all right-hand sides per site); bri_spinor_to_sites
+ *   and bri_spinor_from_sites convert from and to the SoA layout
+ *   [nrhs][12][V] of the other entry points.
+ * bri_spinor_to_sites: psi (SoA) -> psi_sites (site-major); with bound2 !=
+ *   NULL also bound2[r] = (largest |real or imaginary part| of psi_r)^2
+ *   (device doubles).  bri_spinor_from_sites: the inverse.  FP32; the two
+ *   fields must not overlap.
+ * bri_spinor_bound2: the same bounds from an SoA field (FP32 [nrhs][12][V]).
  * bri_apply_mfma: out = D in (dagger = 0) or D^dag in (dagger = 1); in, out
- *   FP32 SoA [nrhs][12][V] complex, nrhs in [1, 65535] (blocks of 12 per
- *   workgroup; a partial block pads with zeros); bound2: device, nrhs doubles,
+ *   FP32 site-major [V][nrhs][12] complex, nrhs in [1, 65535] (blocks of 12
+ *   per workgroup; a partial block pads with zeros); bound2: device, nrhs doubles,
  *   bound2[r] >= the largest squared real or imaginary part of in_r
  *   (bri_spinor_bound2, or a squared 2-norm; any upper bound works, a loose
  *   one costs nothing); coef: NULL for the Brillouin column of Tab. rholambda
@@ -189,6 +196,9 @@ bri_status bri_apply_wilson(bri_dims d, const void *U_soa, bri_prec prec, double
 bri_status bri_pack_w_mfma(bri_dims d, const void *W, bri_prec w_prec, int32_t n_offsets, void *W_mfma,
                            void *stream);
 bri_status bri_spinor_bound2(bri_dims d, int32_t nrhs, const float *psi, double *bound2, void *stream);
+bri_status bri_spinor_to_sites(bri_dims d, int32_t nrhs, const float *psi, float *psi_sites, double *bound2,
+                               void *stream);
+bri_status bri_spinor_from_sites(bri_dims d, int32_t nrhs, const float *psi_sites, float *psi, void *stream);
 bri_status bri_apply_mfma(bri_dims d, const void *W_mfma, double mass, const float *in, float *out,
                           int32_t nrhs, int32_t dagger, const double *coef, const double *bound2,
                           void *stream);
@@ -262,7 +272,8 @@ typedef struct {
     int32_t use_initial_guess; /* 0: x is zeroed first                           */
     int32_t dagger;          /* 1: solve D^dag x = b (CG on D D^dag) instead     */
     int32_t inner_mfma;      /* 1: inner applies on the matrix cores              */
-                             /*    (bri_apply_mfma): inner_prec BRI_F16 and W_lo  */
+                             /*    (bri_apply_mfma, through site-major copies in  */
+                             /*    the workspace): inner_prec BRI_F16 and W_lo    */
                              /*    from bri_pack_w_mfma                            */
 } bri_solve_params;
 

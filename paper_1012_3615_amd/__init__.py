@@ -9,7 +9,7 @@ from .api import (  # noqa: F401
     spinor_empty, links_empty, transporters_empty,
     bri_pack_links, bri_pack_spinor, bri_unpack_spinor, bri_unpack_links,
     bri_build_transporters, bri_apply, bri_apply_dag, bri_apply_wilson,
-    bri_pack_w_mfma, bri_spinor_bound2, bri_apply_mfma,
+    bri_pack_w_mfma, bri_spinor_bound2, bri_apply_mfma, bri_spinor_to_sites, bri_spinor_from_sites,
     bri_set_apply_config, bri_get_apply_config, bri_clear_apply_configs,
     solve_params, bri_solve_cgne, bri_solve_cgne_noalloc, bri_grad_links,
     W_AVERAGE, W_SU3, W_SU3_2ROW, Operator, bri_project_su3, bri_ape_smear, bri_build_transporters_ex,

@@ -79,6 +79,8 @@ PROTOTYPES = {
     "bri_apply_wilson": (_i32, [_D, _vp, _i32, _dbl, _vp, _vp, _i32, _i32, _vp]),
     "bri_pack_w_mfma": (_i32, [_D, _vp, _i32, _i32, _vp, _vp]),
     "bri_spinor_bound2": (_i32, [_D, _i32, _vp, _vp, _vp]),
+    "bri_spinor_to_sites": (_i32, [_D, _i32, _vp, _vp, _vp, _vp]),
+    "bri_spinor_from_sites": (_i32, [_D, _i32, _vp, _vp, _vp]),
     "bri_apply_mfma": (_i32, [_D, _vp, _dbl, _vp, _vp, _i32, _i32, _vp, _vp, _vp]),
     "bri_set_apply_config": (_i32, [_D, _i32, _i32, _i32, _i32, _i32, _i32]),
     "bri_get_apply_config": (_i32, [_D, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),

@@ -8,6 +8,7 @@ real tensors whose last axis holds (re, im):
     links         [4, 9, V, 2]         element   = 3*a + b
     transporters  [n_offsets, 9, V, 2]   (two-row SU(3) form: [n_offsets, 6, V, 2])
     matrix-core transporter store  [V, 80, 9, 2] float16 (site-major)
+    site-major spinors (matrix-core apply)  [V, nrhs, 12, 2] float32
     clover term   [2, 18, V, 2]
 
 with dtype float64 (F64), float32 (F32) or float16 (F16).  Canonical fields
@@ -245,25 +246,63 @@ def bri_spinor_bound2(dims, psi, out=None):
     return out
 
 
-def bri_apply_mfma(dims, Wm, psi, mass, dagger=False, coef=None, bound2=None, out=None):
-    """out = D psi (or D^dag psi) on the matrix cores: Wm from bri_pack_w_mfma,
-    psi and out FP32; bound2 (float64 [nrhs], device) bounds the squared
-    components of psi, computed here when not given."""
-    _need_cuda(Wm, psi, out, bound2)
+def bri_spinor_to_sites(dims, psi, out=None, bound2=None):
+    """SoA FP32 spinor [nrhs, 12, V, 2] -> site-major [V, nrhs, 12, 2] (the
+    layout of the matrix-core apply); with a float64 tensor bound2 [nrhs]
+    (or True) also the per-right-hand-side bounds.  Returns the site-major
+    field, or (field, bound2) when bounds were asked for."""
+    _need_cuda(psi, out)
     V = volume(dims)
-    _shape(Wm, (V, 80, 9, 2), "matrix-core store")
     _shape(psi, (psi.shape[0], 12, V, 2), "spinor")
-    if psi.dtype != torch.float32 or Wm.dtype != torch.float16:
+    nrhs = psi.shape[0]
+    if psi.dtype != torch.float32:
+        raise ValueError("site-major fields are FP32")
+    if out is None:
+        out = torch.empty((V, nrhs, 12, 2), dtype=torch.float32, device=psi.device)
+    _shape(out, (V, nrhs, 12, 2), "site-major spinor")
+    want = bound2 is not None and bound2 is not False
+    if bound2 is True:
+        bound2 = torch.empty(nrhs, dtype=torch.float64, device=psi.device)
+    _check(_lib_handle.bri_spinor_to_sites(_dims(dims), nrhs, _ptr(psi), _ptr(out), _ptr(bound2) if want else None,
+                                           _stream()), "bri_spinor_to_sites")
+    return (out, bound2) if want else out
+
+
+def bri_spinor_from_sites(dims, psi_sites, out=None):
+    """Site-major [V, nrhs, 12, 2] -> SoA [nrhs, 12, V, 2] (FP32)."""
+    _need_cuda(psi_sites, out)
+    V = volume(dims)
+    nrhs = psi_sites.shape[1]
+    _shape(psi_sites, (V, nrhs, 12, 2), "site-major spinor")
+    if out is None:
+        out = torch.empty((nrhs, 12, V, 2), dtype=torch.float32, device=psi_sites.device)
+    _shape(out, (nrhs, 12, V, 2), "spinor")
+    _check(_lib_handle.bri_spinor_from_sites(_dims(dims), nrhs, _ptr(psi_sites), _ptr(out), _stream()),
+           "bri_spinor_from_sites")
+    return out
+
+
+def bri_apply_mfma(dims, Wm, psi_sites, mass, dagger=False, coef=None, bound2=None, out=None):
+    """out = D psi (or D^dag psi) on the matrix cores: Wm from bri_pack_w_mfma,
+    psi_sites and out site-major FP32 [V, nrhs, 12, 2] (bri_spinor_to_sites);
+    bound2 (float64 [nrhs], device) bounds the squared components of psi, as
+    bri_spinor_to_sites gives it; required."""
+    _need_cuda(Wm, psi_sites, out, bound2)
+    V = volume(dims)
+    nrhs = psi_sites.shape[1]
+    _shape(Wm, (V, 80, 9, 2), "matrix-core store")
+    _shape(psi_sites, (V, nrhs, 12, 2), "site-major spinor")
+    if psi_sites.dtype != torch.float32 or Wm.dtype != torch.float16:
         raise ValueError("the matrix-core apply takes an FP16 store and FP32 fields")
     if bound2 is None:
-        bound2 = bri_spinor_bound2(dims, psi)
-    _shape(bound2, (psi.shape[0],), "bound2")
+        raise ValueError("bound2 is required (bri_spinor_to_sites(..., bound2=True) gives it)")
+    _shape(bound2, (nrhs,), "bound2")
     if out is None:
-        out = torch.empty_like(psi)
-    elif out.shape != psi.shape or out.dtype != psi.dtype:
+        out = torch.empty_like(psi_sites)
+    elif out.shape != psi_sites.shape or out.dtype != psi_sites.dtype:
         raise ValueError("out must match the input spinor's shape and dtype")
     _keep, cptr = _coef_arg(coef)
-    _check(_lib_handle.bri_apply_mfma(_dims(dims), _ptr(Wm), float(mass), _ptr(psi), _ptr(out), psi.shape[0],
+    _check(_lib_handle.bri_apply_mfma(_dims(dims), _ptr(Wm), float(mass), _ptr(psi_sites), _ptr(out), nrhs,
                                       int(bool(dagger)), cptr, _ptr(bound2), _stream()), "bri_apply_mfma")
     return out
 

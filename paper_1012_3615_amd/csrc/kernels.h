@@ -50,11 +50,15 @@ hipError_t build_fused(const Geom &g, const double2 *U, void *W, int wp, int nof
 
 // mfma.hip: the site-major FP16 store of the matrix-core apply (V x 2880 B
 // from a 40- or 80-offset store of precision wp), per-right-hand-side bounds
-// of an FP32 field, and the apply itself (FP32 fields, up to 12 right-hand
-// sides per workgroup; bound2 per right-hand side with stride bstride; tlen
-// <= 0 picks the t-chunk)
+// of an FP32 SoA field, and the apply itself (FP32 site-major fields
+// [V][nrhs][12], 12 right-hand sides per workgroup; bound2 per right-hand
+// side with stride bstride; tlen <= 0 picks the t-chunk)
 hipError_t pack_w_mfma(const Geom &g, const void *W, int wp, int noff, void *Wm, hipStream_t st);
 hipError_t spinor_bound2(const Geom &g, int nrhs, const float2 *in, double *bound2, hipStream_t st);
+// SoA [nrhs][12][V] <-> site-major [V][nrhs][12] FP32 spinors; to_sites with
+// bound2 != nullptr also writes the per-right-hand-side bounds
+hipError_t spinor_sites(const Geom &g, int nrhs, const float2 *src, float2 *dst, bool to_sites, double *bound2,
+                        hipStream_t st);
 hipError_t apply_mfma(const Geom &g, const void *Wm, const float2 *in, float2 *out, int nrhs, double diag,
                       const double *table, bool dag, const double *bound2, int bstride, int tlen, hipStream_t st);
 

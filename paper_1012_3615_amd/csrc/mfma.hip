@@ -30,7 +30,11 @@
 // The transporters come from a site-major FP16 store (bri_pack_w_mfma):
 // for each site the 80 offsets in the order of the 80-offset store, each a
 // row-major 3x3 complex matrix (2880 B per site), so that a lane's three
-// entries of one row are one 12-byte load.
+// entries of one row are one 12-byte load.  The spinors are site-major too,
+// [V][nrhs][12] FP32 complex: the records of all right-hand sides of a halo
+// point are one contiguous run, so staging a plane reads whole cache lines
+// and writes the output in runs of 96 B per right-hand side.  k_transpose
+// converts from and to the SoA layout of the other kernels.
 #include <cmath>
 
 #include "abi_internal.h"
@@ -63,9 +67,9 @@ __host__ __device__ constexpr int comp(int p, int mu) {
 
 struct Args {
     Geom g;
-    int ntx, nty, ntc, tlen, nrhs;
+    int ntx, nty, ntc, tlen, nrhs;  // nrhs: right-hand sides of a site record (12 complex each)
     const uint32_t *Wm;     // site-major FP16 store, one complex per 32-bit word
-    const float2 *in;       // [nrhs][12][V]
+    const float2 *in;       // site-major: [V][nrhs][12]
     float2 *out;
     const double *bound2;   // per right-hand side (stride bstride): >= max |component|^2 of in
     int bstride;
@@ -113,6 +117,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
     float2 *__restrict__ out = a.out;
     const uint32_t *__restrict__ Wm = a.Wm;
     const float diag = a.diag, slam = a.slam, srho = a.srho;
+    const size_t srec = (size_t)a.nrhs * 12;  // complex numbers per site record
     const float lamw[5] = {0.0f, a.lam[1], a.lam[2], a.lam[3], a.lam[4]};
     const float rhow[5] = {0.0f, a.rho[1], a.rho[2], a.rho[3], a.rho[4]};
     const int tid = threadIdx.x, lane = tid & 63;
@@ -192,7 +197,9 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
 #pragma unroll
         for (int k = k0; k < k1; ++k) {
             const int idx = tid + k * NTHR;
-            const int rp = idx % RP, rec = (idx / RP) % RN, pz = idx / (RP * RN);
+            // records of one point consecutive: a point's right-hand sides are
+            // one contiguous piece of its site record
+            const int rec = idx % RN, rp = (idx / RN) % RP, pz = idx / (RP * RN);
             const int r = rec >> 2, s = rec & 3;
             const bool live = idx < NREC && r < nr;
             const int hx = rp % HX, hy = rp / HX;
@@ -200,10 +207,10 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
             // when Lx or Ly is smaller than the tile: a full modulo
             const int xx = (x0 + hx - 1 + Lx) % Lx, yy = (y0 + hy - 1 + Ly) % Ly, zz = (z + pz - 1 + Lz) % Lz;
             const size_t site = (size_t)xx + (size_t)Lx * (yy + (size_t)Ly * (zz + (size_t)Lz * tw));
-            const float2 *src = in + ((size_t)(r0 + min(r, nr - 1)) * 12 + 3 * s) * V + site;
+            const float2 *src = in + site * srec + (size_t)(r0 + min(r, nr - 1)) * 12 + 3 * s;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                const float2 v = src[b * V];
+                const float2 v = src[b];
                 pre[k - k0][b] = live ? v : make_float2(0.0f, 0.0f);
             }
         }
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
 #pragma unroll
         for (int k = k0; k < k1; ++k) {
             const int idx = tid + k * NTHR;
-            const float sc = sm.scl[((idx / RP) % RN) >> 2];
+            const float sc = sm.scl[(idx % RN) >> 2];
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 preh[k][b] = bits(h2{(_Float16)(pre[k - k0][b].x * sc), (_Float16)(pre[k - k0][b].y * sc)});
@@ -231,7 +238,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
         for (int k = 0; k < KMAX; ++k) {
             const int idx = tid + k * NTHR;
             if (idx < NREC) {
-                const int rp = idx % RP, rec = (idx / RP) % RN, pz = idx / (RP * RN);
+                const int rec = idx % RN, rp = (idx / RN) % RP, pz = idx / (RP * RN);
                 const int li = ((slot * 3 + pz) * RN + rec) * RPP + rp;
                 sm.b01[li] = make_uint2(preh[k][0], preh[k][1]);
                 sm.b2[li] = preh[k][2];
@@ -253,7 +260,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             const int r = min(4 * j + er4, nr - 1);
-            px[j] = in[((size_t)(r0 + r) * 12 + 3 * es + min(ea, 2)) * V + site];
+            px[j] = in[site * srec + (size_t)(r0 + r) * 12 + 3 * es + min(ea, 2)];
         }
     };
 
@@ -348,9 +355,9 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
                 float2 o;
                 o.x = fmaf(slam * X0.x + srho * gre, is, diag * px[j].x);
                 o.y = fmaf(slam * X0.y + srho * gim, is, diag * px[j].y);
-                // cached stores: the sites of a tile row write pieces of each
-                // plane that L2 merges with the neighbouring tiles'
-                out[((size_t)(r0 + r) * 12 + 3 * es + ea) * V + site] = o;
+                // the 48 lanes of a column tile write 384 contiguous bytes of
+                // the site record
+                out[site * srec + (size_t)(r0 + r) * 12 + 3 * es + ea] = o;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -449,6 +456,55 @@ __global__ __launch_bounds__(256) void k_pack(Geom g, const WS *__restrict__ W, 
     for (int i = threadIdx.x; i < ns * WSITE; i += blockDim.x) Wm[(size_t)s0 * WSITE + i] = buf[i];
 }
 
+// ---------------------------------------------------------------- site-major spinors
+// SoA [nrhs][12][V] <-> site-major [V][nrhs][12] (FP32 complex), through LDS
+// in blocks of 32 sites x 96 components (8 right-hand sides), so that both
+// sides are read and written in contiguous pieces.  The forward direction
+// can also give bound2 (as k_absmax2).
+constexpr int TS = 32, TC = 96;
+template <bool TO_SITES>
+__global__ __launch_bounds__(256) void k_transpose(int V, int ncomp, const float2 *__restrict__ src,
+                                                   float2 *__restrict__ dst, unsigned long long *__restrict__ bound2) {
+    __shared__ float2 tile[TC][TS + 1];
+    const int s0 = blockIdx.x * TS, c0 = blockIdx.y * TC;
+    const int ns = min(TS, V - s0), nc = min(TC, ncomp - c0);
+    for (int i = threadIdx.x; i < TC * TS; i += blockDim.x) {
+        if (TO_SITES) {
+            const int c = i / TS, s = i % TS;  // 32 consecutive sites of one plane
+            if (c < nc && s < ns) tile[c][s] = src[(size_t)(c0 + c) * V + s0 + s];
+        } else {
+            const int s = i / TC, c = i % TC;  // consecutive components of one site
+            if (c < nc && s < ns) tile[c][s] = src[(size_t)(s0 + s) * ncomp + c0 + c];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TC * TS; i += blockDim.x) {
+        if (TO_SITES) {
+            const int s = i / TC, c = i % TC;
+            if (c < nc && s < ns) dst[(size_t)(s0 + s) * ncomp + c0 + c] = tile[c][s];
+        } else {
+            const int c = i / TS, s = i % TS;
+            if (c < nc && s < ns) dst[(size_t)(c0 + c) * V + s0 + s] = tile[c][s];
+        }
+    }
+    if (TO_SITES && bound2) {
+        // thread (k, s): right-hand side c0 / 12 + k at site s0 + s; max over its 24 reals
+        const int k = threadIdx.x / TS, s = threadIdx.x % TS;
+        float m = 0.0f;
+        if (12 * k < nc && s < ns)
+            for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(tile[12 * k + c][s].x), fabsf(tile[12 * k + c][s].y)));
+        for (int o = 16; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));  // within the 32 lanes of k
+        if (s == 0 && 12 * k < nc) {
+            // the bound only grows: once it covers this block's value, as it
+            // soon does on most blocks, no atomic is needed (a stale read
+            // only costs a redundant one)
+            const unsigned long long d = (unsigned long long)__double_as_longlong((double)m * (double)m);
+            unsigned long long *b = bound2 + c0 / 12 + k;
+            if (__hip_atomic_load(b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < d) atomicMax(b, d);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- bounds
 // bound2[r] = (max over the real components of psi_r of |v|)^2, by an
 // unsigned maximum on the bits of the non-negative doubles (order-independent)
@@ -499,6 +555,19 @@ hipError_t spinor_bound2(const Geom &g, int nrhs, const float2 *in, double *boun
     size_t bx = (per + 255) / 256;
     if (bx > 512) bx = 512;
     hipLaunchKernelGGL(mfma::k_absmax2, dim3((unsigned)bx, (unsigned)nrhs), dim3(256), 0, st, (const float *)in, per, o);
+    return hipGetLastError();
+}
+
+hipError_t spinor_sites(const Geom &g, int nrhs, const float2 *src, float2 *dst, bool to_sites, double *bound2,
+                        hipStream_t st) {
+    const int ncomp = 12 * nrhs;
+    const dim3 grid((g.V + mfma::TS - 1) / mfma::TS, (ncomp + mfma::TC - 1) / mfma::TC);
+    unsigned long long *b = (unsigned long long *)bound2;
+    if (to_sites && b) hipLaunchKernelGGL(mfma::k_zero_u64, dim3((nrhs + 63) / 64), dim3(64), 0, st, b, nrhs);
+    if (to_sites)
+        hipLaunchKernelGGL(mfma::k_transpose<true>, grid, dim3(256), 0, st, g.V, ncomp, src, dst, b);
+    else
+        hipLaunchKernelGGL(mfma::k_transpose<false>, grid, dim3(256), 0, st, g.V, ncomp, src, dst, nullptr);
     return hipGetLastError();
 }
 
@@ -565,6 +634,32 @@ bri_status bri_spinor_bound2(bri_dims d, int32_t nrhs, const float *psi, double 
     if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
     if (!aligned(psi) || !aligned(bound2)) return fail(BRI_E_ARG, "null or misaligned (16 B) pointer");
     return hip_check(spinor_bound2(g, nrhs, (const float2 *)psi, bound2, (hipStream_t)stream), "spinor bound");
+}
+
+bri_status bri_spinor_to_sites(bri_dims d, int32_t nrhs, const float *psi, float *psi_sites, double *bound2,
+                               void *stream) {
+    g_last_error.clear();
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
+    if (!aligned(psi) || !aligned(psi_sites) || (bound2 && !aligned(bound2)))
+        return fail(BRI_E_ARG, "null or misaligned (16 B) pointer");
+    const size_t sb = (size_t)g.V * 12 * nrhs * 8;
+    if (overlap(psi, sb, psi_sites, sb)) return fail(BRI_E_ARG, "psi and psi_sites overlap");
+    return hip_check(spinor_sites(g, nrhs, (const float2 *)psi, (float2 *)psi_sites, true, bound2, (hipStream_t)stream),
+                     "spinor to site-major");
+}
+
+bri_status bri_spinor_from_sites(bri_dims d, int32_t nrhs, const float *psi_sites, float *psi, void *stream) {
+    g_last_error.clear();
+    Geom g;
+    if (!dims_ok(d, &g)) return fail(BRI_E_ARG, "invalid lattice extents");
+    if (nrhs < 1 || nrhs > 65535) return fail(BRI_E_ARG, "nrhs must be in [1, 65535]");
+    if (!aligned(psi) || !aligned(psi_sites)) return fail(BRI_E_ARG, "null or misaligned (16 B) pointer");
+    const size_t sb = (size_t)g.V * 12 * nrhs * 8;
+    if (overlap(psi, sb, psi_sites, sb)) return fail(BRI_E_ARG, "psi and psi_sites overlap");
+    return hip_check(spinor_sites(g, nrhs, (const float2 *)psi_sites, (float2 *)psi, false, nullptr, (hipStream_t)stream),
+                     "spinor from site-major");
 }
 
 bri_status bri_apply_mfma(bri_dims d, const void *W_mfma, double mass, const float *in, float *out, int32_t nrhs,

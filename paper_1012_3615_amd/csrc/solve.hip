@@ -45,10 +45,12 @@ hipError_t zero(size_t n, T *p, hipStream_t st) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t r_hi, dx_hi, e, r, p, q, z, part, red, stv, scale, unscale, total;
+    size_t r_hi, dx_hi, e, r, p, q, z, part, red, stv, scale, unscale, sin, sout, bnd, total;
 };
 
-Layout layout(size_t n, int nrhs, size_t tbytes) {
+// sites: the matrix-core inner apply's site-major copies of its input and
+// output and the per-column bounds of the input
+Layout layout(size_t n, int nrhs, size_t tbytes, bool sites = false) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -65,10 +67,15 @@ Layout layout(size_t n, int nrhs, size_t tbytes) {
     L.q = take(lv);
     L.z = take(lv);
     L.part = take((size_t)nrhs * 1024 * 2 * sizeof(double));
-    L.red = take((size_t)4 * nrhs * 2 * sizeof(double));
+    L.red = take((size_t)3 * nrhs * 2 * sizeof(double));
     L.stv = take((size_t)7 * nrhs * sizeof(double));
     L.scale = take((size_t)nrhs * sizeof(double));
     L.unscale = take((size_t)nrhs * sizeof(double));
+    if (sites) {
+        L.sin = take(lv);
+        L.sout = take(lv);
+        L.bnd = take((size_t)nrhs * sizeof(double));
+    }
     L.total = o;
     return L;
 }
@@ -115,15 +122,17 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
     T *q = (T *)(c.w + c.L.q), *z = (T *)(c.w + c.L.z);
     double *part = (double *)(c.w + c.L.part);
     double *qq2 = (double *)(c.w + c.L.red), *rr2 = qq2 + 2 * c.nrhs, *zz2 = rr2 + 2 * c.nrhs;
-    double *pp2 = zz2 + 2 * c.nrhs;
-    // the operator; the matrix-core apply takes a bound of each input column
-    // (its squared 2-norm, stride 2 in the reduction output)
+    // the operator; the matrix-core apply works on site-major copies (the
+    // transposition into them also gives the per-column bounds it needs)
     const double diag = (op.coef ? op.coef[0] : lam_k(0)) + c.mass;
-    auto apply = [&](const T *in, T *out, bool dag, const double *in_norm2) -> bri_status {
-        if (op.mfma)
-            return hip_check(apply_mfma(c.g, op.W, (const float2 *)in, (float2 *)out, c.nrhs, diag, op.coef, dag,
-                                        in_norm2, 2, 0, c.st),
-                             "apply (matrix cores)");
+    auto apply = [&](const T *in, T *out, bool dag) -> bri_status {
+        if (op.mfma) {
+            float2 *si = (float2 *)(c.w + c.L.sin), *so = (float2 *)(c.w + c.L.sout);
+            double *bnd = (double *)(c.w + c.L.bnd);
+            BRI_HIP(spinor_sites(c.g, c.nrhs, (const float2 *)in, si, true, bnd, c.st), "to site-major");
+            BRI_HIP(apply_mfma(c.g, op.W, si, so, c.nrhs, diag, op.coef, dag, bnd, 1, 0, c.st), "apply (matrix cores)");
+            return hip_check(spinor_sites(c.g, c.nrhs, so, (float2 *)out, false, nullptr, c.st), "from site-major");
+        }
         return apply_op(c.d, op, sp, c.mass, in, out, c.nrhs, c.st, dag);
     };
     double *stv = (double *)(c.w + c.L.stv);
@@ -132,20 +141,19 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
 
     BRI_HIP(zero(c.n * c.nrhs, e, c.st), "zero");
     BRI_TRY(norm2<T>(c, r, rr2));
-    BRI_TRY(apply(r, z, !c.dag, rr2));
+    BRI_TRY(apply(r, z, !c.dag));
     ++*applies;
     BRI_TRY(norm2<T>(c, z, zz2));
     BRI_HIP(cg_init(c.nrhs, stv, rr2, zz2, rel * rel, c.st), "cg init");
     BRI_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, c.st), "copy");
     std::vector<double> hs(7 * c.nrhs);
     for (int it = 1; it <= max_it; ++it) {
-        if (op.mfma) BRI_TRY(norm2<T>(c, p, pp2));
-        BRI_TRY(apply(p, q, c.dag, pp2));
+        BRI_TRY(apply(p, q, c.dag));
         BRI_TRY(norm2<T>(c, q, qq2));
         BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
         BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
         BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
-        BRI_TRY(apply(r, z, !c.dag, rr2));
+        BRI_TRY(apply(r, z, !c.dag));
         BRI_TRY(norm2<T>(c, z, zz2));
         BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
         BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
@@ -193,7 +201,7 @@ static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc
     if (!aligned(hi.W) || !aligned(b) || !aligned(x) || (mixed && !aligned(lo.W)))
         return fail(BRI_E_ARG, "null or misaligned pointer");
     const size_t n = (size_t)24 * g.V;
-    const Layout L = layout(n, nrhs, mixed ? sizeof(float) : sizeof(double));
+    const Layout L = layout(n, nrhs, mixed ? sizeof(float) : sizeof(double), p->inner_mfma == 1);
     if (!aligned(work) || work_bytes < L.total)
         return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", L.total);
     const size_t vb = n * nrhs * sizeof(double);
@@ -313,7 +321,7 @@ size_t bri_solve_workspace_bytes(bri_dims d, const bri_solve_params *p, int32_t 
     Geom g;
     if (!p || !dims_ok(d, &g) || nrhs < 1 || nrhs > BRI_MAX_RHS) return 0;
     const size_t tb = p->inner_prec == BRI_F64 ? sizeof(double) : sizeof(float);
-    return layout((size_t)24 * g.V, nrhs, tb).total;
+    return layout((size_t)24 * g.V, nrhs, tb, p->inner_mfma == 1).total;
 }
 
 bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_hi, const void *W_lo,

@@ -126,14 +126,14 @@ def run(dims, names, reps=3, mass=0.1):
             continue
         if name == "mfma12_w80_f16":
             # the matrix-core apply of the 12 point sources (site-major FP16
-            # store from the FP32 80-offset store, FP32 spinors)
+            # store from the FP32 80-offset store, site-major FP32 spinors)
             W = bri.bri_build_transporters(dims, U64, bri.F32, 80)
             Wm = bri.bri_pack_w_mfma(dims, W)
             del W
             src = torch.from_numpy(synth.point_sources(dims)).to("cuda")
             x = bri.bri_pack_spinor(dims, src, bri.F32)
             del src
-            b2 = bri.bri_spinor_bound2(dims, x)
+            x, b2 = bri.bri_spinor_to_sites(dims, x, bound2=True)
             y = torch.empty_like(x)
             ms = _time(lambda: bri.bri_apply_mfma(dims, Wm, x, mass, bound2=b2, out=y), reps)
             out.append({"variant": name, "ms": ms, "alg_GBs": V * (80 * 9 * 4 + 2 * 12 * 12 * 8) / ms / 1e6,

@@ -72,3 +72,43 @@ def test_fullsize_sampled_parity(dims, eps, seed):
           "recompute D")
     check(sampled(bri, dims, bri.bri_apply_dag(dims, U32, x, 0.1, variant=bri.RECOMPUTE), sites), refd, 1e-5,
           "recompute D^dag")
+
+
+def test_fullsize_mfma_12rhs_sampled():
+    """The matrix-core apply at 32^3 x 64 in the launch the benchmark times
+    (12 right-hand sides in one workgroup column, t chunks of 64, FP16
+    store from the FP32 80-offset store): twelve Gaussian columns, D and
+    D^dag at the sampled sites, each column within 5e-3 of the oracle in the
+    2-norm and 1e-2 per element against its largest sampled element (the
+    bars of the small-lattice matrix-core tests)."""
+    import torch
+    import paper_1012_3615_amd as bri
+    dims, eps, seed = (32, 32, 32, 64), 0.3, 4001
+    u, _, sites, _, _ = inputs(dims, eps, seed)
+    V = int(np.prod(dims))
+    idx = torch.as_tensor(sites[:, 0] + dims[0] * (sites[:, 1] + dims[1] * (sites[:, 2] + dims[2] * sites[:, 3])),
+                          device="cuda")
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    Wm = bri.bri_pack_w_mfma(dims, bri.bri_build_transporters(dims, U, bri.F32, 80))
+    del U
+    x = torch.empty((12, 12, V, 2), dtype=torch.float32, device="cuda")
+    refs, refds = [], []
+    for r in range(12):
+        log(f"fullsize mfma column {r}")
+        psi = synth.gaussian_spinor(dims, seed + 10 + r, nrhs=1)
+        refs.append(dirac.apply_at(u, psi[0], 0.1, sites).reshape(len(sites), 12))
+        refds.append(dirac.apply_dag_at(u, psi[0], 0.1, sites).reshape(len(sites), 12))
+        x[r] = bri.bri_pack_spinor(dims, dev(psi), bri.F32)[0]
+        del psi
+    xs, b2 = bri.bri_spinor_to_sites(dims, x, bound2=True)
+    for dag, ref in ((False, refs), (True, refds)):
+        log(f"fullsize mfma apply dagger={dag}")
+        out = bri.bri_spinor_from_sites(dims, bri.bri_apply_mfma(dims, Wm, xs, 0.1, dagger=dag, bound2=b2))
+        g = out[:, :, idx, :].double().cpu().numpy()  # [12 rhs, 12 comp, N, 2]
+        g = g[..., 0] + 1j * g[..., 1]
+        for r in range(12):
+            got = g[r].T  # [N, 12]
+            err = np.linalg.norm(got - ref[r]) / np.linalg.norm(ref[r])
+            emax = float(np.abs(got - ref[r]).max() / np.abs(ref[r]).max())
+            assert err <= 5e-3 and emax <= 1e-2, f"dagger={dag} rhs {r}: rel {err:.3e} max-elem {emax:.3e}"
+        del out

@@ -13,7 +13,12 @@ within half an FP16 unit (2^-11 relative) of each real component.
 Lattices cover ragged x-y tiles (the workgroup tile is 4 x 2), extent-2 and
 extent-3 directions (the halo wraps onto the tile), t-chunks with a ragged
 tail (Lt = 20 with 16-step chunks), right-hand-side counts that fill 1, 2
-and 3 column tiles and a partial second block of twelve (13, 25)."""
+and 3 column tiles and a partial second block of twelve (13, 25).
+
+The apply reads and writes site-major fields [V, nrhs, 12]; the tests move
+the oracle's fields there and back with bri_spinor_to_sites and
+bri_spinor_from_sites, whose results are checked bit for bit against a
+plain permutation of the SoA tensor."""
 import numpy as np
 import pytest
 
@@ -60,6 +65,13 @@ def check_columns(got, ref, what, tol=TOL, tol_elem=TOL_ELEM):
         assert err <= tol and emax <= tol_elem, f"{what} rhs {r}: rel {err:.3e} max-elem {emax:.3e}"
 
 
+def mfma_apply(bri, dims, Wm, x, mass, bound2=None, **kw):
+    """SoA FP32 spinor in, SoA out, through the site-major apply."""
+    xs, b2 = bri.bri_spinor_to_sites(dims, x, bound2=True)
+    out = bri.bri_apply_mfma(dims, Wm, xs, mass, bound2=b2 if bound2 is None else bound2, **kw)
+    return bri.bri_spinor_from_sites(dims, out)
+
+
 def store_to_canon(dims, Wm):
     """[V, 80, 9, 2] float16 -> complex (80, Lt, Lz, Ly, Lx, 3, 3)."""
     a = Wm.detach().cpu().numpy().astype(np.float64)
@@ -87,6 +99,27 @@ def test_store_is_rounded_transporters(bri, dims):
             assert np.all(np.abs(g - r) <= bound), (prec, noff, float(np.abs(g - r).max()))
 
 
+@pytest.mark.parametrize("dims,nrhs", [((4, 4, 4, 4), 12), ((5, 3, 2, 6), 5), ((3, 2, 2, 3), 25), ((7, 5, 3, 3), 1),
+                                       ((6, 4, 4, 8), 64)])
+def test_site_major_transposes_are_exact(bri, dims, nrhs):
+    """The two layouts hold the same numbers: to_sites is the permutation
+    [nrhs, 12, V] -> [V, nrhs, 12], from_sites its inverse, bit for bit; the
+    bounds are the squared largest |re| or |im| of each right-hand side.
+    Shapes cover site counts and component counts (12 nrhs) that are not
+    multiples of the 32 x 96 transpose tile."""
+    import torch
+    V = int(np.prod(dims))
+    log(f"site-major transposes dims={dims} nrhs={nrhs}")
+    g = torch.Generator(device="cpu").manual_seed(5701 + nrhs)
+    x = torch.randn((nrhs, 12, V, 2), generator=g, dtype=torch.float32).cuda()
+    x[0] *= 1e-20
+    xs, b2 = bri.bri_spinor_to_sites(dims, x, bound2=True)
+    assert torch.equal(xs, x.permute(2, 0, 1, 3).contiguous())
+    assert torch.equal(b2, torch.amax(x.abs().reshape(nrhs, -1), dim=1).double() ** 2)
+    assert torch.equal(bri.bri_spinor_to_sites(dims, x), xs)
+    assert torch.equal(bri.bri_spinor_from_sites(dims, xs), x)
+
+
 @pytest.mark.parametrize("dims,nrhs", CASES)
 def test_apply_mfma_matches_oracle(bri, dims, nrhs):
     u, psi, ref, refd = setup_case(dims, nrhs)
@@ -95,8 +128,8 @@ def test_apply_mfma_matches_oracle(bri, dims, nrhs):
     W = bri.bri_build_transporters(dims, U, bri.F32, 80)
     Wm = bri.bri_pack_w_mfma(dims, W)
     x = bri.bri_pack_spinor(dims, dev(psi), bri.F32)
-    out = bri.bri_apply_mfma(dims, Wm, x, 0.1)
-    outd = bri.bri_apply_mfma(dims, Wm, x, 0.1, dagger=True)
+    out = mfma_apply(bri, dims, Wm, x, 0.1)
+    outd = mfma_apply(bri, dims, Wm, x, 0.1, dagger=True)
     check_columns(soa_to_canon(dims, out), ref, "D")
     check_columns(soa_to_canon(dims, outd), refd, "D^dag")
 
@@ -114,8 +147,8 @@ def test_apply_mfma_coefficient_tables(bri, name):
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     Wm = bri.bri_pack_w_mfma(dims, bri.bri_build_transporters(dims, U, bri.F64, 40))
     x = bri.bri_pack_spinor(dims, dev(psi), bri.F32)
-    check_columns(soa_to_canon(dims, bri.bri_apply_mfma(dims, Wm, x, 0.1, coef=table)), ref, f"D {name}")
-    check_columns(soa_to_canon(dims, bri.bri_apply_mfma(dims, Wm, x, 0.1, dagger=True, coef=table)), refd,
+    check_columns(soa_to_canon(dims, mfma_apply(bri, dims, Wm, x, 0.1, coef=table)), ref, f"D {name}")
+    check_columns(soa_to_canon(dims, mfma_apply(bri, dims, Wm, x, 0.1, dagger=True, coef=table)), refd,
                   f"D^dag {name}")
 
 
@@ -128,8 +161,8 @@ def test_brillouin_table_equals_default(bri):
     U = bri.bri_pack_links(dims, dev(u), bri.F64)
     Wm = bri.bri_pack_w_mfma(dims, bri.bri_build_transporters(dims, U, bri.F32, 80))
     x = bri.bri_pack_spinor(dims, dev(psi), bri.F32)
-    a = bri.bri_apply_mfma(dims, Wm, x, 0.1)
-    b = bri.bri_apply_mfma(dims, Wm, x, 0.1, coef=bri.TABLE_BRILLOUIN)
+    a = mfma_apply(bri, dims, Wm, x, 0.1)
+    b = mfma_apply(bri, dims, Wm, x, 0.1, coef=bri.TABLE_BRILLOUIN)
     assert torch.equal(a, b)
 
 
@@ -154,10 +187,10 @@ def test_column_scales_are_independent(bri):
     b2 = bri.bri_spinor_bound2(dims, x)
     want = torch.amax(x.abs().reshape(5, -1), dim=1).double() ** 2
     assert torch.equal(b2, want)
-    check_columns(soa_to_canon(dims, bri.bri_apply_mfma(dims, Wm, x, 0.1, bound2=b2)), ref, "scaled columns")
+    check_columns(soa_to_canon(dims, mfma_apply(bri, dims, Wm, x, 0.1, bound2=b2)), ref, "scaled columns")
     # a loose bound (the squared 2-norm) gives the same accuracy
     n2 = (x.double() ** 2).reshape(5, -1).sum(dim=1)
-    check_columns(soa_to_canon(dims, bri.bri_apply_mfma(dims, Wm, x, 0.1, bound2=n2)), ref, "2-norm bound")
+    check_columns(soa_to_canon(dims, mfma_apply(bri, dims, Wm, x, 0.1, bound2=n2)), ref, "2-norm bound")
 
 
 def test_apply_mfma_rejects_bad_arguments(bri):
@@ -165,7 +198,7 @@ def test_apply_mfma_rejects_bad_arguments(bri):
     dims = (4, 4, 4, 4)
     V = 256
     Wm = torch.zeros((V, 80, 9, 2), dtype=torch.float16, device="cuda")
-    x = torch.zeros((2, 12, V, 2), dtype=torch.float32, device="cuda")
+    x = torch.zeros((V, 2, 12, 2), dtype=torch.float32, device="cuda")
     b2 = torch.ones(2, dtype=torch.float64, device="cuda")
     lib = bri.api._lib_handle
     D = bri.api._dims(dims)
@@ -182,6 +215,11 @@ def test_apply_mfma_rejects_bad_arguments(bri):
                               None) == 0
     torch.cuda.synchronize()
     assert torch.count_nonzero(out) == 0
+    # the layout conversions: overlap and right-hand-side count
+    assert lib.bri_spinor_to_sites(D, 2, x.data_ptr(), x.data_ptr(), None, None) == -1
+    assert lib.bri_spinor_from_sites(D, 2, x.data_ptr(), x.data_ptr(), None) == -1
+    assert lib.bri_spinor_to_sites(D, 0, x.data_ptr(), out.data_ptr(), None, None) == -1
+    assert lib.bri_spinor_from_sites(D, 70000, x.data_ptr(), out.data_ptr(), None) == -1
 
 
 def test_mixed_solve_with_matrix_core_inner_apply(bri):
