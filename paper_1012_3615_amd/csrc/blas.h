@@ -28,6 +28,15 @@ hipError_t convert(size_t n, int nrhs, const S *src, D *dst, const double *scale
 // x += scale[rhs] * e
 template <typename S>
 hipError_t accum(size_t n, int nrhs, const S *e, double *x, const double *scale, hipStream_t st);
+// site-major FP32 fields [V][nrhs][24] (nrhs <= 256): partials per rhs over
+// site_blocks(V, nrhs) workgroups, summed by dot_finish
+int site_blocks(size_t V, int nrhs);
+hipError_t norm2_sites(size_t V, int nrhs, const float *a, double *part, int nblk, hipStream_t st);
+hipError_t update_xr_sites(size_t V, int nrhs, const double *alpha, float *x, const float *p, float *r, const float *q,
+                           double *part, int nblk, hipStream_t st);
+// p = z + beta p, |p|^2 partials
+hipError_t update_p_sites(size_t V, int nrhs, const double *beta, const float *z, float *p, double *part, int nblk,
+                          hipStream_t st);
 // r = b - dx, |r|^2 partials
 hipError_t residual(size_t n, int nrhs, const double *b, const double *dx, double *r, double *part,
                     int nblk, hipStream_t st);

@@ -1,5 +1,6 @@
 // BLAS-1 kernels for the solver: every field is nrhs blocks of n real
-// numbers (n = 24 V: 12 complex components per site).  Reductions are
+// numbers (n = 24 V: 12 complex components per site), or, for the inner
+// solve on the matrix cores, site-major [V][nrhs][24] FP32.  Reductions are
 // deterministic: each workgroup sums a fixed slice in a fixed tree order into
 // its own partial (FP64), and a second kernel adds the partials of each
 // right-hand side in a fixed order.  No atomics.
@@ -182,6 +183,125 @@ __global__ void k_init(int nrhs, double *st, const double *rr2, const double *zz
     active[r] = (rr[r] > 0.0 && zz[r] > 0.0) ? 1.0 : 0.0;
 }
 
+// ---- site-major fields [V][nrhs][24] (FP32): the inner solve on the matrix
+// cores keeps its vectors in the layout of that apply.  A thread owns one
+// record (a site's 24 reals of one right-hand side, 96 contiguous bytes); a
+// workgroup covers SB = kB / nrhs consecutive sites per pass, so the records
+// of its threads are one contiguous piece and every thread keeps its
+// right-hand side.  The per-rhs block sums are a tree over the SB sites in a
+// fixed order, the partials then added by k_dot_finish: deterministic.
+struct SiteBlock {
+    int sb, rhs, sl;  // sites per pass, the thread's right-hand side and site in the pass
+    bool on;          // thread inside the SB x nrhs records
+};
+__device__ __forceinline__ SiteBlock site_block(int nrhs) {
+    SiteBlock b;
+    b.sb = kB / nrhs;
+    b.sl = threadIdx.x / nrhs;
+    b.rhs = threadIdx.x % nrhs;
+    b.on = b.sl < b.sb;
+    return b;
+}
+// per-rhs sum over the block's threads in a fixed tree order; the result for
+// rhs lands in sh[rhs]
+__device__ __forceinline__ void site_block_sum(const SiteBlock &b, int nrhs, double v, double *sh) {
+    sh[threadIdx.x] = b.on ? v : 0.0;
+    __syncthreads();
+    int p2 = 1;
+    while (p2 < b.sb) p2 <<= 1;
+    for (int h = p2 >> 1; h > 0; h >>= 1) {
+        if (b.on && b.sl < h && b.sl + h < b.sb) sh[threadIdx.x] += sh[threadIdx.x + h * nrhs];
+        __syncthreads();
+    }
+}
+__device__ __forceinline__ void site_partial(const SiteBlock &b, int nrhs, double v, double *sh, double *partial) {
+    site_block_sum(b, nrhs, v, sh);
+    if ((int)threadIdx.x < nrhs) {
+        partial[((size_t)threadIdx.x * gridDim.x + blockIdx.x) * 2 + 0] = sh[threadIdx.x];
+        partial[((size_t)threadIdx.x * gridDim.x + blockIdx.x) * 2 + 1] = 0.0;
+    }
+}
+__device__ __forceinline__ double sq4(float4 v, double acc) {
+    acc = fma((double)v.x, (double)v.x, acc);
+    acc = fma((double)v.y, (double)v.y, acc);
+    acc = fma((double)v.z, (double)v.z, acc);
+    return fma((double)v.w, (double)v.w, acc);
+}
+
+// |a|^2 partials per rhs
+__global__ __launch_bounds__(kB) void k_norm2_sites(size_t V, int nrhs, const float4 *__restrict__ a, double *partial) {
+    __shared__ double sh[kB];
+    const SiteBlock b = site_block(nrhs);
+    double acc = 0.0;
+    if (b.on)
+        for (size_t s = (size_t)blockIdx.x * b.sb + b.sl; s < V; s += (size_t)gridDim.x * b.sb) {
+            const float4 *pa = a + (s * nrhs + b.rhs) * 6;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) acc = sq4(pa[i], acc);
+        }
+    site_partial(b, nrhs, acc, sh, partial);
+}
+
+// x += alpha p ; r -= alpha q ; |r|^2 partials
+__global__ __launch_bounds__(kB) void k_update_xr_sites(size_t V, int nrhs, const double *__restrict__ alpha,
+                                                        float4 *__restrict__ x, const float4 *__restrict__ p,
+                                                        float4 *__restrict__ r, const float4 *__restrict__ q,
+                                                        double *partial) {
+    __shared__ double sh[kB];
+    const SiteBlock b = site_block(nrhs);
+    double acc = 0.0;
+    if (b.on) {
+        const double al = alpha[b.rhs];
+        for (size_t s = (size_t)blockIdx.x * b.sb + b.sl; s < V; s += (size_t)gridDim.x * b.sb) {
+            const size_t o = (s * nrhs + b.rhs) * 6;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const float4 pv = p[o + i], qv = q[o + i];
+                float4 xv = x[o + i], rv = r[o + i];
+                xv.x = (float)((double)xv.x + al * (double)pv.x);
+                xv.y = (float)((double)xv.y + al * (double)pv.y);
+                xv.z = (float)((double)xv.z + al * (double)pv.z);
+                xv.w = (float)((double)xv.w + al * (double)pv.w);
+                rv.x = (float)((double)rv.x - al * (double)qv.x);
+                rv.y = (float)((double)rv.y - al * (double)qv.y);
+                rv.z = (float)((double)rv.z - al * (double)qv.z);
+                rv.w = (float)((double)rv.w - al * (double)qv.w);
+                x[o + i] = xv;
+                r[o + i] = rv;
+                acc = sq4(rv, acc);
+            }
+        }
+    }
+    site_partial(b, nrhs, acc, sh, partial);
+}
+
+// p = z + beta p ; |p|^2 partials
+__global__ __launch_bounds__(kB) void k_update_p_sites(size_t V, int nrhs, const double *__restrict__ beta,
+                                                       const float4 *__restrict__ z, float4 *__restrict__ p,
+                                                       double *partial) {
+    __shared__ double sh[kB];
+    const SiteBlock b = site_block(nrhs);
+    double acc = 0.0;
+    if (b.on) {
+        const double be = beta[b.rhs];
+        for (size_t s = (size_t)blockIdx.x * b.sb + b.sl; s < V; s += (size_t)gridDim.x * b.sb) {
+            const size_t o = (s * nrhs + b.rhs) * 6;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const float4 zv = z[o + i];
+                float4 pv = p[o + i];
+                pv.x = (float)((double)zv.x + be * (double)pv.x);
+                pv.y = (float)((double)zv.y + be * (double)pv.y);
+                pv.z = (float)((double)zv.z + be * (double)pv.z);
+                pv.w = (float)((double)zv.w + be * (double)pv.w);
+                p[o + i] = pv;
+                acc = sq4(pv, acc);
+            }
+        }
+    }
+    site_partial(b, nrhs, acc, sh, partial);
+}
+
 int nblocks(size_t n) {
     size_t b = (n + kB - 1) / kB;
     return (int)(b < (size_t)kMaxBlocks ? b : (size_t)kMaxBlocks);
@@ -191,6 +311,27 @@ int nblocks(size_t n) {
 
 int dot_blocks(size_t n) { return nblocks(n); }
 
+int site_blocks(size_t V, int nrhs) {
+    const size_t sb = (size_t)(kB / nrhs);
+    const size_t b = (V + sb - 1) / sb;
+    return (int)(b < (size_t)kMaxBlocks ? b : (size_t)kMaxBlocks);
+}
+hipError_t norm2_sites(size_t V, int nrhs, const float *a, double *part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm2_sites, dim3(nblk), dim3(kB), 0, st, V, nrhs, (const float4 *)a, part);
+    return hipGetLastError();
+}
+hipError_t update_xr_sites(size_t V, int nrhs, const double *alpha, float *x, const float *p, float *r, const float *q,
+                           double *part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_xr_sites, dim3(nblk), dim3(kB), 0, st, V, nrhs, alpha, (float4 *)x, (const float4 *)p,
+                       (float4 *)r, (const float4 *)q, part);
+    return hipGetLastError();
+}
+hipError_t update_p_sites(size_t V, int nrhs, const double *beta, const float *z, float *p, double *part, int nblk,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_update_p_sites, dim3(nblk), dim3(kB), 0, st, V, nrhs, beta, (const float4 *)z, (float4 *)p,
+                       part);
+    return hipGetLastError();
+}
 template <typename T>
 hipError_t dot_partials_t(size_t n, int nrhs, const T *a, const T *b, double *part, int nblk,
                           hipStream_t st) {

@@ -36,6 +36,7 @@
 // and writes the output in runs of 96 B per right-hand side.  k_transpose
 // converts from and to the SoA layout of the other kernels.
 #include <cmath>
+#include <cstddef>
 
 #include "abi_internal.h"
 #include "kernels.h"
@@ -45,7 +46,7 @@ namespace mfma {
 
 constexpr int TX = 4, TY = 2, HX = TX + 2, HY = TY + 2, RP = HX * HY;  // 24 halo-tile points
 constexpr int RPP = RP + 1;  // odd point stride of the LDS ring (conflict-free column reads)
-constexpr int NTHR = 256;
+constexpr int NTHR = 512;
 constexpr int NWAVE = NTHR / 64;
 constexpr int SPW = TX * TY / NWAVE;  // consecutive sites of a tile row per wavefront (2)
 constexpr int NTB = 3;  // column tiles (4 right-hand sides each) per workgroup
@@ -98,26 +99,35 @@ struct Smem {
     // row << 16 | ring record of the lane's B column for the step's offset
     uint32_t ktab[3][KSTEPS][64];
     float scl[4 * NT], iscl[4 * NT];
+    // per halo point of a plane set (z-1..z+1 x the 6 x 4 halo tile): byte
+    // offset of its site record (from the block's first right-hand side)
+    // within a t plane, and its ring index (z plane, point)
+    uint2 ptab[3 * RP];
 };
 
 template <int NT>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_apply_mfma(const Args a) {
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply_mfma(const Args a) {
     constexpr int RN = Smem<NT>::RN;
-    constexpr int NREC = 3 * RN * RP;  // records of one plane set (three z planes)
-    constexpr int KMAX = (NREC + NTHR - 1) / NTHR;
+    constexpr int NPTS = 3 * RP;             // halo points of one plane set (three z planes)
+    constexpr int CPP = 3 * RN / 2;          // 16-byte chunks (two complex numbers) of a point's records
+    constexpr int PS = NTHR / CPP;           // points staged side by side (a thread keeps its chunk)
+    constexpr int KMAX = (NPTS + PS - 1) / PS;  // points per staging thread
     constexpr int NB = SPW;                   // staging batches per plane set (one per site)
-    constexpr int KB = (KMAX + NB - 1) / NB;  // records of a batch
+    constexpr int KB = (KMAX + NB - 1) / NB;  // points of a batch
     __shared__ Smem<NT> sm;
 
     // kernel-argument fields as locals: the lambdas below capture by
     // reference, and a captured kernel argument would be copied to scratch
     const int Lx = a.g.L[0], Ly = a.g.L[1], Lz = a.g.L[2], Lt = a.g.L[3];
     const size_t V = (size_t)a.g.V;
-    const float2 *__restrict__ in = a.in;
-    float2 *__restrict__ out = a.out;
-    const uint32_t *__restrict__ Wm = a.Wm;
+    // 64-bit bases are wave-uniform (scalar registers); the lanes add
+    // 32-bit byte offsets (the host bounds a t plane of the fields by 4 GiB)
+    const char *__restrict__ in = (const char *)a.in;
+    char *__restrict__ out = (char *)a.out;
+    const char *__restrict__ Wm = (const char *)a.Wm;
     const float diag = a.diag, slam = a.slam, srho = a.srho;
-    const size_t srec = (size_t)a.nrhs * 12;  // complex numbers per site record
+    const uint32_t recb = (uint32_t)a.nrhs * 96u;  // bytes of a site record (nrhs x 12 complex FP32)
+    const size_t planeb = (size_t)a.g.V / Lt * recb;  // bytes of a t plane
     const float lamw[5] = {0.0f, a.lam[1], a.lam[2], a.lam[3], a.lam[4]};
     const float rhow[5] = {0.0f, a.rho[1], a.rho[2], a.rho[3], a.rho[4]};
     const int tid = threadIdx.x, lane = tid & 63;
@@ -155,6 +165,15 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
         sm.iscl[tid] = 1.0f / s;
     }
 
+    for (int p = tid; p < NPTS; p += NTHR) {
+        const int pz = p / RP, rp = p % RP, hx = rp % HX, hy = rp / HX;
+        // the halo tile can reach past the lattice by more than one extent
+        // when Lx or Ly is smaller than the tile: a full modulo
+        const int xx = (x0 + hx - 1 + Lx) % Lx, yy = (y0 + hy - 1 + Ly) % Ly, zz = (z + pz - 1 + Lz) % Lz;
+        const uint32_t s3 = (uint32_t)xx + (uint32_t)Lx * ((uint32_t)yy + (uint32_t)Ly * (uint32_t)zz);
+        sm.ptab[p] = make_uint2(s3 * recb + (uint32_t)r0 * 96u, (uint32_t)(pz * RN * RPP + rp));
+    }
+
     // ---- lane constants of the MFMA operands, as an LDS table
     const int grp = lane >> 4, row = lane & 15;  // A/B: lane group (offset of the step), row or column
     const int acol = row < 15 ? row / 5 : 0;     // colour a of the A row (row 15 is padding)
@@ -179,51 +198,60 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
     const int ys = y0 + ky, xs0 = x0 + kx0;
     const int nval = ys < Ly ? max(0, min(SPW, Lx - xs0)) : 0;  // valid sites of the wavefront
     const int srp0 = kx0 + HX * ky;  // halo-tile point of site 0 minus the offset (1, 1)
-    auto site_of = [&](int x, int t) __attribute__((always_inline)) { return (size_t)x + (size_t)Lx * (ys + (size_t)Ly * (z + (size_t)Lz * t)); };
+    // sites past the lattice (ragged tiles) are computed on a clamped site
+    // and not stored, so that the walk has no branches
+    const int ysc = min(ys, Ly - 1);
+    auto site_of = [&](int i, int t) __attribute__((always_inline)) {
+        return (size_t)min(xs0 + i, Lx - 1) + (size_t)Lx * (ysc + (size_t)Ly * (z + (size_t)Lz * t));
+    };
 
     // epilogue lane (one column tile at a time): colour a = lane / 16, rhs r' = (lane % 16) / 4, spin s = lane % 4
     const int ea = lane >> 4, er4 = (lane >> 2) & 3, es = lane & 3;
 
     // ---- staging of one plane set (z-1..z+1 at time tt) in NB batches:
     // loads into registers, conversion to scaled FP16, stores into the ring.
-    // Every load is issued (straight-line code, so the compiler counts
-    // outstanding loads exactly): records past the plane set or of absent
-    // right-hand sides read a valid element and are zeroed afterwards.
-    float2 pre[KB][3];
-    uint32_t preh[KMAX][3];
+    // A thread keeps one 16-byte chunk of a point's records (two complex
+    // numbers of one right-hand side: 12 complex numbers, six chunks, per
+    // right-hand side) and takes every PS-th halo point, so that the lanes of
+    // a load cover whole cache lines of a site record.  Every load is issued
+    // (straight-line code, so the compiler counts outstanding loads exactly):
+    // points past the plane set read point 0 and are not stored, chunks of
+    // absent right-hand sides read a present one and are scaled by zero.
+    const int sch = tid % CPP, sp0 = tid / CPP;  // the thread's chunk and first point
+    const int sr = sch / 6;                      // its right-hand side in the block
+    const uint32_t rofs = (uint32_t)(min(sr, nr - 1) * 6 + sch % 6) * 16u;  // chunk within the block's records
+    // LDS byte address of the chunk's complex number h (0, 1) in ring record
+    // (0, 0) and the bytes per ring record of its array: colours 0, 1 in b01,
+    // colour 2 in b2
+    uint32_t lofs[2], lstr[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = 2 * (sch % 6) + h, rec = 4 * sr + k / 3, col = k % 3;  // spin k / 3
+        constexpr uint32_t b01 = offsetof(Smem<NT>, b01), b2 = offsetof(Smem<NT>, b2);
+        lstr[h] = col < 2 ? 8u : 4u;
+        lofs[h] = (col < 2 ? b01 + 4u * col : b2) + (uint32_t)rec * RPP * lstr[h];
+    }
+    float ssc = 0.0f;  // the chunk's scale (zero for an absent right-hand side), set after the scales are stored
+    float4 pre[KB];
+    uint32_t preh[KMAX][2];
+    auto point_of = [&](int k) __attribute__((always_inline)) {
+        const int p = sp0 + PS * k;
+        return p < NPTS ? p : 0;
+    };
     auto load_batch = [&](int tt, auto B) __attribute__((always_inline)) {
         constexpr int k0 = decltype(B)::value * KB, k1 = k0 + KB < KMAX ? k0 + KB : KMAX;
         const int tw = ((tt % Lt) + Lt) % Lt;
+        const char *pl = in + (size_t)tw * planeb;  // uniform
 #pragma unroll
-        for (int k = k0; k < k1; ++k) {
-            const int idx = tid + k * NTHR;
-            // records of one point consecutive: a point's right-hand sides are
-            // one contiguous piece of its site record
-            const int rec = idx % RN, rp = (idx / RN) % RP, pz = idx / (RP * RN);
-            const int r = rec >> 2, s = rec & 3;
-            const bool live = idx < NREC && r < nr;
-            const int hx = rp % HX, hy = rp / HX;
-            // the halo tile can reach past the lattice by more than one extent
-            // when Lx or Ly is smaller than the tile: a full modulo
-            const int xx = (x0 + hx - 1 + Lx) % Lx, yy = (y0 + hy - 1 + Ly) % Ly, zz = (z + pz - 1 + Lz) % Lz;
-            const size_t site = (size_t)xx + (size_t)Lx * (yy + (size_t)Ly * (zz + (size_t)Lz * tw));
-            const float2 *src = in + site * srec + (size_t)(r0 + min(r, nr - 1)) * 12 + 3 * s;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const float2 v = src[b];
-                pre[k - k0][b] = live ? v : make_float2(0.0f, 0.0f);
-            }
-        }
+        for (int k = k0; k < k1; ++k) pre[k - k0] = *(const float4 *)(pl + (sm.ptab[point_of(k)].x + rofs));
     };
     auto convert_batch = [&](auto B) __attribute__((always_inline)) {
         constexpr int k0 = decltype(B)::value * KB, k1 = k0 + KB < KMAX ? k0 + KB : KMAX;
 #pragma unroll
         for (int k = k0; k < k1; ++k) {
-            const int idx = tid + k * NTHR;
-            const float sc = sm.scl[(idx % RN) >> 2];
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                preh[k][b] = bits(h2{(_Float16)(pre[k - k0][b].x * sc), (_Float16)(pre[k - k0][b].y * sc)});
+            const float4 v = pre[k - k0];
+            preh[k][0] = bits(h2{(_Float16)(v.x * ssc), (_Float16)(v.y * ssc)});
+            preh[k][1] = bits(h2{(_Float16)(v.z * ssc), (_Float16)(v.w * ssc)});
         }
     };
     // batch b: convert batch b - 1, issue batch b; b = NB converts the last
@@ -233,15 +261,15 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
         if constexpr (b < NB) load_batch(tt, ic<b>{});
     };
     auto store_planes = [&](int tt) __attribute__((always_inline)) {
-        const int slot = ((tt % 3) + 3) % 3;
+        const uint32_t sbase = (uint32_t)(((tt % 3) + 3) % 3) * (3 * RN * RPP);
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            const int idx = tid + k * NTHR;
-            if (idx < NREC) {
-                const int rec = idx % RN, rp = (idx / RN) % RP, pz = idx / (RP * RN);
-                const int li = ((slot * 3 + pz) * RN + rec) * RPP + rp;
-                sm.b01[li] = make_uint2(preh[k][0], preh[k][1]);
-                sm.b2[li] = preh[k][2];
+            const int p = sp0 + PS * k;
+            if (p < NPTS && sp0 < PS) {  // (threads past PS x CPP only load)
+                const uint32_t li = sbase + sm.ptab[p].y;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    *(uint32_t *)((char *)&sm + (lofs[h] + li * lstr[h])) = preh[k][h];
             }
         }
     };
@@ -251,25 +279,32 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
     // consumed, one reduction step at a time (unconditionally, see above)
     uint32_t wa[KSTEPS][3];
     float2 px[NT];
+    const uint32_t awb = awoff * 4u;  // byte offset of the lane's row in a site's transporters
     auto load_rows = [&](size_t site, int q) __attribute__((always_inline)) {
-        const uint32_t *wp = Wm + site * WSITE + awoff + q * 36;
+        const char *ws = Wm + site * (WSITE * 4);  // uniform
 #pragma unroll
-        for (int b = 0; b < 3; ++b) wa[q][b] = __builtin_nontemporal_load(wp + b);
+        for (int b = 0; b < 3; ++b)
+            wa[q][b] = __builtin_nontemporal_load((const uint32_t *)(ws + (awb + (uint32_t)(q * 144 + 4 * b))));
+    };
+    // byte offset of the epilogue lane's output (column tile j) in a site record
+    auto out_ofs = [&](int j) __attribute__((always_inline)) {
+        return (uint32_t)((r0 + min(4 * j + er4, nr - 1)) * 12 + 3 * es + min(ea, 2)) * 8u;
     };
     auto load_px = [&](size_t site) __attribute__((always_inline)) {
+        const char *is = in + site * recb;  // uniform
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int r = min(4 * j + er4, nr - 1);
-            px[j] = in[site * srec + (size_t)(r0 + r) * 12 + 3 * es + min(ea, 2)];
-        }
+        for (int j = 0; j < NT; ++j) px[j] = *(const float2 *)(is + out_ofs(j));
     };
 
-    // ---- one site: 20 reduction steps, then the epilogue; the site at
-    // position SP of the wavefront issues staging batches 2 SP and 2 SP + 1
-    // of the plane set tt inside its reduction steps (after the waits for its
-    // own transporter rows, which then cover none of them)
+    // ---- one site: 20 reduction steps, then the epilogue (stored when the
+    // site is valid); the site at position SP of the wavefront issues
+    // staging batch SP of the plane set tt inside its first reduction step
+    // (after the wait for its own transporter rows, which then covers none of
+    // them).  The staging is issued on every step, also the last of a chunk
+    // (its plane set is then not stored): with no branch around the loads,
+    // their registers need no copies, which would wait for them at once.
     int tm = 0;  // t mod 3 (table of the current t)
-    auto compute_site = [&](size_t site, int srp, size_t next, bool stage, int tt, int sp) __attribute__((always_inline)) {
+    auto compute_site = [&](size_t site, int srp, size_t next, bool valid, int tt, int sp) __attribute__((always_inline)) {
         f4 acc[2][NT];
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -322,7 +357,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
                 acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, A0), Bj, acc[0][j], 0, 0, 0);
                 acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, A1), Bj, acc[1][j], 0, 0, 0);
             }
-            if (q == 0 && stage) static_for<0, NB>([&](auto B) __attribute__((always_inline)) {
+            if (q == 0) static_for<0, NB>([&](auto B) __attribute__((always_inline)) {
                 if (sp == decltype(B)::value) stage_step(tt, B);
             });
             __builtin_amdgcn_sched_barrier(0);  // keep the steps in order (bounded register use)
@@ -342,7 +377,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
             for (int e = 0; e < 4; ++e) scr[4 * grp + e][row] = make_float2(acc[0][j][e], acc[1][j][e]);
             __builtin_amdgcn_wave_barrier();
             const int r = 4 * j + er4;
-            if (lane < 48 && r < nr) {
+            if (valid && lane < 48 && r < nr) {
                 const float2 X0 = scr[5 * ea + 0][cb + es];
                 const float2 X1 = scr[5 * ea + 1][cb + sxy];
                 const float2 X2 = scr[5 * ea + 2][cb + sxy];
@@ -357,21 +392,22 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
                 o.y = fmaf(slam * X0.y + srho * gim, is, diag * px[j].y);
                 // the 48 lanes of a column tile write 384 contiguous bytes of
                 // the site record
-                out[site * srec + (size_t)(r0 + r) * 12 + 3 * es + ea] = o;
+                *(float2 *)(out + site * recb + out_ofs(j)) = o;
             }
             __builtin_amdgcn_wave_barrier();
         }
         load_px(next);
     };
 
-    // ---- t walk; the wavefront's sites in order (site 0, t), ..., (site nval-1, t), (site 0, t + 1), ...
-    if (nval > 0) {
-        const size_t first = site_of(xs0, t0);
+    // ---- t walk; the wavefront's sites in order (site 0, t), (site 1, t), (site 0, t + 1), ...
+    {
+        const size_t first = site_of(0, t0);
 #pragma unroll
         for (int q = 0; q < KSTEPS; ++q) load_rows(first, q);
         load_px(first);
     }
-    __syncthreads();  // scales, table
+    __syncthreads();  // scales, tables
+    ssc = sr < nr ? sm.scl[sr] : 0.0f;
     for (int k = 0; k < 3; ++k) {
         static_for<0, NB + 1>([&](auto B) __attribute__((always_inline)) { stage_step(t0 - 1 + k, B); });
         store_planes(t0 - 1 + k);
@@ -382,19 +418,12 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(1, 1))) vo
         tm = t % 3;
 #pragma unroll
         for (int i = 0; i < SPW; ++i) {
-            if (i < nval) {
-                // next site of the chain (the current one when there is none,
-                // so that every load is issued)
-                const size_t cur = site_of(xs0 + i, t);
-                const size_t next = i + 1 < nval ? site_of(xs0 + i + 1, t) : (more ? site_of(xs0, t + 1) : cur);
-                compute_site(cur, srp0 + i, next, more, t + 2, i);
-            } else if (more) {
-                static_for<0, NB>([&](auto B) __attribute__((always_inline)) {
-                    if (i == decltype(B)::value) stage_step(t + 2, B);
-                });
-            }
+            // next site of the chain (after the last t of the chunk: site 0
+            // of this t again, so that every load is issued)
+            const size_t next = i + 1 < SPW ? site_of(i + 1, t) : site_of(0, more ? t + 1 : t);
+            compute_site(site_of(i, t), srp0 + i, next, i < nval, t + 2, i);
         }
-        if (more) stage_step(t + 2, ic<NB>{});
+        stage_step(t + 2, ic<NB>{});
         __syncthreads();  // the ring slot of t - 1 is free
         if (more) store_planes(t + 2);
         __syncthreads();
@@ -673,6 +702,7 @@ bri_status bri_apply_mfma(bri_dims d, const void *W_mfma, double mass, const flo
         return fail(BRI_E_ARG, "null or misaligned (16 B) pointer");
     const size_t sb = (size_t)g.V * 12 * nrhs * 8;
     if (overlap(in, sb, out, sb)) return fail(BRI_E_ARG, "in and out overlap");
+    if (sb / g.L[3] > 0xffffffffull) return fail(BRI_E_UNSUPPORTED, "a t plane of the spinor field exceeds 4 GiB");
     const double diag = (coef ? coef[0] : lam_k(0)) + mass;
     return hip_check(apply_mfma(g, W_mfma, (const float2 *)in, (float2 *)out, nrhs, diag, coef, dagger != 0, bound2, 1,
                                 0, (hipStream_t)stream),

@@ -45,12 +45,10 @@ hipError_t zero(size_t n, T *p, hipStream_t st) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t r_hi, dx_hi, e, r, p, q, z, part, red, stv, scale, unscale, sin, sout, bnd, total;
+    size_t r_hi, dx_hi, e, r, p, q, z, part, red, stv, scale, unscale, total;
 };
 
-// sites: the matrix-core inner apply's site-major copies of its input and
-// output and the per-column bounds of the input
-Layout layout(size_t n, int nrhs, size_t tbytes, bool sites = false) {
+Layout layout(size_t n, int nrhs, size_t tbytes) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -67,15 +65,10 @@ Layout layout(size_t n, int nrhs, size_t tbytes, bool sites = false) {
     L.q = take(lv);
     L.z = take(lv);
     L.part = take((size_t)nrhs * 1024 * 2 * sizeof(double));
-    L.red = take((size_t)3 * nrhs * 2 * sizeof(double));
+    L.red = take((size_t)4 * nrhs * 2 * sizeof(double));
     L.stv = take((size_t)7 * nrhs * sizeof(double));
     L.scale = take((size_t)nrhs * sizeof(double));
     L.unscale = take((size_t)nrhs * sizeof(double));
-    if (sites) {
-        L.sin = take(lv);
-        L.sout = take(lv);
-        L.bnd = take((size_t)nrhs * sizeof(double));
-    }
     L.total = o;
     return L;
 }
@@ -100,9 +93,15 @@ struct Ctx {
 #define BRI_HIP(expr, what) BRI_TRY(hip_check((expr), what))
 
 template <typename T>
-bri_status norm2(const Ctx &c, const T *a, double *out2) {
-    const int nb = dot_blocks(c.n);
+bri_status norm2(const Ctx &c, const T *a, double *out2, bool sites = false) {
     double *part = (double *)(c.w + c.L.part);
+    if (sites) {
+        const int nb = site_blocks(c.g.V, c.nrhs);
+        BRI_HIP(norm2_sites(c.g.V, c.nrhs, (const float *)a, part, nb, c.st), "norm partials");
+        BRI_HIP(dot_finish(c.nrhs, part, nb, out2, c.st), "norm finish");
+        return BRI_OK;
+    }
+    const int nb = dot_blocks(c.n);
     BRI_HIP(dot_partials_t<T>(c.n, c.nrhs, a, a, part, nb, c.st), "norm partials");
     BRI_HIP(dot_finish(c.nrhs, part, nb, out2, c.st), "norm finish");
     return BRI_OK;
@@ -115,6 +114,10 @@ bri_status fetch(const Ctx &c, const double *dev, double *host, size_t count) {
 }
 
 // inner CGNE on D e = r with e = 0 initially; r holds the right-hand side.
+// With the matrix-core operator (op.mfma, T = float) every inner vector is
+// site-major [V][nrhs][24], the layout of that apply, and each apply takes
+// the squared 2-norm of its input, which the iteration computes anyway, as
+// the bound of its components.
 template <typename T>
 bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, int max_it, int check_every,
                       int *iters, int *applies) {
@@ -122,41 +125,50 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
     T *q = (T *)(c.w + c.L.q), *z = (T *)(c.w + c.L.z);
     double *part = (double *)(c.w + c.L.part);
     double *qq2 = (double *)(c.w + c.L.red), *rr2 = qq2 + 2 * c.nrhs, *zz2 = rr2 + 2 * c.nrhs;
-    // the operator; the matrix-core apply works on site-major copies (the
-    // transposition into them also gives the per-column bounds it needs)
+    double *pp2 = zz2 + 2 * c.nrhs;
+    const bool sites = op.mfma;
     const double diag = (op.coef ? op.coef[0] : lam_k(0)) + c.mass;
-    auto apply = [&](const T *in, T *out, bool dag) -> bri_status {
-        if (op.mfma) {
-            float2 *si = (float2 *)(c.w + c.L.sin), *so = (float2 *)(c.w + c.L.sout);
-            double *bnd = (double *)(c.w + c.L.bnd);
-            BRI_HIP(spinor_sites(c.g, c.nrhs, (const float2 *)in, si, true, bnd, c.st), "to site-major");
-            BRI_HIP(apply_mfma(c.g, op.W, si, so, c.nrhs, diag, op.coef, dag, bnd, 1, 0, c.st), "apply (matrix cores)");
-            return hip_check(spinor_sites(c.g, c.nrhs, so, (float2 *)out, false, nullptr, c.st), "from site-major");
-        }
+    auto apply = [&](const T *in, T *out, bool dag, const double *in2) -> bri_status {
+        if (sites)
+            return hip_check(apply_mfma(c.g, op.W, (const float2 *)in, (float2 *)out, c.nrhs, diag, op.coef, dag, in2,
+                                        2, 0, c.st),
+                             "apply (matrix cores)");
         return apply_op(c.d, op, sp, c.mass, in, out, c.nrhs, c.st, dag);
     };
     double *stv = (double *)(c.w + c.L.stv);
-    const int nb = dot_blocks(c.n);
+    const int nb = sites ? site_blocks(c.g.V, c.nrhs) : dot_blocks(c.n);
     const size_t bytes = c.n * c.nrhs * sizeof(T);
 
     BRI_HIP(zero(c.n * c.nrhs, e, c.st), "zero");
-    BRI_TRY(norm2<T>(c, r, rr2));
-    BRI_TRY(apply(r, z, !c.dag));
+    BRI_TRY(norm2<T>(c, r, rr2, sites));
+    BRI_TRY(apply(r, z, !c.dag, rr2));
     ++*applies;
-    BRI_TRY(norm2<T>(c, z, zz2));
+    BRI_TRY(norm2<T>(c, z, zz2, sites));
     BRI_HIP(cg_init(c.nrhs, stv, rr2, zz2, rel * rel, c.st), "cg init");
     BRI_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, c.st), "copy");
+    if (sites) BRI_HIP(hipMemcpyAsync(pp2, zz2, 2 * c.nrhs * sizeof(double), hipMemcpyDeviceToDevice, c.st), "copy");
     std::vector<double> hs(7 * c.nrhs);
     for (int it = 1; it <= max_it; ++it) {
-        BRI_TRY(apply(p, q, c.dag));
-        BRI_TRY(norm2<T>(c, q, qq2));
+        BRI_TRY(apply(p, q, c.dag, pp2));
+        BRI_TRY(norm2<T>(c, q, qq2, sites));
         BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
-        BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
+        if (sites)
+            BRI_HIP(update_xr_sites(c.g.V, c.nrhs, stv + 3 * c.nrhs, (float *)e, (const float *)p, (float *)r,
+                                    (const float *)q, part, nb, c.st),
+                    "update x,r");
+        else
+            BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
         BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
-        BRI_TRY(apply(r, z, !c.dag));
-        BRI_TRY(norm2<T>(c, z, zz2));
+        BRI_TRY(apply(r, z, !c.dag, rr2));
+        BRI_TRY(norm2<T>(c, z, zz2, sites));
         BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
-        BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
+        if (sites) {
+            BRI_HIP(update_p_sites(c.g.V, c.nrhs, stv + 4 * c.nrhs, (const float *)z, (float *)p, part, nb, c.st),
+                    "update p");
+            BRI_HIP(dot_finish(c.nrhs, part, nb, pp2, c.st), "pp finish");
+        } else {
+            BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
+        }
         *applies += 2;
         *iters = it;
         if (it % check_every == 0 || it == max_it) {
@@ -201,7 +213,7 @@ static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc
     if (!aligned(hi.W) || !aligned(b) || !aligned(x) || (mixed && !aligned(lo.W)))
         return fail(BRI_E_ARG, "null or misaligned pointer");
     const size_t n = (size_t)24 * g.V;
-    const Layout L = layout(n, nrhs, mixed ? sizeof(float) : sizeof(double), p->inner_mfma == 1);
+    const Layout L = layout(n, nrhs, mixed ? sizeof(float) : sizeof(double));
     if (!aligned(work) || work_bytes < L.total)
         return fail(BRI_E_WORKSPACE, "workspace too small: need %zu bytes", L.total);
     const size_t vb = n * nrhs * sizeof(double);
@@ -258,10 +270,19 @@ static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc
             // the last cycle then stops early instead of overshooting
             const double need = worst > 0.0 ? 0.5 * p->tol / worst : 0.5;
             const double rel = std::fmin(0.5, std::fmax(p->inner_tol, need));
-            float *r_lo = (float *)(c.w + L.r);
-            BRI_HIP((convert<double, float>(n, nrhs, r_hi, r_lo, scale, c.st)), "convert");
+            float *r_lo = (float *)(c.w + L.r), *e_lo = (float *)(c.w + L.e);
+            // the matrix-core inner solve works on site-major vectors: the
+            // scaled residual goes there through q, the correction comes back
+            // through q (free outside the inner solve)
+            float *t_lo = (float *)(c.w + L.q);
+            BRI_HIP((convert<double, float>(n, nrhs, r_hi, lo.mfma ? t_lo : r_lo, scale, c.st)), "convert");
+            if (lo.mfma)
+                BRI_HIP(spinor_sites(g, nrhs, (const float2 *)t_lo, (float2 *)r_lo, true, nullptr, c.st), "to site-major");
             BRI_TRY(inner_cgne<float>(c, lo, BRI_F32, rel, p->max_iter - iters, p->check_every, &it, &applies));
-            BRI_HIP(accum<float>(n, nrhs, (const float *)(c.w + L.e), x, unscale, c.st), "accumulate");
+            if (lo.mfma)
+                BRI_HIP(spinor_sites(g, nrhs, (const float2 *)e_lo, (float2 *)t_lo, false, nullptr, c.st),
+                        "from site-major");
+            BRI_HIP(accum<float>(n, nrhs, lo.mfma ? t_lo : e_lo, x, unscale, c.st), "accumulate");
         } else {
             // plain FP64: aim the inner solve at the final tolerance of the worst column
             const double rel = worst > 0.0 ? std::fmin(0.5, 0.5 * p->tol / worst) : 0.5;
@@ -321,7 +342,7 @@ size_t bri_solve_workspace_bytes(bri_dims d, const bri_solve_params *p, int32_t 
     Geom g;
     if (!p || !dims_ok(d, &g) || nrhs < 1 || nrhs > BRI_MAX_RHS) return 0;
     const size_t tb = p->inner_prec == BRI_F64 ? sizeof(double) : sizeof(float);
-    return layout((size_t)24 * g.V, nrhs, tb, p->inner_mfma == 1).total;
+    return layout((size_t)24 * g.V, nrhs, tb).total;
 }
 
 bri_status bri_solve_cgne(bri_dims d, const bri_solve_params *p, const void *W_hi, const void *W_lo,
