@@ -22,10 +22,11 @@
 // t over a chunk.  For each t it needs psi on the planes (z-1..z+1) x
 // (t-1..t+1) over the tile and a one-site halo: a ring of nine planes in LDS
 // (FP16, all right-hand sides of the block), three of which are replaced per
-// step, loaded into registers during the previous step.  Each wavefront
-// computes two sites per step: 20 reduction steps of four offsets, six MFMAs
-// each (2 row tiles x 3 column tiles), then an epilogue through LDS that
-// applies the gamma matrices, rescales and adds the diagonal term in FP32.
+// step, loaded into registers during the previous step.  Eight wavefronts,
+// two per SIMD so that one issues while the other waits, each compute one
+// site per step: 20 reduction steps of four offsets, six MFMAs each (2 row
+// tiles x 3 column tiles), then an epilogue through LDS that applies the
+// gamma matrices, rescales and adds the diagonal term in FP32.
 //
 // The transporters come from a site-major FP16 store (bri_pack_w_mfma):
 // for each site the 80 offsets in the order of the 80-offset store, each a
@@ -48,7 +49,7 @@ constexpr int TX = 4, TY = 2, HX = TX + 2, HY = TY + 2, RP = HX * HY;  // 24 hal
 constexpr int RPP = RP + 1;  // odd point stride of the LDS ring (conflict-free column reads)
 constexpr int NTHR = 512;
 constexpr int NWAVE = NTHR / 64;
-constexpr int SPW = TX * TY / NWAVE;  // consecutive sites of a tile row per wavefront (2)
+constexpr int SPW = TX * TY / NWAVE;  // consecutive sites of a tile row per wavefront (1)
 constexpr int NTB = 3;  // column tiles (4 right-hand sides each) per workgroup
 constexpr int NPT = 80;        // offsets
 constexpr int KSTEPS = NPT / 4;  // reduction steps of four offsets
@@ -69,6 +70,7 @@ __host__ __device__ constexpr int comp(int p, int mu) {
 struct Args {
     Geom g;
     int ntx, nty, ntc, tlen, nrhs;  // nrhs: right-hand sides of a site record (12 complex each)
+    int gx, gy, gz;                 // tiles per block group in x, y, z (divisors of ntx, nty, Lz)
     const uint32_t *Wm;     // site-major FP16 store, one complex per 32-bit word
     const float2 *in;       // site-major: [V][nrhs][12]
     float2 *out;
@@ -134,17 +136,26 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index (uniform)
 
     // right-hand-side block fastest: the blocks of a tile run back to back
-    // on one XCD and share the transporter rows through its L2
+    // on one XCD and share the transporter rows through its L2; then the
+    // tiles of a gx x gy x gz group, so that the workgroups an XCD runs at
+    // one time are neighbours in x, y and z and share their halo planes
+    // through its L2
     const int nrb = (a.nrhs + 4 * NT - 1) / (4 * NT);
     int rest = xcd_block(blockIdx.x, gridDim.x);
     const int rb = rest % nrb;
     rest /= nrb;
-    const int bx = rest % a.ntx;
-    rest /= a.ntx;
-    const int by = rest % a.nty;
-    rest /= a.nty;
-    const int z = rest % Lz;
-    const int tc = rest / Lz;
+    const int ix = rest % a.gx;
+    rest /= a.gx;
+    const int iy = rest % a.gy;
+    rest /= a.gy;
+    const int iz = rest % a.gz;
+    rest /= a.gz;
+    const int bx = (rest % (a.ntx / a.gx)) * a.gx + ix;
+    rest /= a.ntx / a.gx;
+    const int by = (rest % (a.nty / a.gy)) * a.gy + iy;
+    rest /= a.nty / a.gy;
+    const int z = (rest % (Lz / a.gz)) * a.gz + iz;
+    const int tc = rest / (Lz / a.gz);
     const int t0 = tc * a.tlen, t1 = min(t0 + a.tlen, Lt);
     const int r0 = rb * 4 * NT, nr = min(4 * NT, a.nrhs - r0);
     const int x0 = bx * TX, y0 = by * TY;
@@ -312,12 +323,13 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
             for (int j = 0; j < NT; ++j) acc[m][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
         const uint32_t(*kt)[64] = sm.ktab[tm];
         // B operands of a step: psi(x + n) for the step's four offsets, all
-        // column tiles; two static buffers (step parity), the padding word of
-        // every operand zeroed once
-        u4 Bb[2][NT];
+        // column tiles; read from LDS two steps ahead into three static
+        // buffers (step mod 3), the padding word of every operand zeroed once
+        constexpr int BD = 3;  // B buffers
+        u4 Bb[BD][NT];
         u4 A0 = u4{0u, 0u, 0u, 0u}, A1 = u4{0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < BD; ++h)
 #pragma unroll
             for (int j = 0; j < NT; ++j) Bb[h][j] = u4{0u, 0u, 0u, 0u};
         auto read_b = [&](uint32_t k, u4 (&B)[NT]) {
@@ -330,17 +342,18 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
                 B[j].z = sm.b2[li + 16 * j * RPP];
             }
         };
-        uint32_t kc = kt[0][lane], kn = kt[1][lane];
-        read_b(kc, Bb[0]);
+        // table words of steps q, q + 1, q + 2 (each step reads the one of q + 3)
+        uint32_t kw[BD];
+#pragma unroll
+        for (int h = 0; h < BD; ++h) kw[h] = kt[h][lane];
+        read_b(kw[0], Bb[0]);
+        read_b(kw[1], Bb[1]);
 #pragma unroll
         for (int q = 0; q < KSTEPS; ++q) {
-            u4(&B)[NT] = Bb[q & 1];
-            const uint32_t kq = kc;
-            if (q + 1 < KSTEPS) {  // operands of the next step
-                read_b(kn, Bb[(q + 1) & 1]);
-                kc = kn;
-                if (q + 2 < KSTEPS) kn = kt[q + 2][lane];
-            }
+            u4(&B)[NT] = Bb[q % BD];
+            const uint32_t kq = kw[q % BD];
+            if (q + 2 < KSTEPS) read_b(kw[(q + 2) % BD], Bb[(q + 2) % BD]);  // operands two steps ahead
+            if (q + BD < KSTEPS) kw[q % BD] = kt[q + BD][lane];
             const h2 m1 = hv((kq >> 16) * 0x10001u);  // (c, c)
             const h2 m0 = h2{m1.x, -m1.y};
             const h2 w0 = hv(wa[q][0]), w1 = hv(wa[q][1]), w2 = hv(wa[q][2]);
@@ -609,6 +622,14 @@ hipError_t apply_mfma(const Geom &g, const void *Wm, const float2 *in, float2 *o
     a.tlen = tlen > 0 ? (tlen < g.L[3] ? tlen : g.L[3]) : (g.L[3] < 64 ? g.L[3] : 64);
     a.ntc = (g.L[3] + a.tlen - 1) / a.tlen;
     a.nrhs = nrhs;
+    // block groups of up to 2 x 4 x 4 tiles (32 workgroups, one per CU of an XCD)
+    auto group = [](int n, int want) {
+        while (want > 1 && n % want) want /= 2;
+        return want;
+    };
+    a.gx = group(a.ntx, 2);
+    a.gy = group(a.nty, 4);
+    a.gz = group(g.L[2], 4);
     a.Wm = (const uint32_t *)Wm;
     a.in = in;
     a.out = out;
