@@ -782,7 +782,7 @@ def main():
             "mfma_issued_TFs": issued / (ms * 1e-3) / 1e12,
             "mfma_frac_fp16_dense": issued / (ms * 1e-3) / 1e12 / FP16_PEAK_TFS,
             "to_sites_with_bound_ms": float(np.mean(pb)), "from_sites_ms": float(np.mean(pf)),
-            "kernel": "k_apply_mfma<3> (4x2 tile, 12 rhs per workgroup, site-major spinors)"}
+            "kernel": "k_apply_mfma<3> (4x2 tile, 8 wavefronts, 12 rhs per workgroup, site-major spinors)"}
         del Wm, b2, o12, x12, xs
         x12 = bri.bri_pack_spinor(DIMS, torch.from_numpy(src).to(dev), bri.F64)
         W64 = bri.bri_build_transporters(DIMS, U64, bri.F64, 80)
