@@ -184,41 +184,48 @@ __global__ void k_init(int nrhs, double *st, const double *rr2, const double *zz
 }
 
 // ---- site-major fields [V][nrhs][24] (FP32): the inner solve on the matrix
-// cores keeps its vectors in the layout of that apply.  A thread owns one
-// record (a site's 24 reals of one right-hand side, 96 contiguous bytes); a
-// workgroup covers SB = kB / nrhs consecutive sites per pass, so the records
-// of its threads are one contiguous piece and every thread keeps its
-// right-hand side.  The per-rhs block sums are a tree over the SB sites in a
-// fixed order, the partials then added by k_dot_finish: deterministic.
+// cores keeps its vectors in the layout of that apply.  A site's records are
+// 6 nrhs chunks of 16 bytes; a workgroup of 6 nrhs m threads covers m
+// consecutive sites per pass, a thread one chunk, so that the lanes of every
+// load and store are consecutive 16-byte pieces and a thread keeps its
+// right-hand side.  The per-rhs block sums are fixed-order: the six chunks
+// of a record, then a tree over the m sites; the partials are then added by
+// k_dot_finish.  Deterministic.
+constexpr int kSiteMax = 6 * 64;  // largest workgroup (64 right-hand sides, one site per pass)
 struct SiteBlock {
-    int sb, rhs, sl;  // sites per pass, the thread's right-hand side and site in the pass
-    bool on;          // thread inside the SB x nrhs records
+    int cps, m, sl, c;  // chunks per site, sites per pass, the thread's site in the pass and chunk
+    bool on;            // thread inside the m x cps chunks
 };
 __device__ __forceinline__ SiteBlock site_block(int nrhs) {
     SiteBlock b;
-    b.sb = kB / nrhs;
-    b.sl = threadIdx.x / nrhs;
-    b.rhs = threadIdx.x % nrhs;
-    b.on = b.sl < b.sb;
+    b.cps = 6 * nrhs;
+    b.m = blockDim.x / b.cps;
+    b.sl = threadIdx.x / b.cps;
+    b.c = threadIdx.x % b.cps;
+    b.on = b.sl < b.m;
     return b;
 }
-// per-rhs sum over the block's threads in a fixed tree order; the result for
-// rhs lands in sh[rhs]
-__device__ __forceinline__ void site_block_sum(const SiteBlock &b, int nrhs, double v, double *sh) {
-    sh[threadIdx.x] = b.on ? v : 0.0;
+__device__ __forceinline__ void site_partial(const SiteBlock &b, int nrhs, double v, double *sh, double *partial) {
+    const int t = threadIdx.x;
+    sh[t] = b.on ? v : 0.0;
+    __syncthreads();
+    const bool lead = b.on && b.c % 6 == 0;  // first chunk of a record
+    if (lead) {
+        double r = sh[t];
+#pragma unroll
+        for (int i = 1; i < 6; ++i) r += sh[t + i];
+        sh[t] = r;
+    }
     __syncthreads();
     int p2 = 1;
-    while (p2 < b.sb) p2 <<= 1;
+    while (p2 < b.m) p2 <<= 1;
     for (int h = p2 >> 1; h > 0; h >>= 1) {
-        if (b.on && b.sl < h && b.sl + h < b.sb) sh[threadIdx.x] += sh[threadIdx.x + h * nrhs];
+        if (lead && b.sl < h && b.sl + h < b.m) sh[t] += sh[t + h * b.cps];
         __syncthreads();
     }
-}
-__device__ __forceinline__ void site_partial(const SiteBlock &b, int nrhs, double v, double *sh, double *partial) {
-    site_block_sum(b, nrhs, v, sh);
-    if ((int)threadIdx.x < nrhs) {
-        partial[((size_t)threadIdx.x * gridDim.x + blockIdx.x) * 2 + 0] = sh[threadIdx.x];
-        partial[((size_t)threadIdx.x * gridDim.x + blockIdx.x) * 2 + 1] = 0.0;
+    if (t < nrhs) {
+        partial[((size_t)t * gridDim.x + blockIdx.x) * 2 + 0] = sh[6 * t];
+        partial[((size_t)t * gridDim.x + blockIdx.x) * 2 + 1] = 0.0;
     }
 }
 __device__ __forceinline__ double sq4(float4 v, double acc) {
@@ -229,74 +236,66 @@ __device__ __forceinline__ double sq4(float4 v, double acc) {
 }
 
 // |a|^2 partials per rhs
-__global__ __launch_bounds__(kB) void k_norm2_sites(size_t V, int nrhs, const float4 *__restrict__ a, double *partial) {
-    __shared__ double sh[kB];
+__global__ __launch_bounds__(kSiteMax) void k_norm2_sites(size_t V, int nrhs, const float4 *__restrict__ a,
+                                                          double *partial) {
+    __shared__ double sh[kSiteMax];
     const SiteBlock b = site_block(nrhs);
     double acc = 0.0;
     if (b.on)
-        for (size_t s = (size_t)blockIdx.x * b.sb + b.sl; s < V; s += (size_t)gridDim.x * b.sb) {
-            const float4 *pa = a + (s * nrhs + b.rhs) * 6;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) acc = sq4(pa[i], acc);
-        }
+        for (size_t s = (size_t)blockIdx.x * b.m + b.sl; s < V; s += (size_t)gridDim.x * b.m)
+            acc = sq4(a[s * b.cps + b.c], acc);
     site_partial(b, nrhs, acc, sh, partial);
 }
 
 // x += alpha p ; r -= alpha q ; |r|^2 partials
-__global__ __launch_bounds__(kB) void k_update_xr_sites(size_t V, int nrhs, const double *__restrict__ alpha,
-                                                        float4 *__restrict__ x, const float4 *__restrict__ p,
-                                                        float4 *__restrict__ r, const float4 *__restrict__ q,
-                                                        double *partial) {
-    __shared__ double sh[kB];
+__global__ __launch_bounds__(kSiteMax) void k_update_xr_sites(size_t V, int nrhs, const double *__restrict__ alpha,
+                                                              float4 *__restrict__ x, const float4 *__restrict__ p,
+                                                              float4 *__restrict__ r, const float4 *__restrict__ q,
+                                                              double *partial) {
+    __shared__ double sh[kSiteMax];
     const SiteBlock b = site_block(nrhs);
     double acc = 0.0;
     if (b.on) {
-        const double al = alpha[b.rhs];
-        for (size_t s = (size_t)blockIdx.x * b.sb + b.sl; s < V; s += (size_t)gridDim.x * b.sb) {
-            const size_t o = (s * nrhs + b.rhs) * 6;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                const float4 pv = p[o + i], qv = q[o + i];
-                float4 xv = x[o + i], rv = r[o + i];
-                xv.x = (float)((double)xv.x + al * (double)pv.x);
-                xv.y = (float)((double)xv.y + al * (double)pv.y);
-                xv.z = (float)((double)xv.z + al * (double)pv.z);
-                xv.w = (float)((double)xv.w + al * (double)pv.w);
-                rv.x = (float)((double)rv.x - al * (double)qv.x);
-                rv.y = (float)((double)rv.y - al * (double)qv.y);
-                rv.z = (float)((double)rv.z - al * (double)qv.z);
-                rv.w = (float)((double)rv.w - al * (double)qv.w);
-                x[o + i] = xv;
-                r[o + i] = rv;
-                acc = sq4(rv, acc);
-            }
+        const double al = alpha[b.c / 6];
+        for (size_t s = (size_t)blockIdx.x * b.m + b.sl; s < V; s += (size_t)gridDim.x * b.m) {
+            const size_t o = s * b.cps + b.c;
+            const float4 pv = p[o], qv = q[o];
+            float4 xv = x[o], rv = r[o];
+            xv.x = (float)((double)xv.x + al * (double)pv.x);
+            xv.y = (float)((double)xv.y + al * (double)pv.y);
+            xv.z = (float)((double)xv.z + al * (double)pv.z);
+            xv.w = (float)((double)xv.w + al * (double)pv.w);
+            rv.x = (float)((double)rv.x - al * (double)qv.x);
+            rv.y = (float)((double)rv.y - al * (double)qv.y);
+            rv.z = (float)((double)rv.z - al * (double)qv.z);
+            rv.w = (float)((double)rv.w - al * (double)qv.w);
+            x[o] = xv;
+            r[o] = rv;
+            acc = sq4(rv, acc);
         }
     }
     site_partial(b, nrhs, acc, sh, partial);
 }
 
 // p = z + beta p ; |p|^2 partials
-__global__ __launch_bounds__(kB) void k_update_p_sites(size_t V, int nrhs, const double *__restrict__ beta,
-                                                       const float4 *__restrict__ z, float4 *__restrict__ p,
-                                                       double *partial) {
-    __shared__ double sh[kB];
+__global__ __launch_bounds__(kSiteMax) void k_update_p_sites(size_t V, int nrhs, const double *__restrict__ beta,
+                                                             const float4 *__restrict__ z, float4 *__restrict__ p,
+                                                             double *partial) {
+    __shared__ double sh[kSiteMax];
     const SiteBlock b = site_block(nrhs);
     double acc = 0.0;
     if (b.on) {
-        const double be = beta[b.rhs];
-        for (size_t s = (size_t)blockIdx.x * b.sb + b.sl; s < V; s += (size_t)gridDim.x * b.sb) {
-            const size_t o = (s * nrhs + b.rhs) * 6;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                const float4 zv = z[o + i];
-                float4 pv = p[o + i];
-                pv.x = (float)((double)zv.x + be * (double)pv.x);
-                pv.y = (float)((double)zv.y + be * (double)pv.y);
-                pv.z = (float)((double)zv.z + be * (double)pv.z);
-                pv.w = (float)((double)zv.w + be * (double)pv.w);
-                p[o + i] = pv;
-                acc = sq4(pv, acc);
-            }
+        const double be = beta[b.c / 6];
+        for (size_t s = (size_t)blockIdx.x * b.m + b.sl; s < V; s += (size_t)gridDim.x * b.m) {
+            const size_t o = s * b.cps + b.c;
+            const float4 zv = z[o];
+            float4 pv = p[o];
+            pv.x = (float)((double)zv.x + be * (double)pv.x);
+            pv.y = (float)((double)zv.y + be * (double)pv.y);
+            pv.z = (float)((double)zv.z + be * (double)pv.z);
+            pv.w = (float)((double)zv.w + be * (double)pv.w);
+            p[o] = pv;
+            acc = sq4(pv, acc);
         }
     }
     site_partial(b, nrhs, acc, sh, partial);
@@ -311,25 +310,31 @@ int nblocks(size_t n) {
 
 int dot_blocks(size_t n) { return nblocks(n); }
 
+// sites per pass of a site-major workgroup (6 nrhs m threads, m up to 256 / (6 nrhs))
+static int site_m(int nrhs) {
+    const int m = kB / (6 * nrhs);
+    return m > 0 ? m : 1;
+}
 int site_blocks(size_t V, int nrhs) {
-    const size_t sb = (size_t)(kB / nrhs);
-    const size_t b = (V + sb - 1) / sb;
+    const size_t m = (size_t)site_m(nrhs);
+    const size_t b = (V + m - 1) / m;
     return (int)(b < (size_t)kMaxBlocks ? b : (size_t)kMaxBlocks);
 }
 hipError_t norm2_sites(size_t V, int nrhs, const float *a, double *part, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_norm2_sites, dim3(nblk), dim3(kB), 0, st, V, nrhs, (const float4 *)a, part);
+    hipLaunchKernelGGL(k_norm2_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, (const float4 *)a,
+                       part);
     return hipGetLastError();
 }
 hipError_t update_xr_sites(size_t V, int nrhs, const double *alpha, float *x, const float *p, float *r, const float *q,
                            double *part, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_update_xr_sites, dim3(nblk), dim3(kB), 0, st, V, nrhs, alpha, (float4 *)x, (const float4 *)p,
-                       (float4 *)r, (const float4 *)q, part);
+    hipLaunchKernelGGL(k_update_xr_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, alpha,
+                       (float4 *)x, (const float4 *)p, (float4 *)r, (const float4 *)q, part);
     return hipGetLastError();
 }
 hipError_t update_p_sites(size_t V, int nrhs, const double *beta, const float *z, float *p, double *part, int nblk,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_update_p_sites, dim3(nblk), dim3(kB), 0, st, V, nrhs, beta, (const float4 *)z, (float4 *)p,
-                       part);
+    hipLaunchKernelGGL(k_update_p_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, beta,
+                       (const float4 *)z, (float4 *)p, part);
     return hipGetLastError();
 }
 template <typename T>
