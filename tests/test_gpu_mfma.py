@@ -251,3 +251,26 @@ def test_mixed_solve_with_matrix_core_inner_apply(bri):
                           dagger=True)
     xd, infod = bri.bri_solve_cgne(dims, W_hi, bs, 0.1, pd, W_lo=Wm)
     assert infod["converged"] and max(infod["true_residual"][:12]) <= 1e-10, infod
+
+
+@pytest.mark.parametrize("nrhs", [1, 5, 43])
+def test_mixed_solve_matrix_core_rhs_counts(bri, nrhs):
+    """The site-major inner CGNE with right-hand-side counts that leave the
+    BLAS-1 workgroups partly idle (5: 240 of 256 threads; 43: one site per
+    pass) and a partial block of twelve in the apply: Gaussian sources, true
+    FP64 residual 1e-10, solution equal to the plain FP64 solve."""
+    import torch
+    dims = (6, 4, 4, 8)
+    u = synth.gauge_links(dims, 0.3, 5701)
+    src = synth.gaussian_spinor(dims, 5702, nrhs=nrhs)
+    log(f"mixed solve, matrix-core inner apply, nrhs={nrhs}")
+    U = bri.bri_pack_links(dims, dev(u), bri.F64)
+    W_hi = bri.bri_build_transporters(dims, U, bri.F64, 80)
+    Wm = bri.bri_pack_w_mfma(dims, W_hi)
+    bs = bri.bri_pack_spinor(dims, dev(src), bri.F64)
+    p = bri.solve_params(tol=1e-10, inner_tol=1e-2, inner_prec=bri.F16, inner_mfma=True)
+    x, info = bri.bri_solve_cgne(dims, W_hi, bs, 0.1, p, W_lo=Wm)
+    assert info["converged"] and max(info["true_residual"][:nrhs]) <= 1e-10, info
+    x64, info64 = bri.bri_solve_cgne(dims, W_hi, bs, 0.1, bri.solve_params(tol=1e-10))
+    rel = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+    assert rel < 1e-8, rel
