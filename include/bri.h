@@ -84,7 +84,8 @@ const char *bri_last_error(void);
 /* ABI revision of this header (incremented on incompatible change; 3 added
  * the coefficient table to bri_operator and to the gradient calls, 5
  * replaced the per-precision kernel choice by per-shape configurations, 6
- * added the matrix-core apply and bri_solve_params.inner_mfma).  bri_abi_version() returns the
+ * added the matrix-core apply, its site-major spinor conversions and
+ * bri_solve_params.inner_mfma).  bri_abi_version() returns the
  * revision the library was built with; a caller compares it to
  * BRI_ABI_VERSION. */
 #define BRI_ABI_VERSION 6
@@ -187,11 +188,13 @@ bri_status bri_apply_wilson(bri_dims d, const void *U_soa, bri_prec prec, double
  *   FP32 site-major [V][nrhs][12] complex, nrhs in [1, 65535] (blocks of 12
  *   per workgroup; a partial block pads with zeros); bound2: device, nrhs doubles,
  *   bound2[r] >= the largest squared real or imaginary part of in_r
- *   (bri_spinor_bound2, or a squared 2-norm; any upper bound works, a loose
- *   one costs nothing); coef: NULL for the Brillouin column of Tab. rholambda
+ *   (bri_spinor_to_sites gives it, or a squared 2-norm: any upper bound
+ *   works; the looser it is, the closer small components come to the FP16
+ *   subnormal range); coef: NULL for the Brillouin column of Tab. rholambda
  *   or 9 host doubles lambda_0..4, rho_1..4.  in and out must not overlap;
- *   pointers 16-byte aligned (BRI_E_ARG otherwise).  Enqueued on stream,
- *   asynchronous; no allocation. */
+ *   pointers 16-byte aligned (BRI_E_ARG otherwise); a t plane of the fields
+ *   (V / Lt sites x nrhs x 96 B) must stay below 4 GiB (BRI_E_UNSUPPORTED
+ *   otherwise).  Enqueued on stream, asynchronous; no allocation. */
 #define BRI_MFMA_W_BYTES_PER_SITE 2880
 bri_status bri_pack_w_mfma(bri_dims d, const void *W, bri_prec w_prec, int32_t n_offsets, void *W_mfma,
                            void *stream);

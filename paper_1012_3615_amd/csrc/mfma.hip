@@ -651,6 +651,8 @@ hipError_t apply_mfma(const Geom &g, const void *Wm, const float2 *in, float2 *o
         a.lam[k] = (float)(lam[k] / sl);
         a.rho[k] = (float)(rho[k] / sr);
     }
+    // the kernel adds 32-bit byte offsets within a t plane of the spinor fields
+    if ((size_t)g.V / g.L[3] * (size_t)nrhs * 96 > 0xffffffffull) return hipErrorInvalidValue;
     const int nrb = (nrhs + 4 * mfma::NTB - 1) / (4 * mfma::NTB);
     const long long blocks = (long long)a.ntx * a.nty * g.L[2] * a.ntc * nrb;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;

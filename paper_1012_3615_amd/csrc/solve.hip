@@ -210,6 +210,8 @@ static bri_status solve_core(bri_dims d, const bri_solve_params *p, const OpDesc
         return fail(BRI_E_ARG, "the matrix-core inner apply needs inner_prec = BRI_F16");
     if (p->inner_mfma && (lo.rows != 3 || lo.clover))
         return fail(BRI_E_UNSUPPORTED, "the matrix-core inner apply has no two-row store or clover term");
+    if (p->inner_mfma && (size_t)g.V / g.L[3] * (size_t)nrhs * 96 > 0xffffffffull)
+        return fail(BRI_E_UNSUPPORTED, "a t plane of the matrix-core inner vectors exceeds 4 GiB");
     if (!aligned(hi.W) || !aligned(b) || !aligned(x) || (mixed && !aligned(lo.W)))
         return fail(BRI_E_ARG, "null or misaligned pointer");
     const size_t n = (size_t)24 * g.V;
