@@ -1,6 +1,8 @@
 // Stored-transporter apply with LDS-staged spinor layers (one right-hand
 // side per thread).
 #pragma once
+#include <type_traits>
+
 #include "stencil.h"
 #include "su3.h"
 
@@ -39,6 +41,10 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                                                         SS *__restrict__ out, A diag, int nrhs,
                                                         const SS *__restrict__ clover, Coef<A> cf) {
     using TS = TileShape<TX, TY>;
+    // FP16 transporters and spinors: colour products on packed FP16 pairs
+    // with FP32 accumulation (the transporter words stay as loaded)
+    constexpr bool H2 = std::is_same<WS, __half2>::value && std::is_same<SS, __half2>::value &&
+                        std::is_same<A, float>::value && ROWS == 3;
     __shared__ SS lds[R][12][TS::NH];
     // one-dimensional grid: tile-major, right-hand-side group fastest, so the
     // groups of a tile run back to back on one XCD and share its transporters
@@ -137,11 +143,33 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
             }
         }
     };
+    // the same as raw FP16 words, the conjugate by the sign of the high half
+    auto load_w_h2 = [&](int layer, int nx, int ny, uint32_t (&w)[3][3]) {
+        const int lnz = layer % 3 - 1, lnt = layer / 3 - 1;
+        const int i = (nx + 1) + 3 * (ny + 1) + 9 * (lnz + 1) + 27 * (lnt + 1);
+        const uint32_t *W32 = reinterpret_cast<const uint32_t *>(W);
+        if (NOFF == 80) {
+            const uint32_t *p = W32 + (size_t)(i < 40 ? i : i - 1) * 9 * V + site;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = __builtin_nontemporal_load(p + e * V);
+        } else if (i > 40) {
+            const uint32_t *p = W32 + (size_t)(i - 41) * 9 * V + site;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = p[e * V];
+        } else {
+            const int zn = (z + lnz + Lz) % Lz, tn = (t + lnt + Lt) % Lt;
+            const int yn = ((x + nx + Lx) % Lx) + Lx * (((y + ny + Ly) % Ly) + Ly * (zn + Lz * tn));
+            const uint32_t *p = W32 + (size_t)(39 - i) * 9 * V + yn;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) w[e % 3][e / 3] = p[e * V] ^ 0x80000000u;
+        }
+    };
     // with PF the next transporter of the layer is in flight during the
     // arithmetic of the current one (not across layers: vector-memory loads
     // return in order, and an HBM load issued before the layer's LDS fill
     // would delay the fill's L2 hits)
     cx<A> wn[3][3];
+    uint32_t wnh[3][3];
 
 #pragma unroll 1
     for (int layer = 0; layer < 9; ++layer) {
@@ -165,7 +193,12 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
         __syncthreads();
         const bool centre = (nz | nt) == 0;  // this layer holds n = 0 at o = 4
         if (valid) {
-            if (PF) load_w(layer, -1, -1, wn);
+            if (PF) {
+                if constexpr (H2)
+                    load_w_h2(layer, -1, -1, wnh);
+                else
+                    load_w(layer, -1, -1, wn);
+            }
             // one offset (nx, ny) = (o % 3 - 1, o / 3 - 1) of this layer
             auto offset = [&](const int o) __attribute__((always_inline)) {
                 const int nx = o % 3 - 1, ny = o / 3 - 1;
@@ -185,6 +218,32 @@ __global__ __launch_bounds__(TX *TY) void k_apply_tiled(Geom g, int ntx, int nty
                 const int k = (nx != 0) + (ny != 0) + (nz != 0) + (nt != 0);
                 const A lam = coef_pick(cf.lam, k);
                 const A rho = DAG ? -coef_pick(cf.rho, k) : coef_pick(cf.rho, k);
+                if constexpr (H2) {
+                    uint32_t w[3][3];
+                    if (PF) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) w[a][b] = wnh[a][b];
+                        int o2 = o + 1;
+                        if (centre && o2 == 4) ++o2;
+                        if (o2 < 9) load_w_h2(layer, o2 % 3 - 1, o2 / 3 - 1, wnh);
+                    } else {
+                        load_w_h2(layer, nx, ny, w);
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (R > 1 && r >= nr) break;
+                        uint32_t psi[4][3];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+#pragma unroll
+                            for (int b = 0; b < 3; ++b)
+                                psi[s][b] = *reinterpret_cast<const uint32_t *>(&lds[r][3 * s + b][qn]);
+                        colour_spin_accum_h2(acc[r], w, psi, lam, rho, nx, ny, nz, nt);
+                    }
+                    return;
+                }
                 cx<A> w[3][3];
                 if (PF) {
 #pragma unroll

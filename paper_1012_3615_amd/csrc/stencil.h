@@ -118,6 +118,42 @@ __device__ __forceinline__ void colour_spin_accum(cx<A> acc[4][3], const cx<A> w
 }
 
 
+// FP16 colour products with FP32 accumulation (v_dot2_f32_f16), for FP16
+// transporters and spinors: both operands are exact in FP32 products, so the
+// result equals the converted FP32 arithmetic up to the order of the
+// additions.  A transporter entry w = (re, im) (one 32-bit word, re in the
+// low half) enters as the two words (re, -im) and (im, re); a spinor entry
+// stays as stored.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2v, a), __builtin_bit_cast(h2v, b), c, false);
+}
+__device__ __forceinline__ void h2_pair(uint32_t w, uint32_t &wp, uint32_t &wq) {
+    wp = w ^ 0x80000000u;                          // (re, -im)
+    wq = __builtin_amdgcn_alignbit(w, w, 16);     // (im, re)
+}
+// chi[s] = w[a][.] psi[s][.] for colour row a, all spins, and accumulate
+__device__ __forceinline__ void colour_spin_accum_h2(cx<float> acc[4][3], const uint32_t w[3][3],
+                                                     const uint32_t psi[4][3], float lam, float rho, int nx,
+                                                     int ny, int nz, int nt) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        uint32_t wp[3], wq[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) h2_pair(w[a][b], wp[b], wq[b]);
+        cx<float> chi[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            chi[s].re = dot2(wp[2], psi[s][2], dot2(wp[1], psi[s][1], dot2(wp[0], psi[s][0], 0.0f)));
+            chi[s].im = dot2(wq[2], psi[s][2], dot2(wq[1], psi[s][1], dot2(wq[0], psi[s][0], 0.0f)));
+        }
+        cx<float> o[4] = {acc[0][a], acc[1][a], acc[2][a], acc[3][a]};
+        spin_accum_rt(o, chi, lam, rho, nx, ny, nz, nt);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s][a] = o[s];
+    }
+}
+
 // ------------------------------------------------------------------ clover term
 // Per site two Hermitian 6x6 blocks (spins 0,1 and spins 2,3; local index
 // 3*s + colour), stored as [2][18][V] complex: planes 0..2 hold the real
