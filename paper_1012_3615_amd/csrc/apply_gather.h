@@ -1,6 +1,8 @@
 // Stored-transporter apply, neighbour gathers through the caches, several
 // right-hand sides per thread (the fused multi-RHS form).
 #pragma once
+#include <type_traits>
+
 #include "stencil.h"
 
 namespace bri {
@@ -16,6 +18,10 @@ __global__ __launch_bounds__(256) void k_apply_stored(Geom g, const WS *__restri
     if (site >= g.V) return;
     const size_t V = (size_t)g.V;
     const int r0 = blockIdx.y * R;
+    // FP16 transporters and spinors: the same packed FP16 colour products as
+    // the LDS-tiled kernel (so that all configurations agree bit for bit)
+    constexpr bool H2 = std::is_same<WS, __half2>::value && std::is_same<SS, __half2>::value &&
+                        std::is_same<A, float>::value;
     int c[4];
     coords(g, site, c);
     const Nbr nb = make_nbr(g, c);
@@ -50,6 +56,31 @@ __global__ __launch_bounds__(256) void k_apply_stored(Geom g, const WS *__restri
         const A lam = coef_pick(cf.lam, k);
         const A rho = DAG ? -coef_pick(cf.rho, k) : coef_pick(cf.rho, k);
         const int y = nbr_rt(nb, nx, ny, nz, nt);
+        if constexpr (H2) {
+            const uint32_t *W32 = reinterpret_cast<const uint32_t *>(W);
+            uint32_t w[3][3];
+            if (NOFF == 80 || i > 40) {
+                const uint32_t *p = W32 + (size_t)(NOFF == 80 ? j : i - 41) * 9 * V + site;
+#pragma unroll
+                for (int e = 0; e < 9; ++e) w[e / 3][e % 3] = p[e * V];
+            } else {
+                const uint32_t *p = W32 + (size_t)(39 - i) * 9 * V + y;
+#pragma unroll
+                for (int e = 0; e < 9; ++e) w[e % 3][e / 3] = p[e * V] ^ 0x80000000u;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (R > 1 && r0 + r >= nrhs) break;
+                const uint32_t *q = reinterpret_cast<const uint32_t *>(in) + (size_t)(r0 + r) * 12 * V + y;
+                uint32_t psi[4][3];
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) psi[s][b] = q[(3 * s + b) * V];
+                colour_spin_accum_h2(acc[r], w, psi, lam, rho, nx, ny, nz, nt);
+            }
+            continue;
+        }
         cx<A> w[3][3];
         if (NOFF == 80 || i > 40) {
             const WS *p = W + (size_t)(NOFF == 80 ? j : i - 41) * 9 * V + site;

@@ -121,7 +121,6 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     // kernel-argument fields as locals: the lambdas below capture by
     // reference, and a captured kernel argument would be copied to scratch
     const int Lx = a.g.L[0], Ly = a.g.L[1], Lz = a.g.L[2], Lt = a.g.L[3];
-    const size_t V = (size_t)a.g.V;
     // 64-bit bases are wave-uniform (scalar registers); the lanes add
     // 32-bit byte offsets (the host bounds a t plane of the fields by 4 GiB)
     const char *__restrict__ in = (const char *)a.in;
