@@ -29,7 +29,7 @@ hipError_t convert(size_t n, int nrhs, const S *src, D *dst, const double *scale
 template <typename S>
 hipError_t accum(size_t n, int nrhs, const S *e, double *x, const double *scale, hipStream_t st);
 // site-major FP32 fields [V][nrhs][24] (nrhs <= 64): partials per rhs over
-// site_blocks(V, nrhs) workgroups, summed by dot_finish
+// site_blocks(V, nrhs) <= 4096 workgroups, summed by dot_finish
 int site_blocks(size_t V, int nrhs);
 hipError_t norm2_sites(size_t V, int nrhs, const float *a, double *part, int nblk, hipStream_t st);
 hipError_t update_xr_sites(size_t V, int nrhs, const double *alpha, float *x, const float *p, float *r, const float *q,

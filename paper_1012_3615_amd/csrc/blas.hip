@@ -11,6 +11,9 @@ namespace {
 
 constexpr int kB = 256;
 constexpr int kMaxBlocks = 1024;
+// site-major kernels put every right-hand side into one workgroup, so they
+// need more workgroups to keep enough loads in flight
+constexpr int kMaxSiteBlocks = 4096;
 
 template <typename T>
 __device__ __forceinline__ double to_d(T v) { return (double)v; }
@@ -318,7 +321,7 @@ static int site_m(int nrhs) {
 int site_blocks(size_t V, int nrhs) {
     const size_t m = (size_t)site_m(nrhs);
     const size_t b = (V + m - 1) / m;
-    return (int)(b < (size_t)kMaxBlocks ? b : (size_t)kMaxBlocks);
+    return (int)(b < (size_t)kMaxSiteBlocks ? b : (size_t)kMaxSiteBlocks);
 }
 hipError_t norm2_sites(size_t V, int nrhs, const float *a, double *part, int nblk, hipStream_t st) {
     hipLaunchKernelGGL(k_norm2_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, (const float4 *)a,

@@ -64,7 +64,7 @@ Layout layout(size_t n, int nrhs, size_t tbytes) {
     L.p = take(lv);
     L.q = take(lv);
     L.z = take(lv);
-    L.part = take((size_t)nrhs * 1024 * 2 * sizeof(double));
+    L.part = take((size_t)nrhs * 4096 * 2 * sizeof(double));  // per-workgroup partials (site-major: up to 4096)
     L.red = take((size_t)4 * nrhs * 2 * sizeof(double));
     L.stv = take((size_t)7 * nrhs * sizeof(double));
     L.scale = take((size_t)nrhs * sizeof(double));
