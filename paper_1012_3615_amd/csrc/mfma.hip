@@ -306,15 +306,24 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
         for (int j = 0; j < NT; ++j) px[j] = *(const float2 *)(is + out_ofs(j));
     };
 
-    // ---- one site: 20 reduction steps, then the epilogue (stored when the
-    // site is valid); the site at position SP of the wavefront issues
-    // staging batch SP of the plane set tt inside its first reduction step
-    // (after the wait for its own transporter rows, which then covers none of
-    // them).  The staging is issued on every step, also the last of a chunk
-    // (its plane set is then not stored): with no branch around the loads,
-    // their registers need no copies, which would wait for them at once.
+    // ---- one site at time t: 20 reduction steps, then the epilogue (stored
+    // when the site is valid).  Offsets are ordered by n_t, so steps 0..QA
+    // are the last to read plane t - 1 (step QA also reads plane t).  After
+    // step QA one workgroup barrier serves the whole t step: every wavefront
+    // is then past plane t - 1, whose ring slot takes plane t + 2 (loaded
+    // into registers during the previous t step, converted and stored now),
+    // and the stores of plane t + 1 made at the previous step are visible
+    // before the steps that read it.  Then the loads of plane t + 3 are
+    // issued, to be stored at the next step.  Every load is issued on every
+    // step, also past the end of a chunk (not needed, stored harmlessly):
+    // with no branch around the loads their registers need no copies, which
+    // would wait for them at once.
+    static_assert(SPW == 1 && NB == 1, "one site per wavefront and t step");
+    constexpr int QA = 6;  // offsets 0..26 (4 QA + 3) have n_t = -1
+    static_assert(comp(4 * QA + 2, 3) == -1 && comp(4 * QA + 3, 3) == 0 && comp(4 * QA + 4, 3) == 0,
+                  "reduction steps ordered by n_t");
     int tm = 0;  // t mod 3 (table of the current t)
-    auto compute_site = [&](size_t site, int srp, size_t next, bool valid, int tt, int sp) __attribute__((always_inline)) {
+    auto compute_site = [&](size_t site, int srp, size_t next, bool valid, int t) __attribute__((always_inline)) {
         f4 acc[2][NT];
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -369,9 +378,13 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
                 acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, A0), Bj, acc[0][j], 0, 0, 0);
                 acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, A1), Bj, acc[1][j], 0, 0, 0);
             }
-            if (q == 0) static_for<0, NB>([&](auto B) __attribute__((always_inline)) {
-                if (sp == decltype(B)::value) stage_step(tt, B);
-            });
+            if (q == QA) {
+                // (the B reads issued so far beyond this step are of planes t, t + 1)
+                __syncthreads();
+                convert_batch(ic<0>{});
+                store_planes(t + 2);
+                load_batch(t + 3, ic<0>{});
+            }
             __builtin_amdgcn_sched_barrier(0);  // keep the steps in order (bounded register use)
         }
         // epilogue per column tile: accumulator rows 4 (lane / 16) + e, column
@@ -424,21 +437,14 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
         static_for<0, NB + 1>([&](auto B) __attribute__((always_inline)) { stage_step(t0 - 1 + k, B); });
         store_planes(t0 - 1 + k);
     }
+    load_batch(t0 + 2, ic<0>{});  // stored during the first step
     __syncthreads();
     for (int t = t0; t < t1; ++t) {
-        const bool more = t + 1 < t1;
         tm = t % 3;
-#pragma unroll
-        for (int i = 0; i < SPW; ++i) {
-            // next site of the chain (after the last t of the chunk: site 0
-            // of this t again, so that every load is issued)
-            const size_t next = i + 1 < SPW ? site_of(i + 1, t) : site_of(0, more ? t + 1 : t);
-            compute_site(site_of(i, t), srp0 + i, next, i < nval, t + 2, i);
-        }
-        stage_step(t + 2, ic<NB>{});
-        __syncthreads();  // the ring slot of t - 1 is free
-        if (more) store_planes(t + 2);
-        __syncthreads();
+        // next site of the chain (after the last t of the chunk: this site
+        // again, so that every load is issued)
+        const size_t next = site_of(0, t + 1 < t1 ? t + 1 : t);
+        compute_site(site_of(0, t), srp0, next, nval > 0, t);
     }
 }
 
