@@ -60,7 +60,7 @@ constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------- fused build
 // All transporters of a site in one kernel, the way k_apply_recompute builds
-// them: 16 consecutive sites x 16 threads per workgroup, every one of the 80
+// them: 16 consecutive sites x 32 threads per workgroup, every one of the 80
 // transporters of a site built once by the hop-order recursion (k! W
 // carried, two- and three-hop ones shared through LDS, one support per wave),
 // in FP64, and written to the store as soon as it is built (the 40-offset
@@ -76,7 +76,7 @@ __device__ __forceinline__ void store_w(WT *__restrict__ W, size_t V, int site, 
     const int plane = NOFF == 80 ? (i < 40 ? i : i - 1) : i - 41;
     WT *o = W + (size_t)plane * 9 * V + site;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) st(o + e * V, cscale(inv_fact, s[e / 3][e % 3]));
+    for (int e = 0; e < 9; ++e) stnt(o + e * V, cscale(inv_fact, s[e / 3][e % 3]));
 }
 
 template <int P, typename WT, int NOFF>
@@ -130,16 +130,42 @@ __device__ __forceinline__ void build_l3(const double2 *U, WT *W, size_t V, cons
     store_w<WT, NOFF>(W, V, site, valid, n, 1.0 / 6.0, w);
 }
 
+// First site of the 16-site x strip that a workgroup builds.  With gy > 0
+// (Lx a multiple of 16, gy | Ly, gz | Lz) the strips are ordered in groups of
+// Lx/16 x gy x gz strips at one t, a group walking t before the next group
+// (y blocks fastest): the workgroups an XCD runs at a time then cover a
+// compact (x, y, z) block, and its next t step re-reads the links of this one
+// from L2.  With gy = 0 the strips follow the site order.
+__device__ __forceinline__ int strip_base(const Geom &g, int blk, int gy, int gz) {
+    if (gy == 0) return blk * 16;
+    const int nxs = g.L[0] / 16;
+    int r = blk;
+    const int xs = r % nxs;
+    r /= nxs;
+    const int yy = r % gy;
+    r /= gy;
+    const int zz = r % gz;
+    r /= gz;
+    const int t = r % g.L[3];
+    r /= g.L[3];
+    const int nyb = g.L[1] / gy;
+    const int y = (r % nyb) * gy + yy, z = (r / nyb) * gz + zz;
+    return 16 * xs + y * g.stride[1] + z * g.stride[2] + t * g.stride[3];
+}
+
 template <typename WT, int NOFF>
-__global__ __launch_bounds__(256) void k_build_fused(Geom g, const double2 *__restrict__ U, WT *__restrict__ W) {
+__global__ __launch_bounds__(512) void k_build_fused(Geom g, const double2 *__restrict__ U, WT *__restrict__ W, int gy,
+                                                    int gz) {
+    // 16 sites x 32 threads: eight waves, each of 16 sites x 4 roles; the
+    // FP64 levels in LDS (129 KB) allow one workgroup per CU, i.e. two waves
+    // per SIMD
     constexpr int S = 16;
     __shared__ cx<double> w2[24][9][S];
     __shared__ cx<double> w3[32][9][S];
     const int sl = threadIdx.x % S;
     const int role = (threadIdx.x / S) % 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int s0 = blk * S + sl;
+    const int s0 = strip_base(g, xcd_block(blockIdx.x, gridDim.x), gy, gz) + sl;
     const bool valid = s0 < g.V;
     const int site = valid ? s0 : 0;
     const size_t V = (size_t)g.V;
@@ -147,18 +173,16 @@ __global__ __launch_bounds__(256) void k_build_fused(Geom g, const double2 *__re
     coords(g, site, c);
     const NbrParts q = make_parts(g, c);
 
-    // two hops and the links
-    static_for<0, 4>([&](auto P) {
+    // two hops: waves 0-5, one direction pair each, role = the two signs;
+    // links: wave 6 the x and y directions, wave 7 z and t, role bit 0 the sign
+    static_for<0, 6>([&](auto P) {
         if (wave == decltype(P)::value) build_l2<decltype(P)::value, WT, NOFF>(U, W, V, q, role, sl, site, valid, w2);
     });
-    if (wave == 0) build_l2<4, WT, NOFF>(U, W, V, q, role, sl, site, valid, w2);
-    if (wave == 1) build_l2<5, WT, NOFF>(U, W, V, q, role, sl, site, valid, w2);
-    if (wave >= 2) {
-        // links: wave 2 the x and y directions, wave 3 z and t; role bit 0 the sign
+    if (wave >= 6) {
         const int sgn = (role & 1) ? -1 : 1;
         static_for<0, 4>([&](auto M) {
             constexpr int MU = decltype(M)::value;
-            if (wave == 2 + MU / 2 && (role >> 1) == MU % 2) {
+            if (wave == 6 + MU / 2 && (role >> 1) == MU % 2) {
                 int n[4] = {0, 0, 0, 0};
                 n[MU] = sgn;
                 cx<double> w[3][3];
@@ -168,19 +192,19 @@ __global__ __launch_bounds__(256) void k_build_fused(Geom g, const double2 *__re
         });
     }
     __syncthreads();
-    // three hops
-#pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-        const int bits = 4 * half + role;
-        static_for<0, 4>([&](auto Q) {
-            if (wave == decltype(Q)::value)
-                build_l3<decltype(Q)::value, WT, NOFF>(U, W, V, q, bits, sl, site, valid, w2, w3);
-        });
-    }
+    // three hops: support = all directions but Q = wave / 2, signs 4 (wave % 2) + role
+    static_for<0, 4>([&](auto Q) {
+        if ((wave >> 1) == decltype(Q)::value)
+            build_l3<decltype(Q)::value, WT, NOFF>(U, W, V, q, 4 * (wave & 1) + role, sl, site, valid, w2, w3);
+    });
     __syncthreads();
-    // four hops
+    // four hops, signs 4 (wave % 4) + role: waves 0-3 sum the paths whose last
+    // step is along x or y, waves 4-7 those along z or t; the first half goes
+    // through LDS (the two-hop slots are free by now) to the second, which
+    // adds it and stores
     {
-        const int bits = 4 * wave + role;
+        const int h = wave >> 2;
+        const int bits = 4 * (wave & 3) + role;
         int n[4];
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) n[mu] = ((bits >> mu) & 1) ? -1 : 1;
@@ -188,12 +212,23 @@ __global__ __launch_bounds__(256) void k_build_fused(Geom g, const double2 *__re
         zero33(w);
         static_for<0, 4>([&](auto M) {
             constexpr int MU = decltype(M)::value;
-            const int low = bits & ((1 << MU) - 1), high = bits >> (MU + 1);
-            lds_get<double, 16>(w3, 8 * MU + (low | (high << MU)), sl, p);
-            last_link<MU, double2, double>(U, V, q, n, l);
-            mat_mul_acc(w, p, l);
+            if (h == MU / 2) {
+                const int low = bits & ((1 << MU) - 1), high = bits >> (MU + 1);
+                lds_get<double, 16>(w3, 8 * MU + (low | (high << MU)), sl, p);
+                last_link<MU, double2, double>(U, V, q, n, l);
+                mat_mul_acc(w, p, l);
+            }
         });
-        store_w<WT, NOFF>(W, V, site, valid, n, 1.0 / 24.0, w);
+        if (h == 0) lds_put<double, 16>(w2, bits, sl, w);
+        __syncthreads();
+        if (h == 1) {
+            lds_get<double, 16>(w2, bits, sl, p);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) w[a][b] = cmake<double>(w[a][b].re + p[a][b].re, w[a][b].im + p[a][b].im);
+            store_w<WT, NOFF>(W, V, site, valid, n, 1.0 / 24.0, w);
+        }
     }
 }
 
@@ -202,10 +237,18 @@ hipError_t build_fused_t(const Geom &g, const double2 *U, void *W, int noff, hip
     // the link planes are addressed with 32-bit byte offsets
     if ((size_t)g.V * sizeof(double2) >= ((size_t)1 << 32)) return hipErrorInvalidValue;
     dim3 grid((g.V + 15) / 16);
+    // strip groups of Lx/16 x 4 x 4 (32 workgroups at Lx = 32, what an XCD
+    // holds at a time); 32^3 x 64 FP32 W80: 7.43 ms in site order, 7.02 ms
+    // with 4 x 4, 7.11-7.18 ms with 8 x 4, 4 x 8 or 8 x 8, 7.75 ms with 2 x 2
+    int gy = 0, gz = 0;
+    if (g.L[0] % 16 == 0) {
+        gy = g.L[1] % 4 == 0 ? 4 : g.L[1] % 2 == 0 ? 2 : 1;
+        gz = g.L[2] % 4 == 0 ? 4 : g.L[2] % 2 == 0 ? 2 : 1;
+    }
     if (noff == 80)
-        hipLaunchKernelGGL((k_build_fused<WT, 80>), grid, dim3(256), 0, st, g, U, (WT *)W);
+        hipLaunchKernelGGL((k_build_fused<WT, 80>), grid, dim3(512), 0, st, g, U, (WT *)W, gy, gz);
     else
-        hipLaunchKernelGGL((k_build_fused<WT, 40>), grid, dim3(256), 0, st, g, U, (WT *)W);
+        hipLaunchKernelGGL((k_build_fused<WT, 40>), grid, dim3(512), 0, st, g, U, (WT *)W, gy, gz);
     return hipGetLastError();
 }
 }  // namespace
