@@ -23,13 +23,15 @@ hipError_t launch_recompute(const Geom &g, const void *U, const void *in, void *
     // element planes are addressed with 32-bit byte offsets
     if ((size_t)g.V * sizeof(LS) >= ((size_t)1 << 32) || (size_t)g.V * sizeof(SS) >= ((size_t)1 << 32))
         return hipErrorInvalidValue;
-    dim3 grid((g.V + 15) / 16, nrhs);  // 16 sites x 16 threads per workgroup
+    dim3 grid((g.V + 15) / 16, nrhs);  // 16 sites per workgroup
+    int gy, gz;
+    strip_groups(g, gy, gz);
     if (dag)
-        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, true>), grid, dim3(256), 0, st, g,
-                           (const LS *)U, (const SS *)in, (SS *)out, (A)diag);
+        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, true>), grid, dim3(16 * recompute_tps<A>()), 0, st, g,
+                           (const LS *)U, (const SS *)in, (SS *)out, (A)diag, gy, gz);
     else
-        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, false>), grid, dim3(256), 0, st, g,
-                           (const LS *)U, (const SS *)in, (SS *)out, (A)diag);
+        hipLaunchKernelGGL((k_apply_recompute<LS, SS, A, false>), grid, dim3(16 * recompute_tps<A>()), 0, st, g,
+                           (const LS *)U, (const SS *)in, (SS *)out, (A)diag, gy, gz);
     return hipGetLastError();
 }
 }  // namespace

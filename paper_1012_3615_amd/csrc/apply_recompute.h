@@ -269,35 +269,83 @@ __device__ __forceinline__ void task_l4(const LS *U, const SS *in, size_t V, con
     stencil_term<15, SS, A>(in, V, nb, n, (A)(lam_k(4) / f), (A)(DAG ? -rho_k(4) / f : rho_k(4) / f), w, acc);
 }
 
-// One workgroup = 16 consecutive sites x 16 threads per site, four waves of
-// 16 sites x 4 "roles".  The 80 transporters of each site are built exactly
-// once, by the hop-order recursion of the path average (Sec. 5.1),
+// First site of the 16-site x strip that a workgroup takes.  With gy > 0
+// (Lx a multiple of 16, gy | Ly, gz | Lz) the strips are ordered in groups of
+// Lx/16 x gy x gz strips at one t, a group walking t before the next group
+// (y blocks fastest): the workgroups an XCD runs at a time then cover a
+// compact (x, y, z) block, and its next t step re-reads the links of this one
+// from L2.  With gy = 0 the strips follow the site order.
+__device__ __forceinline__ int strip_base(const Geom &g, int blk, int gy, int gz) {
+    if (gy == 0) return blk * 16;
+    const int nxs = g.L[0] / 16;
+    int r = blk;
+    const int xs = r % nxs;
+    r /= nxs;
+    const int yy = r % gy;
+    r /= gy;
+    const int zz = r % gz;
+    r /= gz;
+    const int t = r % g.L[3];
+    r /= g.L[3];
+    const int nyb = g.L[1] / gy;
+    const int y = (r % nyb) * gy + yy, z = (r / nyb) * gz + zz;
+    return 16 * xs + y * g.stride[1] + z * g.stride[2] + t * g.stride[3];
+}
+
+// the strip groups used with strip_base: Lx/16 x 4 x 4 where the extents allow
+inline void strip_groups(const Geom &g, int &gy, int &gz) {
+    gy = gz = 0;
+    if (g.L[0] % 16 != 0) return;
+    gy = g.L[1] % 4 == 0 ? 4 : g.L[1] % 2 == 0 ? 2 : 1;
+    gz = g.L[2] % 4 == 0 ? 4 : g.L[2] % 2 == 0 ? 2 : 1;
+}
+
+// One workgroup = 16 consecutive sites x TPS threads per site (TPS = 16 for
+// FP32, 32 for FP64), TPS / 4 waves of 16 sites x 4 "roles".  The 80
+// transporters of each site are built exactly once, by the hop-order
+// recursion of the path average (Sec. 5.1),
 //   W(n) = (1/k) sum_{mu in supp n} W(n - n_mu mu) L(n, mu),
 // carried as k! W (no scaling; the stencil coefficients take the 1/k!),
 // level by level; the two- and three-hop ones stay in LDS, where the next
 // level reads them as predecessors: 208 3x3 products per site (48 + 96 + 64),
 // none repeated.  Each wave takes offsets of one support at a time, its four
 // roles the sign combinations, so directions are compile-time and only the
-// signs vary across lanes:
-//   pass 1: wave w the pair w (two hops);
-//   pass 2: waves 0, 1 the pairs 4, 5; wave 2 the links +-x, +-y, wave 3 +-z, +-t;
-//   pass 3, 4: wave w the three-hop offsets without direction w (signs 0-3, 4-7);
-//   pass 5: wave w the four-hop offsets with sign bits 4w + role.
-// Each transporter is applied to psi(x+n) as soon as it is built; the 16
-// partial sums of a site are added in a fixed order through LDS, then the
-// diagonal term.
+// signs vary across lanes.  With 16 threads per site:
+//   two hops: wave w the pair w, then waves 0, 1 the pairs 4, 5 and wave 2
+//   the links +-x, +-y, wave 3 +-z, +-t;
+//   three hops: wave w the offsets without direction w (signs 0-3, then 4-7);
+//   four hops: wave w the offsets with sign bits 4 w + role.
+// With 32 threads per site (FP64: the levels take 129 KB of LDS, one
+// workgroup per CU, so the eight waves give two per SIMD instead of one):
+//   two hops: wave w < 6 the pair w; wave 6 the links +-x, +-y, wave 7 +-z, +-t;
+//   three hops: wave w the offsets without direction w / 2, signs 4 (w % 2) + role;
+//   four hops: signs 4 (w % 4) + role; waves 0-3 sum the paths whose last
+//   step is along x or y, waves 4-7 those along z or t, and the first half
+//   reaches the second through LDS.
+// The x strips run in groups (strip_base).  Each transporter is applied to
+// psi(x+n) as soon as it is complete; the TPS partial sums of a site are
+// added in a fixed order through LDS, then the diagonal term.
+// 32^3 x 64: FP32 4.53 ms in site order, 4.34 ms with 4 x 4 strip groups
+// (4.82 ms with 32 threads per site); FP64 7.96 ms (16 threads per site,
+// site order) -> 7.01 ms.
+template <typename A>
+constexpr int recompute_tps() { return sizeof(A) == 8 ? 32 : 16; }
+
 template <typename LS, typename SS, typename A, bool DAG>
-__global__ __launch_bounds__(256) void k_apply_recompute(Geom g, const LS *__restrict__ U,
-                                                         const SS *__restrict__ in, SS *__restrict__ out, A diag) {
+__global__ __launch_bounds__(16 * recompute_tps<A>())
+void k_apply_recompute(Geom g, const LS *__restrict__ U, const SS *__restrict__ in, SS *__restrict__ out, A diag,
+                       int gy, int gz) {
     constexpr int S = 16;
-    __shared__ cx<A> w2[24][9][S];
-    __shared__ cx<A> w3[32][9][S];
-    static_assert(sizeof(w2) >= sizeof(A) * 2 * 16 * 12 * S, "the reduction reuses the two-hop buffer");
+    constexpr int TPS = recompute_tps<A>();
+    __shared__ cx<A> lds[56][9][S];
+    cx<A>(*w2)[9][S] = lds;       // 24 two-hop slots
+    cx<A>(*w3)[9][S] = lds + 24;  // 32 three-hop slots
+    static_assert(sizeof(lds) >= sizeof(A) * 2 * TPS * 12 * S, "the reduction reuses the level buffers");
     const int sl = threadIdx.x % S;
     const int role = (threadIdx.x / S) % 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int s0 = blk * S + sl;
+    const int base = strip_base(g, xcd_block(blockIdx.x, gridDim.x), gy, gz);
+    const int s0 = base + sl;
     const bool valid = s0 < g.V;
     const int site = valid ? s0 : 0;
     const size_t V = (size_t)g.V;
@@ -311,43 +359,87 @@ __global__ __launch_bounds__(256) void k_apply_recompute(Geom g, const LS *__res
     int c[4];
     coords(g, site, c);
     const NbrParts nb = make_parts(g, c);
+    const int sgn = (role & 1) ? -1 : 1;  // sign of a link task
 
-    // two hops and the links
-    static_for<0, 4>([&](auto P) {
-        if (wave == decltype(P)::value) task_l2<decltype(P)::value, LS, SS, A, DAG, S>(U, in, V, nb, role, sl, w2, acc);
-    });
-    if (wave == 0) task_l2<4, LS, SS, A, DAG, S>(U, in, V, nb, role, sl, w2, acc);
-    if (wave == 1) task_l2<5, LS, SS, A, DAG, S>(U, in, V, nb, role, sl, w2, acc);
-    if (wave >= 2) {
-        const int sgn = (role & 1) ? -1 : 1;
-        if (wave == 2) {
-            if (role < 2)
-                task_l1<0, LS, SS, A, DAG>(U, in, V, nb, sgn, acc);
-            else
-                task_l1<1, LS, SS, A, DAG>(U, in, V, nb, sgn, acc);
-        } else {
-            if (role < 2)
-                task_l1<2, LS, SS, A, DAG>(U, in, V, nb, sgn, acc);
-            else
-                task_l1<3, LS, SS, A, DAG>(U, in, V, nb, sgn, acc);
-        }
-    }
-    __syncthreads();
-    // three hops
-#pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-        const int bits = 4 * half + role;
-        static_for<0, 4>([&](auto Q) {
-            if (wave == decltype(Q)::value)
-                task_l3<decltype(Q)::value, LS, SS, A, DAG, S>(U, in, V, nb, bits, sl, w2, w3, acc);
+    if constexpr (TPS == 32) {
+        // two hops and the links
+        static_for<0, 6>([&](auto P) {
+            if (wave == decltype(P)::value)
+                task_l2<decltype(P)::value, LS, SS, A, DAG, S>(U, in, V, nb, role, sl, w2, acc);
         });
+        static_for<0, 4>([&](auto M) {
+            constexpr int MU = decltype(M)::value;
+            if (wave == 6 + MU / 2 && (role >> 1) == MU % 2) task_l1<MU, LS, SS, A, DAG>(U, in, V, nb, sgn, acc);
+        });
+        __syncthreads();
+        // three hops
+        static_for<0, 4>([&](auto Q) {
+            if ((wave >> 1) == decltype(Q)::value)
+                task_l3<decltype(Q)::value, LS, SS, A, DAG, S>(U, in, V, nb, 4 * (wave & 1) + role, sl, w2, w3, acc);
+        });
+        __syncthreads();
+        // four hops: the half sums of the paths by the direction of their last
+        // step, the first half through the (now free) two-hop slots
+        const int h = wave >> 2;
+        const int bits = 4 * (wave & 3) + role;
+        int n[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) n[mu] = ((bits >> mu) & 1) ? -1 : 1;
+        cx<A> w[3][3], p[3][3], l[3][3];
+        zero33(w);
+        static_for<0, 4>([&](auto M) {
+            constexpr int MU = decltype(M)::value;
+            if (h == MU / 2) {
+                // predecessor: support all but MU, sign bits of the other three
+                // directions in increasing order
+                const int low = bits & ((1 << MU) - 1), high = bits >> (MU + 1);
+                lds_get<A, S>(w3, 8 * MU + (low | (high << MU)), sl, p);
+                last_link<MU, LS, A>(U, V, nb, n, l);
+                mat_mul_acc(w, p, l);
+            }
+        });
+        if (h == 0) lds_put<A, S>(w2, bits, sl, w);
+        __syncthreads();
+        if (h == 1) {
+            lds_get<A, S>(w2, bits, sl, p);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) w[a][b] = cadd(w[a][b], p[a][b]);
+            constexpr double f = 24.0;
+            stencil_term<15, SS, A>(in, V, nb, n, (A)(lam_k(4) / f), (A)(DAG ? -rho_k(4) / f : rho_k(4) / f), w,
+                                    acc);
+        }
+    } else {
+        // two hops and the links
+        static_for<0, 4>([&](auto P) {
+            if (wave == decltype(P)::value)
+                task_l2<decltype(P)::value, LS, SS, A, DAG, S>(U, in, V, nb, role, sl, w2, acc);
+        });
+        if (wave == 0) task_l2<4, LS, SS, A, DAG, S>(U, in, V, nb, role, sl, w2, acc);
+        if (wave == 1) task_l2<5, LS, SS, A, DAG, S>(U, in, V, nb, role, sl, w2, acc);
+        static_for<0, 4>([&](auto M) {
+            constexpr int MU = decltype(M)::value;
+            if (wave == 2 + MU / 2 && (role >> 1) == MU % 2) task_l1<MU, LS, SS, A, DAG>(U, in, V, nb, sgn, acc);
+        });
+        __syncthreads();
+        // three hops
+#pragma unroll 1
+        for (int half = 0; half < 2; ++half) {
+            const int bits = 4 * half + role;
+            static_for<0, 4>([&](auto Q) {
+                if (wave == decltype(Q)::value)
+                    task_l3<decltype(Q)::value, LS, SS, A, DAG, S>(U, in, V, nb, bits, sl, w2, w3, acc);
+            });
+        }
+        __syncthreads();
+        // four hops
+        task_l4<LS, SS, A, DAG, S>(U, in, V, nb, 4 * wave + role, sl, w3, acc);
     }
     __syncthreads();
-    // four hops
-    task_l4<LS, SS, A, DAG, S>(U, in, V, nb, 4 * wave + role, sl, w3, acc);
 
-    // the 16 partial sums of each site in a fixed order (two-hop buffer reused)
-    A(*red)[12][S][2] = reinterpret_cast<A(*)[12][S][2]>(&w2[0][0][0]);
+    // the TPS partial sums of each site in a fixed order (level buffers reused)
+    A(*red)[12][S][2] = reinterpret_cast<A(*)[12][S][2]>(&lds[0][0][0]);
     const int slot = 4 * wave + role;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -359,11 +451,11 @@ __global__ __launch_bounds__(256) void k_apply_recompute(Geom g, const LS *__res
     __syncthreads();
     if (threadIdx.x < 12 * S) {
         const int ss = threadIdx.x % S, comp = threadIdx.x / S;
-        const int st_site = blk * S + ss;
+        const int st_site = base + ss;
         if (st_site < g.V) {
             cx<A> sum = cmake<A>(red[0][comp][ss][0], red[0][comp][ss][1]);
 #pragma unroll
-            for (int o = 1; o < 16; ++o) sum = cadd(sum, cmake<A>(red[o][comp][ss][0], red[o][comp][ss][1]));
+            for (int o = 1; o < TPS; ++o) sum = cadd(sum, cmake<A>(red[o][comp][ss][0], red[o][comp][ss][1]));
             stnt(out + comp * V + st_site, caxpy(diag, ld_plane<A>(in + (size_t)comp * V, st_site), sum));
         }
     }

@@ -130,29 +130,6 @@ __device__ __forceinline__ void build_l3(const double2 *U, WT *W, size_t V, cons
     store_w<WT, NOFF>(W, V, site, valid, n, 1.0 / 6.0, w);
 }
 
-// First site of the 16-site x strip that a workgroup builds.  With gy > 0
-// (Lx a multiple of 16, gy | Ly, gz | Lz) the strips are ordered in groups of
-// Lx/16 x gy x gz strips at one t, a group walking t before the next group
-// (y blocks fastest): the workgroups an XCD runs at a time then cover a
-// compact (x, y, z) block, and its next t step re-reads the links of this one
-// from L2.  With gy = 0 the strips follow the site order.
-__device__ __forceinline__ int strip_base(const Geom &g, int blk, int gy, int gz) {
-    if (gy == 0) return blk * 16;
-    const int nxs = g.L[0] / 16;
-    int r = blk;
-    const int xs = r % nxs;
-    r /= nxs;
-    const int yy = r % gy;
-    r /= gy;
-    const int zz = r % gz;
-    r /= gz;
-    const int t = r % g.L[3];
-    r /= g.L[3];
-    const int nyb = g.L[1] / gy;
-    const int y = (r % nyb) * gy + yy, z = (r / nyb) * gz + zz;
-    return 16 * xs + y * g.stride[1] + z * g.stride[2] + t * g.stride[3];
-}
-
 template <typename WT, int NOFF>
 __global__ __launch_bounds__(512) void k_build_fused(Geom g, const double2 *__restrict__ U, WT *__restrict__ W, int gy,
                                                     int gz) {
@@ -240,11 +217,8 @@ hipError_t build_fused_t(const Geom &g, const double2 *U, void *W, int noff, hip
     // strip groups of Lx/16 x 4 x 4 (32 workgroups at Lx = 32, what an XCD
     // holds at a time); 32^3 x 64 FP32 W80: 7.43 ms in site order, 7.02 ms
     // with 4 x 4, 7.11-7.18 ms with 8 x 4, 4 x 8 or 8 x 8, 7.75 ms with 2 x 2
-    int gy = 0, gz = 0;
-    if (g.L[0] % 16 == 0) {
-        gy = g.L[1] % 4 == 0 ? 4 : g.L[1] % 2 == 0 ? 2 : 1;
-        gz = g.L[2] % 4 == 0 ? 4 : g.L[2] % 2 == 0 ? 2 : 1;
-    }
+    int gy, gz;
+    strip_groups(g, gy, gz);
     if (noff == 80)
         hipLaunchKernelGGL((k_build_fused<WT, 80>), grid, dim3(512), 0, st, g, U, (WT *)W, gy, gz);
     else
