@@ -28,9 +28,13 @@ PREC = {"f64": 0, "f32": 1, "f16": 2}
 # lattices with Lx a multiple of 32 and Ly of 16, where the FP32 and FP64
 # 80-offset apply with one right-hand side takes the 32x16 tile that the
 # benchmark times at 32^3 x 64 (one tile per (z, t); the second with z and t
-# of extent 2, so the tile's z and t neighbours wrap onto one slice)
+# of extent 2, so the tile's z and t neighbours wrap onto one slice).  With
+# Lx a multiple of 16 the transporter build and the recompute apply order
+# their 16-site x strips in groups of Lx/16 x gy x gz strips (gy, gz = 4, 2 or
+# 1 by divisibility): (16, 6, 2, 2) takes 2 x 2, (32, 16, 3, 4) 4 x 1,
+# (32, 16, 2, 2) 4 x 2 and (16, 3, 3, 2) 1 x 1.
 LATTICES = [(4, 4, 4, 4), (5, 3, 2, 6), (2, 2, 2, 2), (6, 4, 4, 8), (16, 6, 2, 2), (32, 16, 3, 4),
-            (32, 16, 2, 2)]
+            (32, 16, 2, 2), (16, 3, 3, 2)]
 
 
 @pytest.fixture(scope="module")
