@@ -15,13 +15,14 @@ hipError_t dot_partials_t(size_t n, int nrhs, const T *a, const T *b, double *pa
                           hipStream_t st);
 // out[2*rhs + {0,1}] = sum of the partials (fixed order)
 hipError_t dot_finish(int nrhs, const double *part, int nblk, double *out, hipStream_t st);
-// x += alpha p, r -= alpha q, |r|^2 partials
+// r -= alpha q, |r|^2 partials
 template <typename T>
-hipError_t update_xr(size_t n, int nrhs, const double *alpha, T *x, const T *p, T *r, const T *q,
-                     double *part, int nblk, hipStream_t st);
-// p = z + beta p
+hipError_t update_r(size_t n, int nrhs, const double *alpha, T *r, const T *q, double *part, int nblk, hipStream_t st);
+// x += alpha p, then p = z + beta p (the x step deferred to the p step, which
+// reads p anyway)
 template <typename T>
-hipError_t update_p(size_t n, int nrhs, const double *beta, const T *z, T *p, hipStream_t st);
+hipError_t update_xp(size_t n, int nrhs, const double *alpha, const double *beta, T *x, T *p, const T *z,
+                     hipStream_t st);
 // dst = src * scale[rhs]
 template <typename S, typename D>
 hipError_t convert(size_t n, int nrhs, const S *src, D *dst, const double *scale, hipStream_t st);
@@ -32,11 +33,12 @@ hipError_t accum(size_t n, int nrhs, const S *e, double *x, const double *scale,
 // site_blocks(V, nrhs) <= 4096 workgroups, summed by dot_finish
 int site_blocks(size_t V, int nrhs);
 hipError_t norm2_sites(size_t V, int nrhs, const float *a, double *part, int nblk, hipStream_t st);
-hipError_t update_xr_sites(size_t V, int nrhs, const double *alpha, float *x, const float *p, float *r, const float *q,
-                           double *part, int nblk, hipStream_t st);
-// p = z + beta p, |p|^2 partials
-hipError_t update_p_sites(size_t V, int nrhs, const double *beta, const float *z, float *p, double *part, int nblk,
+// r -= alpha q, |r|^2 partials
+hipError_t update_r_sites(size_t V, int nrhs, const double *alpha, float *r, const float *q, double *part, int nblk,
                           hipStream_t st);
+// x += alpha p, p = z + beta p, |p|^2 partials
+hipError_t update_xp_sites(size_t V, int nrhs, const double *alpha, const double *beta, float *x, float *p,
+                           const float *z, double *part, int nblk, hipStream_t st);
 // r = b - dx, |r|^2 partials
 hipError_t residual(size_t n, int nrhs, const double *b, const double *dx, double *r, double *part,
                     int nblk, hipStream_t st);

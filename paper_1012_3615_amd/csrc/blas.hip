@@ -71,12 +71,10 @@ __global__ __launch_bounds__(kB) void k_dot_finish(int nblk, const double *parti
     }
 }
 
-// x += alpha p ; r -= alpha q  (per-rhs real alpha), and |r|^2 partials
+// r -= alpha q  (per-rhs real alpha), and |r|^2 partials
 template <typename T>
-__global__ __launch_bounds__(kB) void k_update_xr(size_t n, const double *__restrict__ alpha,
-                                                  T *__restrict__ x, const T *__restrict__ p,
-                                                  T *__restrict__ r, const T *__restrict__ q,
-                                                  double *partial) {
+__global__ __launch_bounds__(kB) void k_update_r(size_t n, const double *__restrict__ alpha, T *__restrict__ r,
+                                                 const T *__restrict__ q, double *partial) {
     __shared__ double sh[kB];
     const size_t rhs = blockIdx.y;
     const double al = alpha[rhs];
@@ -84,7 +82,6 @@ __global__ __launch_bounds__(kB) void k_update_xr(size_t n, const double *__rest
     double acc = 0.0;
     for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB) {
         const size_t j = off + i;
-        x[j] = (T)((double)x[j] + al * (double)p[j]);
         const T rv = (T)((double)r[j] - al * (double)q[j]);
         r[j] = rv;
         acc = fma((double)rv, (double)rv, acc);
@@ -96,15 +93,21 @@ __global__ __launch_bounds__(kB) void k_update_xr(size_t n, const double *__rest
     }
 }
 
-// p = z + beta p
+// x += alpha p ; p = z + beta p  (the x step of the iteration, taken with the
+// p step so that p is read once)
 template <typename T>
-__global__ __launch_bounds__(kB) void k_update_p(size_t n, const double *__restrict__ beta,
-                                                 const T *__restrict__ z, T *__restrict__ p) {
+__global__ __launch_bounds__(kB) void k_update_xp(size_t n, const double *__restrict__ alpha,
+                                                  const double *__restrict__ beta, T *__restrict__ x,
+                                                  T *__restrict__ p, const T *__restrict__ z) {
     const size_t rhs = blockIdx.y;
-    const double be = beta[rhs];
+    const double al = alpha[rhs], be = beta[rhs];
     const size_t off = rhs * n;
-    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB)
-        p[off + i] = (T)((double)z[off + i] + be * (double)p[off + i]);
+    for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB) {
+        const size_t j = off + i;
+        const double pv = (double)p[j];
+        x[j] = (T)((double)x[j] + al * pv);
+        p[j] = (T)((double)z[j] + be * pv);
+    }
 }
 
 // dst = src * scale[rhs] (precision conversion), scale may be null (= 1)
@@ -251,10 +254,9 @@ __global__ __launch_bounds__(kSiteMax) void k_norm2_sites(size_t V, int nrhs, co
 }
 
 // x += alpha p ; r -= alpha q ; |r|^2 partials
-__global__ __launch_bounds__(kSiteMax) void k_update_xr_sites(size_t V, int nrhs, const double *__restrict__ alpha,
-                                                              float4 *__restrict__ x, const float4 *__restrict__ p,
-                                                              float4 *__restrict__ r, const float4 *__restrict__ q,
-                                                              double *partial) {
+__global__ __launch_bounds__(kSiteMax) void k_update_r_sites(size_t V, int nrhs, const double *__restrict__ alpha,
+                                                             float4 *__restrict__ r, const float4 *__restrict__ q,
+                                                             double *partial) {
     __shared__ double sh[kSiteMax];
     const SiteBlock b = site_block(nrhs);
     double acc = 0.0;
@@ -262,17 +264,12 @@ __global__ __launch_bounds__(kSiteMax) void k_update_xr_sites(size_t V, int nrhs
         const double al = alpha[b.c / 6];
         for (size_t s = (size_t)blockIdx.x * b.m + b.sl; s < V; s += (size_t)gridDim.x * b.m) {
             const size_t o = s * b.cps + b.c;
-            const float4 pv = p[o], qv = q[o];
-            float4 xv = x[o], rv = r[o];
-            xv.x = (float)((double)xv.x + al * (double)pv.x);
-            xv.y = (float)((double)xv.y + al * (double)pv.y);
-            xv.z = (float)((double)xv.z + al * (double)pv.z);
-            xv.w = (float)((double)xv.w + al * (double)pv.w);
+            const float4 qv = q[o];
+            float4 rv = r[o];
             rv.x = (float)((double)rv.x - al * (double)qv.x);
             rv.y = (float)((double)rv.y - al * (double)qv.y);
             rv.z = (float)((double)rv.z - al * (double)qv.z);
             rv.w = (float)((double)rv.w - al * (double)qv.w);
-            x[o] = xv;
             r[o] = rv;
             acc = sq4(rv, acc);
         }
@@ -280,25 +277,32 @@ __global__ __launch_bounds__(kSiteMax) void k_update_xr_sites(size_t V, int nrhs
     site_partial(b, nrhs, acc, sh, partial);
 }
 
-// p = z + beta p ; |p|^2 partials
-__global__ __launch_bounds__(kSiteMax) void k_update_p_sites(size_t V, int nrhs, const double *__restrict__ beta,
-                                                             const float4 *__restrict__ z, float4 *__restrict__ p,
-                                                             double *partial) {
+// x += alpha p ; p = z + beta p ; |p|^2 partials
+__global__ __launch_bounds__(kSiteMax) void k_update_xp_sites(size_t V, int nrhs, const double *__restrict__ alpha,
+                                                              const double *__restrict__ beta,
+                                                              float4 *__restrict__ x, float4 *__restrict__ p,
+                                                              const float4 *__restrict__ z, double *partial) {
     __shared__ double sh[kSiteMax];
     const SiteBlock b = site_block(nrhs);
     double acc = 0.0;
     if (b.on) {
-        const double be = beta[b.c / 6];
+        const double al = alpha[b.c / 6], be = beta[b.c / 6];
         for (size_t s = (size_t)blockIdx.x * b.m + b.sl; s < V; s += (size_t)gridDim.x * b.m) {
             const size_t o = s * b.cps + b.c;
-            const float4 zv = z[o];
-            float4 pv = p[o];
-            pv.x = (float)((double)zv.x + be * (double)pv.x);
-            pv.y = (float)((double)zv.y + be * (double)pv.y);
-            pv.z = (float)((double)zv.z + be * (double)pv.z);
-            pv.w = (float)((double)zv.w + be * (double)pv.w);
-            p[o] = pv;
-            acc = sq4(pv, acc);
+            const float4 pv = p[o], zv = z[o];
+            float4 xv = x[o];
+            xv.x = (float)((double)xv.x + al * (double)pv.x);
+            xv.y = (float)((double)xv.y + al * (double)pv.y);
+            xv.z = (float)((double)xv.z + al * (double)pv.z);
+            xv.w = (float)((double)xv.w + al * (double)pv.w);
+            float4 pn;
+            pn.x = (float)((double)zv.x + be * (double)pv.x);
+            pn.y = (float)((double)zv.y + be * (double)pv.y);
+            pn.z = (float)((double)zv.z + be * (double)pv.z);
+            pn.w = (float)((double)zv.w + be * (double)pv.w);
+            x[o] = xv;
+            p[o] = pn;
+            acc = sq4(pn, acc);
         }
     }
     site_partial(b, nrhs, acc, sh, partial);
@@ -328,16 +332,16 @@ hipError_t norm2_sites(size_t V, int nrhs, const float *a, double *part, int nbl
                        part);
     return hipGetLastError();
 }
-hipError_t update_xr_sites(size_t V, int nrhs, const double *alpha, float *x, const float *p, float *r, const float *q,
-                           double *part, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_update_xr_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, alpha,
-                       (float4 *)x, (const float4 *)p, (float4 *)r, (const float4 *)q, part);
+hipError_t update_r_sites(size_t V, int nrhs, const double *alpha, float *r, const float *q, double *part, int nblk,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_update_r_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, alpha,
+                       (float4 *)r, (const float4 *)q, part);
     return hipGetLastError();
 }
-hipError_t update_p_sites(size_t V, int nrhs, const double *beta, const float *z, float *p, double *part, int nblk,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_update_p_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, beta,
-                       (const float4 *)z, (float4 *)p, part);
+hipError_t update_xp_sites(size_t V, int nrhs, const double *alpha, const double *beta, float *x, float *p,
+                           const float *z, double *part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_xp_sites, dim3(nblk), dim3(6 * nrhs * site_m(nrhs)), 0, st, V, nrhs, alpha, beta,
+                       (float4 *)x, (float4 *)p, (const float4 *)z, part);
     return hipGetLastError();
 }
 template <typename T>
@@ -355,21 +359,23 @@ hipError_t dot_finish(int nrhs, const double *part, int nblk, double *out, hipSt
 }
 
 template <typename T>
-hipError_t update_xr(size_t n, int nrhs, const double *alpha, T *x, const T *p, T *r, const T *q,
-                     double *part, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_update_xr<T>, dim3(nblk, nrhs), dim3(kB), 0, st, n, alpha, x, p, r, q, part);
+hipError_t update_r(size_t n, int nrhs, const double *alpha, T *r, const T *q, double *part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_r<T>, dim3(nblk, nrhs), dim3(kB), 0, st, n, alpha, r, q, part);
     return hipGetLastError();
 }
-template hipError_t update_xr<double>(size_t, int, const double *, double *, const double *, double *, const double *, double *, int, hipStream_t);
-template hipError_t update_xr<float>(size_t, int, const double *, float *, const float *, float *, const float *, double *, int, hipStream_t);
+template hipError_t update_r<double>(size_t, int, const double *, double *, const double *, double *, int, hipStream_t);
+template hipError_t update_r<float>(size_t, int, const double *, float *, const float *, double *, int, hipStream_t);
 
 template <typename T>
-hipError_t update_p(size_t n, int nrhs, const double *beta, const T *z, T *p, hipStream_t st) {
-    hipLaunchKernelGGL(k_update_p<T>, dim3(nblocks(n), nrhs), dim3(kB), 0, st, n, beta, z, p);
+hipError_t update_xp(size_t n, int nrhs, const double *alpha, const double *beta, T *x, T *p, const T *z,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_update_xp<T>, dim3(nblocks(n), nrhs), dim3(kB), 0, st, n, alpha, beta, x, p, z);
     return hipGetLastError();
 }
-template hipError_t update_p<double>(size_t, int, const double *, const double *, double *, hipStream_t);
-template hipError_t update_p<float>(size_t, int, const double *, const float *, float *, hipStream_t);
+template hipError_t update_xp<double>(size_t, int, const double *, const double *, double *, double *, const double *,
+                                      hipStream_t);
+template hipError_t update_xp<float>(size_t, int, const double *, const double *, float *, float *, const float *,
+                                     hipStream_t);
 
 template <typename S, typename D>
 hipError_t convert(size_t n, int nrhs, const S *src, D *dst, const double *scale, hipStream_t st) {

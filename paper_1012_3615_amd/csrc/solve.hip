@@ -8,8 +8,9 @@
 // Inner loop (CGNE, FP32 storage with W_lo in FP32 or FP16, or FP64 with
 //   W_hi for the plain solver), per right-hand side i:
 //     z = D^dag r, p = z, zz = |z|^2
-//     repeat: q = D p; alpha = zz/|q|^2; e += alpha p; r -= alpha q;
-//             z = D^dag r; beta = |z|^2/zz; p = z + beta p
+//     repeat: q = D p; alpha = zz/|q|^2; r -= alpha q;
+//             z = D^dag r; beta = |z|^2/zz; e += alpha p; p = z + beta p
+//   (e is updated in the pass that forms the next p, so p is read once)
 //   until |r| <= inner_tol |r_0|.  All right-hand sides share each fused
 //   apply; a converged column is frozen on the device (alpha = 0).  The host
 //   reads the per-column state every check_every iterations.
@@ -153,21 +154,23 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
         BRI_TRY(norm2<T>(c, q, qq2, sites));
         BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
         if (sites)
-            BRI_HIP(update_xr_sites(c.g.V, c.nrhs, stv + 3 * c.nrhs, (float *)e, (const float *)p, (float *)r,
-                                    (const float *)q, part, nb, c.st),
-                    "update x,r");
+            BRI_HIP(update_r_sites(c.g.V, c.nrhs, stv + 3 * c.nrhs, (float *)r, (const float *)q, part, nb, c.st),
+                    "update r");
         else
-            BRI_HIP(update_xr<T>(c.n, c.nrhs, stv + 3 * c.nrhs, e, p, r, q, part, nb, c.st), "update x,r");
+            BRI_HIP(update_r<T>(c.n, c.nrhs, stv + 3 * c.nrhs, r, q, part, nb, c.st), "update r");
         BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
         BRI_TRY(apply(r, z, !c.dag, rr2));
         BRI_TRY(norm2<T>(c, z, zz2, sites));
         BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
+        // x += alpha p with this iteration's alpha, taken in the pass that
+        // also forms the next p
         if (sites) {
-            BRI_HIP(update_p_sites(c.g.V, c.nrhs, stv + 4 * c.nrhs, (const float *)z, (float *)p, part, nb, c.st),
-                    "update p");
+            BRI_HIP(update_xp_sites(c.g.V, c.nrhs, stv + 3 * c.nrhs, stv + 4 * c.nrhs, (float *)e, (float *)p,
+                                    (const float *)z, part, nb, c.st),
+                    "update x,p");
             BRI_HIP(dot_finish(c.nrhs, part, nb, pp2, c.st), "pp finish");
         } else {
-            BRI_HIP(update_p<T>(c.n, c.nrhs, stv + 4 * c.nrhs, z, p, c.st), "update p");
+            BRI_HIP(update_xp<T>(c.n, c.nrhs, stv + 3 * c.nrhs, stv + 4 * c.nrhs, e, p, z, c.st), "update x,p");
         }
         *applies += 2;
         *iters = it;
