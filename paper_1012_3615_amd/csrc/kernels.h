@@ -60,7 +60,13 @@ hipError_t spinor_bound2(const Geom &g, int nrhs, const float2 *in, double *boun
 hipError_t spinor_sites(const Geom &g, int nrhs, const float2 *src, float2 *dst, bool to_sites, double *bound2,
                         hipStream_t st);
 hipError_t apply_mfma(const Geom &g, const void *Wm, const float2 *in, float2 *out, int nrhs, double diag,
-                      const double *table, bool dag, const double *bound2, int bstride, int tlen, hipStream_t st);
+                      const double *table, bool dag, const double *bound2, int bstride, int tlen, hipStream_t st,
+                      double *nrm = nullptr);
+// workgroups per block of 12 right-hand sides of apply_mfma (tlen as there):
+// with nrm != nullptr the apply also writes, per right-hand side r and such
+// workgroup i, the partial |out|^2 of its sites at nrm[2 (r n + i)] (and 0 at
+// the odd index), n being this count, for dot_finish
+long long mfma_workgroups(const Geom &g, int tlen);
 
 // production.hip
 hipError_t project_su3_soa(const double2 *A, double2 *Y, int64_t n, hipStream_t st);

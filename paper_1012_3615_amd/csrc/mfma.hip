@@ -76,6 +76,7 @@ struct Args {
     float2 *out;
     const double *bound2;   // per right-hand side (stride bstride): >= max |component|^2 of in
     int bstride;
+    double *nrm;            // optional: per (right-hand side, workgroup of its block) partial |out|^2
     float diag, slam, srho;  // lambda_0 + m; channel normalisations
     float lam[5], rho[5];    // lambda_k / slam, rho_k / srho (k = 1..4; rho negated for D^dag)
 };
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     int rest = xcd_block(blockIdx.x, gridDim.x);
     const int rb = rest % nrb;
     rest /= nrb;
+    const int iwg = rest;  // workgroup within the right-hand-side block (partial norm index)
     const int ix = rest % a.gx;
     rest /= a.gx;
     const int iy = rest % a.gy;
@@ -323,6 +325,10 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     static_assert(comp(4 * QA + 2, 3) == -1 && comp(4 * QA + 3, 3) == 0 && comp(4 * QA + 4, 3) == 0,
                   "reduction steps ordered by n_t");
     int tm = 0;  // t mod 3 (table of the current t)
+    const bool want_nrm = a.nrm != nullptr;
+    double nacc[NT];  // the lane's |out|^2 per column tile (its right-hand side 4 j + er4)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) nacc[j] = 0.0;
     auto compute_site = [&](size_t site, int srp, size_t next, bool valid, int t) __attribute__((always_inline)) {
         f4 acc[2][NT];
 #pragma unroll
@@ -418,6 +424,7 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
                 // the 48 lanes of a column tile write 384 contiguous bytes of
                 // the site record
                 *(float2 *)(out + site * recb + out_ofs(j)) = o;
+                if (want_nrm) nacc[j] = fma((double)o.y, (double)o.y, fma((double)o.x, (double)o.x, nacc[j]));
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -445,6 +452,30 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
         // again, so that every load is issued)
         const size_t next = site_of(0, t + 1 < t1 ? t + 1 : t);
         compute_site(site_of(0, t), srp0, next, nval > 0, t);
+    }
+    if (want_nrm) {
+        // |out|^2 per right-hand side: over the 12 lanes of a (column tile,
+        // rhs) pair (spin: lane bits 0-1, colour: bits 4-5; lanes 48-63 hold
+        // zero), then over the wavefronts in order, in fixed order throughout
+        double *ws = (double *)&sm.scr[w][0][0];  // this wavefront's epilogue tile, free now
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            double v = nacc[j];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if ((lane & 0x33) == 0) ws[4 * j + er4] = v;
+        }
+        __syncthreads();
+        if (tid < 4 * NT && tid < nr) {
+            double sum = 0.0;
+            for (int v = 0; v < NWAVE; ++v) sum += ((const double *)&sm.scr[v][0][0])[tid];
+            const size_t nwg = gridDim.x / nrb;
+            double *o = a.nrm + 2 * ((size_t)(r0 + tid) * nwg + iwg);
+            o[0] = sum;
+            o[1] = 0.0;
+        }
     }
 }
 
@@ -618,13 +649,24 @@ hipError_t spinor_sites(const Geom &g, int nrhs, const float2 *src, float2 *dst,
     return hipGetLastError();
 }
 
+static int mfma_tlen(const Geom &g, int tlen) {
+    return tlen > 0 ? (tlen < g.L[3] ? tlen : g.L[3]) : (g.L[3] < 64 ? g.L[3] : 64);
+}
+
+long long mfma_workgroups(const Geom &g, int tlen) {
+    const int tl = mfma_tlen(g, tlen);
+    return (long long)((g.L[0] + mfma::TX - 1) / mfma::TX) * ((g.L[1] + mfma::TY - 1) / mfma::TY) * g.L[2] *
+           ((g.L[3] + tl - 1) / tl);
+}
+
 hipError_t apply_mfma(const Geom &g, const void *Wm, const float2 *in, float2 *out, int nrhs, double diag,
-                      const double *table, bool dag, const double *bound2, int bstride, int tlen, hipStream_t st) {
+                      const double *table, bool dag, const double *bound2, int bstride, int tlen, hipStream_t st,
+                      double *nrm) {
     mfma::Args a{};
     a.g = g;
     a.ntx = (g.L[0] + mfma::TX - 1) / mfma::TX;
     a.nty = (g.L[1] + mfma::TY - 1) / mfma::TY;
-    a.tlen = tlen > 0 ? (tlen < g.L[3] ? tlen : g.L[3]) : (g.L[3] < 64 ? g.L[3] : 64);
+    a.tlen = mfma_tlen(g, tlen);
     a.ntc = (g.L[3] + a.tlen - 1) / a.tlen;
     a.nrhs = nrhs;
     // block groups of up to 2 x 4 x 4 tiles (32 workgroups, one per CU of an XCD)
@@ -640,6 +682,7 @@ hipError_t apply_mfma(const Geom &g, const void *Wm, const float2 *in, float2 *o
     a.out = out;
     a.bound2 = bound2;
     a.bstride = bstride;
+    a.nrm = nrm;
     a.diag = (float)diag;
     double lam[5], rho[5], sl = 0.0, sr = 0.0;
     for (int k = 1; k <= 4; ++k) {

@@ -129,12 +129,24 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
     double *pp2 = zz2 + 2 * c.nrhs;
     const bool sites = op.mfma;
     const double diag = (op.coef ? op.coef[0] : lam_k(0)) + c.mass;
-    auto apply = [&](const T *in, T *out, bool dag, const double *in2) -> bri_status {
-        if (sites)
-            return hip_check(apply_mfma(c.g, op.W, (const float2 *)in, (float2 *)out, c.nrhs, diag, op.coef, dag, in2,
-                                        2, 0, c.st),
-                             "apply (matrix cores)");
-        return apply_op(c.d, op, sp, c.mass, in, out, c.nrhs, c.st, dag);
+    // out = D in (or D^dag in) and out2 = |out|^2 per right-hand side; the
+    // matrix-core apply forms the norm partials itself when they fit the
+    // partial buffer (up to 4096 per right-hand side)
+    const long long mwg = sites ? mfma_workgroups(c.g, 0) : 0;
+    const bool fused_norm = sites && mwg <= 4096;
+    auto apply_norm = [&](const T *in, T *out, bool dag, const double *in2, double *out2) -> bri_status {
+        if (sites) {
+            BRI_HIP(apply_mfma(c.g, op.W, (const float2 *)in, (float2 *)out, c.nrhs, diag, op.coef, dag, in2, 2, 0,
+                               c.st, fused_norm ? part : nullptr),
+                    "apply (matrix cores)");
+            if (fused_norm) {
+                BRI_HIP(dot_finish(c.nrhs, part, (int)mwg, out2, c.st), "norm finish");
+                return BRI_OK;
+            }
+        } else {
+            BRI_TRY(apply_op(c.d, op, sp, c.mass, in, out, c.nrhs, c.st, dag));
+        }
+        return norm2<T>(c, out, out2, sites);
     };
     double *stv = (double *)(c.w + c.L.stv);
     const int nb = sites ? site_blocks(c.g.V, c.nrhs) : dot_blocks(c.n);
@@ -142,16 +154,14 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
 
     BRI_HIP(zero(c.n * c.nrhs, e, c.st), "zero");
     BRI_TRY(norm2<T>(c, r, rr2, sites));
-    BRI_TRY(apply(r, z, !c.dag, rr2));
+    BRI_TRY(apply_norm(r, z, !c.dag, rr2, zz2));
     ++*applies;
-    BRI_TRY(norm2<T>(c, z, zz2, sites));
     BRI_HIP(cg_init(c.nrhs, stv, rr2, zz2, rel * rel, c.st), "cg init");
     BRI_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, c.st), "copy");
     if (sites) BRI_HIP(hipMemcpyAsync(pp2, zz2, 2 * c.nrhs * sizeof(double), hipMemcpyDeviceToDevice, c.st), "copy");
     std::vector<double> hs(7 * c.nrhs);
     for (int it = 1; it <= max_it; ++it) {
-        BRI_TRY(apply(p, q, c.dag, pp2));
-        BRI_TRY(norm2<T>(c, q, qq2, sites));
+        BRI_TRY(apply_norm(p, q, c.dag, pp2, qq2));
         BRI_HIP(cg_alpha(c.nrhs, stv, qq2, c.st), "alpha");
         if (sites)
             BRI_HIP(update_r_sites(c.g.V, c.nrhs, stv + 3 * c.nrhs, (float *)r, (const float *)q, part, nb, c.st),
@@ -159,8 +169,7 @@ bri_status inner_cgne(const Ctx &c, const OpDesc &op, bri_prec sp, double rel, i
         else
             BRI_HIP(update_r<T>(c.n, c.nrhs, stv + 3 * c.nrhs, r, q, part, nb, c.st), "update r");
         BRI_HIP(dot_finish(c.nrhs, part, nb, rr2, c.st), "rr finish");
-        BRI_TRY(apply(r, z, !c.dag, rr2));
-        BRI_TRY(norm2<T>(c, z, zz2, sites));
+        BRI_TRY(apply_norm(r, z, !c.dag, rr2, zz2));
         BRI_HIP(cg_beta(c.nrhs, stv, rr2, zz2, c.st), "beta");
         // x += alpha p with this iteration's alpha, taken in the pass that
         // also forms the next p
