@@ -169,14 +169,79 @@ def cpu_baseline(u, psi, got, full=False):
                 "gflops": FLOPS_PER_SITE * vs / wall / 1e9, "cpu_over_wall": float(sum(cpus) / sum(walls))}
     last = per_size["x".join(map(str, sizes[-1]))]
     used = max(1, int(round(max(e["cpu_over_wall"] for e in per_size.values()))))
-    return {"value": last["sites_per_s"] / V, "unit": "applies/s", "cores": used, "kind": "oracle",
-            "sample": (f"whole-field FP64 numpy oracle (oracle.dirac.apply) on "
-                       f"{', '.join('x'.join(map(str, d)) for d in sizes)} lattices (links exp(i {EPS} H)), "
-                       f"warm-up then median of 3 each; value = the per-site rate at "
-                       f"{'x'.join(map(str, sizes[-1]))} scaled to the 32x32x32x64 volume"),
-            "host_cpu_count": ncpu, "blas_threads": [list(b) for b in blas],
-            "threads_used": f"process CPU time / wall time = {max(e['cpu_over_wall'] for e in per_size.values()):.2f}",
-            "sizes": per_size}, spot_err
+    single = {"value": last["sites_per_s"] / V, "cores": used,
+              "threads_used": f"process CPU time / wall time = {max(e['cpu_over_wall'] for e in per_size.values()):.2f}"}
+    # the host's throughput: one oracle process per core of the GPU's CPU share
+    # (at most 16), each timing three 8^4 applications after a warm-up, all
+    # released together; the rate is the parent's count of applications over
+    # the wall time of the whole concurrent window
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = ncpu
+    nproc = max(1, min(16, avail))
+    multi = cpu_throughput(nproc, 8)
+    value = multi["sites_per_s"] / V if multi else single["value"]
+    return {"value": value, "unit": "applies/s", "cores": nproc if multi else used, "kind": "oracle",
+            "sample": (f"whole-field FP64 numpy oracle (oracle.dirac.apply), unmodified: {nproc} concurrent "
+                       f"processes (one BLAS/OpenMP thread each) on 8x8x8x8 lattices (links exp(i {EPS} H)), "
+                       f"three applications each after a warm-up, released together; value = sites per second "
+                       f"of the whole window scaled to the 32x32x32x64 volume; single-process timings at "
+                       f"{', '.join('x'.join(map(str, d)) for d in sizes)} (median of 3) under 'single_process'"),
+            "host_cpu_count": ncpu, "cpu_affinity": avail, "blas_threads": [list(b) for b in blas],
+            "multi_process": multi, "single_process": single, "sizes": per_size}, spot_err
+
+
+def cpu_worker(L):
+    """One oracle process of the throughput leg: inputs and a warm-up, then
+    'ready'; on a line from the parent, three timed applications on L^4."""
+    import numpy as np
+    import synth
+    from oracle import dirac
+    dims = (L, L, L, L)
+    uu = synth.gauge_links(dims, EPS, SEED_U)
+    pp = synth.gaussian_spinor(dims, SEED_PSI, nrhs=1)[0]
+    dirac.apply(uu, pp, MASS)
+    print("ready", flush=True)
+    sys.stdin.readline()
+    walls = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        dirac.apply(uu, pp, MASS)
+        walls.append(time.perf_counter() - t0)
+    print(json.dumps({"walls": walls}), flush=True)
+
+
+def cpu_throughput(nproc, L):
+    """Runs nproc cpu_worker processes (this file with --cpu-worker L) and
+    returns the aggregate rate, or None if a worker failed."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(L)],
+                              stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+             for _ in range(nproc)]
+    try:
+        if any(p.stdout.readline().strip() != "ready" for p in procs):
+            return None
+        t0 = time.perf_counter()
+        for p in procs:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        res = [json.loads(p.stdout.readline()) for p in procs]
+        window = time.perf_counter() - t0
+    finally:
+        for p in procs:
+            try:
+                p.stdin.close()
+            except OSError:
+                pass
+            p.wait(timeout=60)
+    vs = L ** 4
+    applies = sum(len(r["walls"]) for r in res)
+    per = sorted(w for r in res for w in r["walls"])
+    return {"processes": nproc, "lattice": [L] * 4, "window_s": window, "applications": applies,
+            "sites_per_s": applies * vs / window, "median_application_s": per[len(per) // 2],
+            "gflops": FLOPS_PER_SITE * applies * vs / window / 1e9}
 
 
 def traffic_from_profile(launch_bytes_alg):
@@ -644,7 +709,11 @@ def main():
                     help="also time the whole-field oracle at 16^3x32 (about four minutes)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-worker", type=int, default=0, help=argparse.SUPPRESS)
     a = ap.parse_args()
+    if a.cpu_worker:
+        cpu_worker(a.cpu_worker)
+        return
     if a.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {a.gpus}); "
               "the multi-GPU decomposition is a design, not a measured path", file=sys.stderr)
