@@ -235,7 +235,11 @@ def cpu_throughput(nproc, L):
                 p.stdin.close()
             except OSError:
                 pass
-            p.wait(timeout=60)
+            try:
+                p.wait(timeout=120)
+            except subprocess.TimeoutExpired:
+                p.kill()
+                p.wait()
     vs = L ** 4
     applies = sum(len(r["walls"]) for r in res)
     per = sorted(w for r in res for w in r["walls"])
