@@ -521,7 +521,7 @@ def gradient_timing(torch, bri, dev):
     return {"forward_ms": tf, "backward_ms": tb, "backward_over_forward": tb / tf,
             "grad_links_w": {"ms": tg, "alg_bytes_per_site": GRAD_BYTES_PER_SITE, "alg_GBs": gbps,
                              "hbm_frac": gbps / HBM_PEAK_GBS, "bound": "hbm",
-                             "kernels": "k_grad_level (4 launches) + k_grad_gather"}}
+                             "kernels": "k_grad_fused + k_grad_gather"}}
 
 
 def build_roofline(torch, bri, U64, steps=3):

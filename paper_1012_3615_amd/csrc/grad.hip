@@ -21,7 +21,7 @@
 #include <cmath>
 
 #include "abi_internal.h"
-#include "stencil.h"
+#include "apply_recompute.h"
 #include "kernels.h"
 
 namespace bri {
@@ -48,13 +48,13 @@ __device__ __forceinline__ int site_at(const Geom &g, const int c[4], int d0, in
            g.L[0] * (w(c[1] + d1, g.L[1]) + g.L[1] * (w(c[2] + d2, g.L[2]) + g.L[2] * w(c[3] + d3, g.L[3])));
 }
 
-// direct gradient of the transporter of offset n at the site (y = x + n):
-// G = sum_rhs sum_s (C(n) chi(x))_s psi_s(x+n)^dag
+// direct gradient of the transporter of offset n (K hops) at the site
+// (y = x + n): G = sum_rhs sum_s (C(n) chi(x))_s psi_s(x+n)^dag
+template <int K>
 __device__ inline void grad_direct(int site, int y, size_t V, const double2 *__restrict__ chi,
                                    const double2 *__restrict__ psi, int nrhs, const int n[4], const Coef<double> &cf,
                                    cx<double> G[3][3]) {
-    const int k = (n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0);
-    const double lam = coef_pick(cf.lam, k), rho = coef_pick(cf.rho, k);
+    const double lam = cf.lam[K], rho = cf.rho[K];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -87,59 +87,64 @@ __device__ inline void grad_direct(int site, int y, size_t V, const double2 *__r
 
 // Offsets of each hop count k (index i = (nx+1) + 3(ny+1) + 9(nz+1) + 27(nt+1),
 // increasing): 1, 8, 24, 32, 16 of them.
-struct LevelTable {
-    signed char idx[5][32];
-    int count[5];
-};
-constexpr LevelTable make_levels() {
-    LevelTable t{};
-    for (int i = 0; i < 81; ++i) {
-        const int k = (i % 3 != 1) + ((i / 3) % 3 != 1) + ((i / 9) % 3 != 1) + (i / 27 != 1);
-        t.idx[k][t.count[k]++] = (signed char)i;
-    }
-    return t;
-}
-constexpr LevelTable kLevels = make_levels();
-__constant__ LevelTable c_levels = make_levels();
-
-// steps 1 and 2, one launch per hop count k from 4 down to 1: the full
+// Steps 1 and 2 in one kernel, through the hop levels 4 -> 1: the full
 // gradient of the transporter of offset P (k hops) is its direct term plus
 // what its parents p = P + s e_nu (nu outside the support of P, s = +-1; one
 // hop more) pass down through their last link,
 //   G_P += (1/|p|) G_p L^dag,  L = U_nu(x+P) (s = +1) or U_nu(x+P-nu)^dag (s = -1),
-// the reverse of the same-site recursion that builds the transporters.  The
-// parents are final once the previous launch is done, so every G is written
-// once.  One thread per (site, offset of the level): the offsets of a block
-// of sites are consecutive blocks, kept on one XCD, so chi(x) and the psi
-// neighbours they share are read through that XCD's L2.
-__global__ __launch_bounds__(kB) void k_grad_level(Geom g, int k, const double2 *__restrict__ U,
-                                                   const double2 *__restrict__ chi,
-                                                   const double2 *__restrict__ psi, int nrhs,
-                                                   double2 *__restrict__ G80, Coef<double> cf) {
-    const int cnt = c_levels.count[k];
-    const int lin = xcd_block(blockIdx.x, gridDim.x);
-    const int site = (lin / cnt) * kB + threadIdx.x;
-    if (site >= g.V) return;
-    const int i = c_levels.idx[k][lin % cnt];
+// the reverse of the same-site recursion that builds the transporters.  16
+// consecutive sites x 32 threads per workgroup; every G of a level is written
+// to G80 for the gather and kept in LDS, where the next level pulls it
+// (levels 4 and 2 in one buffer, level 3 in the other: 129 KB, one
+// workgroup per CU; one launch per level, with the parents read back from
+// memory, took 1.1 ms at 16^3 x 32).  Each wavefront takes
+// offsets of one support at a time, its four roles sign combinations, so the
+// directions without a parent pull are the same across the wavefront:
+//   four hops: wave w < 4, sign bits 4 w + role (bit mu: n_mu = -1);
+//   three hops: wave w, the support without direction w / 2, sign bits
+//     4 (w % 2) + role over the support in increasing order;
+//   two hops: wave w < 6, the direction pair w (pair_lo, pair_hi), role the signs;
+//   one hop: wave w < 4, direction w, role 0 / 1 the sign.
+// LDS slots: level 4 its sign bits, level 3 8 Q + sign bits, level 2 4 P +
+// sign bits (the slot layout of the recompute apply).
+__device__ __forceinline__ int grad_slot(const int (&p)[4], int k) {
+    if (k == 4) return (p[0] < 0) | ((p[1] < 0) << 1) | ((p[2] < 0) << 2) | ((p[3] < 0) << 3);
+    if (k == 3) {
+        const int q = p[0] == 0 ? 0 : p[1] == 0 ? 1 : p[2] == 0 ? 2 : 3;
+        int b = 0, j = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+            if (mu != q) b |= (p[mu] < 0) << j++;
+        return 8 * q + b;
+    }
+    // k == 2 (selects, not run-time indices, which would place p in scratch)
+    const int lo = p[0] != 0 ? 0 : p[1] != 0 ? 1 : 2;
+    const int hi = p[3] != 0 ? 3 : p[2] != 0 ? 2 : 1;
+    const int plo = lo == 0 ? p[0] : lo == 1 ? p[1] : p[2];
+    const int phi = hi == 3 ? p[3] : hi == 2 ? p[2] : p[1];
+    return 4 * pair_index(lo, hi) + (plo < 0) + 2 * (phi < 0);
+}
+
+template <int K>
+__device__ __forceinline__ void grad_level_task(const Geom &g, const int (&n)[4], const int (&c)[4], int site,
+                                                bool valid, int sl, const double2 *__restrict__ U,
+                                                const double2 *__restrict__ chi, const double2 *__restrict__ psi,
+                                                int nrhs, double2 *__restrict__ G80, const Coef<double> &cf,
+                                                cx<double> (*prev)[9][16], cx<double> (*cur)[9][16], int cslot) {
     const size_t V = (size_t)g.V;
-    int c[4];
-    coords(g, site, c);
-    const int n[4] = {i % 3 - 1, (i / 3) % 3 - 1, (i / 9) % 3 - 1, i / 27 - 1};
-    const double inv = 1.0 / (k + 1);
+    const int i = (n[0] + 1) + 3 * (n[1] + 1) + 9 * (n[2] + 1) + 27 * (n[3] + 1);
+    const double inv = 1.0 / (K + 1);
     cx<double> G[3][3];
-    grad_direct(site, site_at(g, c, n[0], n[1], n[2], n[3]), V, chi, psi, nrhs, n, cf, G);
-    // nu and sgn unrolled: the offset arrays are then indexed at compile time
-    // (registers, not scratch)
+    grad_direct<K>(site, site_at(g, c, n[0], n[1], n[2], n[3]), V, chi, psi, nrhs, n, cf, G);
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) {
-        if (k == 4 || n[nu] != 0) continue;
+        if (K == 4 || n[nu] != 0) continue;
 #pragma unroll
         for (int sgn = -1; sgn <= 1; sgn += 2) {
             int p[4] = {n[0], n[1], n[2], n[3]};
             p[nu] = sgn;
-            const int ip = (p[0] + 1) + 3 * (p[1] + 1) + 9 * (p[2] + 1) + 27 * (p[3] + 1);
             cx<double> Gp[3][3];
-            ldm(G80 + (size_t)plane80_rt(ip) * 9 * V + site, V, Gp);
+            lds_get<double, 16>(prev, grad_slot(p, K + 1), sl, Gp);
             // the parent's last link: base site x+P (forward) or x+P-nu (backward)
             int d[4] = {n[0], n[1], n[2], n[3]};
             if (sgn < 0) d[nu] = -1;
@@ -163,7 +168,54 @@ __global__ __launch_bounds__(kB) void k_grad_level(Geom g, int k, const double2 
                 }
         }
     }
-    stm(G80 + (size_t)plane80_rt(i) * 9 * V + site, V, G);
+    if (cur) lds_put<double, 16>(cur, cslot, sl, G);
+    if (valid) stm(G80 + (size_t)plane80_rt(i) * 9 * V + site, V, G);
+}
+
+__global__ __launch_bounds__(512) void k_grad_fused(Geom g, const double2 *__restrict__ U,
+                                                    const double2 *__restrict__ chi, const double2 *__restrict__ psi,
+                                                    int nrhs, double2 *__restrict__ G80, Coef<double> cf, int gy,
+                                                    int gz) {
+    constexpr int S = 16;
+    __shared__ cx<double> bufA[24][9][S];  // four hops, then two hops
+    __shared__ cx<double> bufB[32][9][S];  // three hops
+    const int sl = threadIdx.x % S;
+    const int role = (threadIdx.x / S) % 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int s0 = strip_base(g, xcd_block(blockIdx.x, gridDim.x), gy, gz) + sl;
+    const bool valid = s0 < g.V;
+    const int site = valid ? s0 : 0;
+    int c[4];
+    coords(g, site, c);
+
+    if (wave < 4) {  // four hops
+        const int bits = 4 * wave + role;
+        const int n[4] = {(bits & 1) ? -1 : 1, (bits & 2) ? -1 : 1, (bits & 4) ? -1 : 1, (bits & 8) ? -1 : 1};
+        grad_level_task<4>(g, n, c, site, valid, sl, U, chi, psi, nrhs, G80, cf, nullptr, bufA, bits);
+    }
+    __syncthreads();
+    {  // three hops
+        const int q = wave >> 1, bits = 4 * (wave & 1) + role;
+        int n[4], j = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) n[mu] = mu == q ? 0 : (((bits >> j++) & 1) ? -1 : 1);
+        grad_level_task<3>(g, n, c, site, valid, sl, U, chi, psi, nrhs, G80, cf, bufA, bufB, 8 * q + bits);
+    }
+    __syncthreads();
+    if (wave < 6) {  // two hops (level 4 in bufA is no longer read)
+        const int lo = pair_lo(wave), hi = pair_hi(wave);
+        int n[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) n[mu] = mu == lo ? ((role & 1) ? -1 : 1) : mu == hi ? ((role & 2) ? -1 : 1) : 0;
+        grad_level_task<2>(g, n, c, site, valid, sl, U, chi, psi, nrhs, G80, cf, bufB, bufA, 4 * wave + role);
+    }
+    __syncthreads();
+    if (wave < 4 && role < 2) {  // one hop
+        int n[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) n[mu] = mu == wave ? (role ? -1 : 1) : 0;
+        grad_level_task<1>(g, n, c, site, valid, sl, U, chi, psi, nrhs, G80, cf, bufA, nullptr, 0);
+    }
 }
 
 // step 3: gather onto the links; the lower-level transporter W(x, m) is read
@@ -288,9 +340,10 @@ bri_status grad_steps(const Geom &g, const double *U, const double2 *W40, const 
                       int nrhs, double scale, const double *coef, double *gradU, double2 *G80, hipStream_t st) {
     dim3 grid((g.V + kB - 1) / kB);
     const Coef<double> cf = make_coef<double>(coef);
-    for (int k = 4; k >= 1; --k)
-        hipLaunchKernelGGL(k_grad_level, dim3(grid.x * kLevels.count[k]), dim3(kB), 0, st, g, k, (const double2 *)U,
-                           (const double2 *)chi, (const double2 *)psi, nrhs, G80, cf);
+    int gy, gz;
+    strip_groups(g, gy, gz);
+    hipLaunchKernelGGL(k_grad_fused, dim3((g.V + 15) / 16), dim3(512), 0, st, g, (const double2 *)U,
+                       (const double2 *)chi, (const double2 *)psi, nrhs, G80, cf, gy, gz);
     hipLaunchKernelGGL(k_grad_gather, dim3(grid.x * 4), dim3(kB), 0, st, g, W40, (const double2 *)G80,
                        (double2 *)gradU, scale);
     return hip_check(hipGetLastError(), "gradient kernels");
