@@ -34,7 +34,7 @@ def bri():
 # the y halo wraps onto the tile itself; two tiles in x and y), with two z
 # slices per workgroup where Lz is even and one where it is odd
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 5, 3, 4), (2, 3, 2, 5), (16, 6, 2, 2), (32, 8, 2, 3),
-                                  (64, 16, 2, 2), (32, 8, 3, 2)])
+                                  (64, 16, 2, 2), (32, 8, 3, 2), (32, 8, 4, 3)])
 def test_wilson_matches_oracle(bri, dims):
     mass = 0.1
     u = synth.gauge_links(dims, 0.4, 8701)
